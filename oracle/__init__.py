@@ -1,0 +1,200 @@
+"""FP64 CPU oracle for the Brillouin-kernel overlap operator (arXiv:1701.00726).
+
+TEST INFRASTRUCTURE ONLY.  Only `tests/`, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  It shares no code with the HIP
+library (`paper_1701_00726_amd`); the two meet only through the seeded inputs
+of `synth`.
+
+Layouts here are the oracle's own: links U (4, V, 3, 3), off-axis links
+W (V, 81, 3, 3), spinors (nrhs, V, 4, 3), all complex128.  The heavy loops
+are plain C with OpenMP (`oracle.c`, built on first import with gcc).
+
+Functions and the passages they follow:
+  links            off-axis links as averages over all shortest paths (App. C.1)
+  dirac, dirac_adj Brillouin operator eq. (def_bril), c_SW = 0, and its adjoint
+  dense_matrix     the same operator as a dense matrix (small lattices)
+  cg               textbook CG on (D^dag D + sigma) x = b
+  rational_apply   c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, eq. (KLnn_parfrac)
+  sign_apply       gamma5 g_{2n+1}(H) b with H = gamma5 D(-rho), Sec. 3.3 / eq. (def_over)
+  ov_apply         rho (1 + gamma5 g_{2n+1}(H)) b, eq. (def_over)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+from . import kl
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_SO)
+            P = ctypes.c_void_p
+            I = ctypes.c_int
+            D = ctypes.c_double
+            lib.orc_links.argtypes = [P, I, P, P]
+            lib.orc_dirac.argtypes = [P, P, D, P, P, I]
+            lib.orc_dirac_adj.argtypes = [P, P, D, P, P, I]
+            lib.orc_dirac_dense.argtypes = [P, P, D, P]
+            lib.orc_gamma.argtypes = [I, P]
+            lib.orc_spin_matrix.argtypes = [I, D, P]
+            lib.orc_cg.argtypes = [P, P, D, D, P, P, D, I, P]
+            lib.orc_cg.restype = I
+            lib.orc_rational.argtypes = [P, P, D, I, D, P, P, P, P, D, I, P, P]
+            lib.orc_rational.restype = I
+            _lib = lib
+    return _lib
+
+
+def _geom(L):
+    return np.ascontiguousarray(np.asarray(L, dtype=np.int32))
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def volume(L):
+    return int(np.prod(L))
+
+
+# --------------------------------------------------------------------------- basis
+
+
+def gamma(mu: int) -> np.ndarray:
+    """gamma_mu (mu = 0..3 for x, y, z, t) or gamma5 (mu = 4) of the oracle's chiral basis."""
+    out = np.zeros(16, dtype=np.complex128)
+    _load().orc_gamma(int(mu), _ptr(out))
+    return out.reshape(4, 4)
+
+
+def spin_matrix(j: int, m0: float) -> np.ndarray:
+    """S_d for displacement index j = sum_mu (d_mu + 1) 3^mu."""
+    out = np.zeros(16, dtype=np.complex128)
+    _load().orc_spin_matrix(int(j), float(m0), _ptr(out))
+    return out.reshape(4, 4)
+
+
+def gamma5_apply(psi: np.ndarray) -> np.ndarray:
+    g5 = gamma(4)
+    return np.einsum("st,...tc->...sc", g5, psi)
+
+
+# ------------------------------------------------------------------- operator
+
+
+def links(L, U: np.ndarray, tbc: int = 0) -> np.ndarray:
+    """Off-axis links W (V, 81, 3, 3) from links U (4, V, 3, 3); brute-force paths."""
+    V = volume(L)
+    U = _c128(U)
+    assert U.shape == (4, V, 3, 3)
+    W = np.zeros((V, 81, 3, 3), dtype=np.complex128)
+    _load().orc_links(_ptr(_geom(L)), int(tbc), _ptr(U), _ptr(W))
+    return W
+
+
+def _apply(fn, L, W, m0, psi):
+    V = volume(L)
+    psi = _c128(psi)
+    squeeze = psi.ndim == 3
+    if squeeze:
+        psi = psi[None]
+    assert psi.shape[1:] == (V, 4, 3)
+    W = _c128(W)
+    out = np.zeros_like(psi)
+    fn(_ptr(_geom(L)), _ptr(W), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
+    return out[0] if squeeze else out
+
+
+def dirac(L, W, m0: float, psi: np.ndarray) -> np.ndarray:
+    """D_bri(m0) psi, direct 81-term sum."""
+    return _apply(_load().orc_dirac, L, W, m0, psi)
+
+
+def dirac_adj(L, W, m0: float, psi: np.ndarray) -> np.ndarray:
+    """D_bri(m0)^dag psi by the transposed sum (no gamma5 trick)."""
+    return _apply(_load().orc_dirac_adj, L, W, m0, psi)
+
+
+def dense_matrix(L, W, m0: float) -> np.ndarray:
+    """Dense D_bri(m0), index 12*site + 3*spin + colour."""
+    V = volume(L)
+    n = 12 * V
+    M = np.zeros((n, n), dtype=np.complex128)
+    _load().orc_dirac_dense(_ptr(_geom(L)), _ptr(_c128(W)), float(m0), _ptr(M))
+    return M
+
+
+# -------------------------------------------------------------------- solvers
+
+
+def cg(L, W, m0: float, sigma: float, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
+    """x = (D^dag D + sigma)^{-1} b by textbook CG; returns (x, iters, true_rel_resid)."""
+    b = _c128(b)
+    x = np.zeros_like(b)
+    rel = ctypes.c_double(0)
+    it = _load().orc_cg(
+        _ptr(_geom(L)), _ptr(_c128(W)), float(m0), float(sigma), _ptr(b), _ptr(x), float(tol), int(maxit),
+        ctypes.byref(rel),
+    )
+    return x, it, rel.value
+
+
+def rational_apply(L, W, m0: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
+    """y = r_n(D^dag D) b = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, shifts solved one by one.
+
+    Returns (y, iters per shift, true relative residual per shift)."""
+    c0, om, sg = kl.kl_diag_coeffs_f64(n)
+    b = _c128(b)
+    y = np.zeros_like(b)
+    om = np.ascontiguousarray(om, dtype=np.float64)
+    sg = np.ascontiguousarray(sg, dtype=np.float64)
+    iters = np.zeros(n, dtype=np.int32)
+    rel = np.zeros(n, dtype=np.float64)
+    _load().orc_rational(
+        _ptr(_geom(L)), _ptr(_c128(W)), float(m0), int(n), float(c0), _ptr(om), _ptr(sg), _ptr(b), _ptr(y),
+        float(tol), int(maxit), _ptr(iters), _ptr(rel),
+    )
+    return y, iters, rel
+
+
+def sign_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
+    """g_{2n+1}(H) b with H = gamma5 D(-rho):  g(H) = H r_n(H^2), H^2 = D^dag D, so
+    g(H) b = gamma5 D r_n(D^dag D) b."""
+    y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit)
+    return gamma5_apply(dirac(L, W, -rho, y)), iters, rel
+
+
+def ov_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
+    """D_ov b = rho (1 + gamma5 g_{2n+1}(H)) b = rho (b + D(-rho) r_n(D^dag D) b), eq. (def_over)."""
+    y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit)
+    return rho * (b + dirac(L, W, -rho, y)), iters, rel

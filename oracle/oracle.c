@@ -1,0 +1,468 @@
+/*
+ * FP64 CPU oracle for the Brillouin-kernel overlap operator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant generator
+ * with the HIP library.
+ *
+ * What it computes, each piece written out from its plain definition
+ * (Duerr & Koutsou, "On the suitability of the Brillouin action as a kernel
+ * to the overlap procedure", arXiv:1701.00726):
+ *
+ *   orc_links      off-axis links W_d(x) for all 81 displacements d in
+ *                  {-1,0,1}^4: the average over all k! shortest lattice
+ *                  paths from x to x+d (k = number of non-zero d_mu) of the
+ *                  ordered product of the links along the path; no
+ *                  projection back to SU(3) (App. C.1: the average, not the
+ *                  projection, is the favoured choice, and it keeps the
+ *                  operator gamma5-hermitian).
+ *   orc_dirac      the Brillouin operator, eq. (def_bril) with c_SW = 0, as
+ *                  the direct sum over the 81-point hypercube,
+ *                  (D psi)(x) = sum_d S_d (x) W_d(x) psi(x+d).
+ *                  The spin matrices S_d are the position-space weights of
+ *                  the isotropic derivative and the Brillouin Laplacian,
+ *                  read off from their momentum-space forms (App. A:
+ *                  p~_mu = sin p_mu prod_{nu!=mu} (cos p_nu + 2)/3 and
+ *                  lap^bri = (1/4) prod_mu (cos p_mu + 1) - 4).
+ *                  Each factor (cos p + 2)/3 is the one-axis stencil
+ *                  {1/6, 2/3, 1/6}; i sin p is {-1/2, 0, +1/2}; (cos p + 1)
+ *                  is {1/2, 1, 1/2}.  The bare mass sits on the 0-hop term
+ *                  (App. C.1 (ii)).
+ *   orc_dirac_adj  the adjoint D^dag by its definition D^dag(x,y) = D(y,x)^dag
+ *                  (transposed sum; gamma5-hermiticity is NOT used here, so a
+ *                  test can check it).
+ *   orc_dirac_dense  the same operator as a dense matrix (small lattices).
+ *   orc_cg         textbook conjugate gradient on (D^dag D + sigma) x = b.
+ *   orc_rational   y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, every
+ *                  shift solved separately (eq. (KLnn_parfrac) with
+ *                  X^dag X = D^dag D).
+ *
+ * Gamma matrices: the paper only says "chiral representation" (App. C.1).
+ * Used here: gamma_k = [[0, -i s_k], [i s_k, 0]] (s_k the Pauli matrices),
+ * gamma_4 = [[0, 1], [1, 0]], gamma5 = gamma_1 gamma_2 gamma_3 gamma_4.
+ *
+ * Layouts (oracle-private, site-major):
+ *   U   [4][V][3][3]      W   [V][81][3][3]      psi [nrhs][V][4][3]
+ *   site s = x + Lx*(y + Ly*(z + Lz*t)); displacement index
+ *   j = sum_mu (d_mu + 1) 3^mu, so j = 40 is d = 0 and j, 80-j are opposite.
+ * tbc = 1 makes the fermion field antiperiodic in t: a path step that crosses
+ * the t boundary picks up a factor -1.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------ geometry */
+
+static long vol(const int L[4]) { return (long)L[0] * L[1] * L[2] * L[3]; }
+
+static void coords(const int L[4], long s, int c[4]) {
+    for (int mu = 0; mu < 4; ++mu) {
+        c[mu] = (int)(s % L[mu]);
+        s /= L[mu];
+    }
+}
+
+static long site_of(const int L[4], const int c[4]) {
+    long s = 0;
+    for (int mu = 3; mu >= 0; --mu) {
+        int v = ((c[mu] % L[mu]) + L[mu]) % L[mu];
+        s = s * L[mu] + v;
+    }
+    return s;
+}
+
+static void disp_of(int j, int d[4]) {
+    for (int mu = 0; mu < 4; ++mu) {
+        d[mu] = j % 3 - 1;
+        j /= 3;
+    }
+}
+
+/* ------------------------------------------------------------- gamma basis */
+
+static cplx GAM[5][4][4];
+static int gam_ready = 0;
+
+static void init_gammas(void) {
+    if (gam_ready) return;
+    const cplx iu = _Complex_I;
+    cplx pauli[3][2][2] = {
+        {{0, 1}, {1, 0}},
+        {{0, -iu}, {iu, 0}},
+        {{1, 0}, {0, -1}},
+    };
+    memset(GAM, 0, sizeof(GAM));
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                GAM[k][a][2 + b] = -iu * pauli[k][a][b];
+                GAM[k][2 + a][b] = iu * pauli[k][a][b];
+            }
+    for (int a = 0; a < 2; ++a) {
+        GAM[3][a][2 + a] = 1;
+        GAM[3][2 + a][a] = 1;
+    }
+    /* gamma5 = gamma_1 gamma_2 gamma_3 gamma_4 */
+    cplx t1[4][4], t2[4][4];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            cplx s = 0;
+            for (int c = 0; c < 4; ++c) s += GAM[0][a][c] * GAM[1][c][b];
+            t1[a][b] = s;
+        }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            cplx s = 0;
+            for (int c = 0; c < 4; ++c) s += t1[a][c] * GAM[2][c][b];
+            t2[a][b] = s;
+        }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            cplx s = 0;
+            for (int c = 0; c < 4; ++c) s += t2[a][c] * GAM[3][c][b];
+            GAM[4][a][b] = s;
+        }
+    gam_ready = 1;
+}
+
+void orc_gamma(int mu, cplx *out16) {
+    init_gammas();
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) out16[4 * a + b] = GAM[mu][a][b];
+}
+
+/* ------------------------------------------------------- stencil weights */
+
+/* one-axis factors read off from the momentum forms */
+static double w_iso(int dnu) { return dnu == 0 ? 2.0 / 3.0 : 1.0 / 6.0; } /* (cos p + 2)/3 */
+static double w_lap(int dnu) { return dnu == 0 ? 1.0 : 0.5; }             /* (cos p + 1)   */
+
+/* S_d for displacement index j: 4x4 spin matrix multiplying W_d(x) psi(x+d) */
+static void spin_matrix(int j, double m0, cplx S[4][4]) {
+    init_gammas();
+    int d[4];
+    disp_of(j, d);
+    int zero = (d[0] == 0 && d[1] == 0 && d[2] == 0 && d[3] == 0);
+    /* -(1/2) lap^bri : (1/4) prod f - 4 delta  ->  -(1/8) prod f + 2 delta */
+    double prodf = 1.0;
+    for (int mu = 0; mu < 4; ++mu) prodf *= w_lap(d[mu]);
+    double scal = -prodf / 8.0 + (zero ? 2.0 + m0 : 0.0);
+    memset(S, 0, sizeof(cplx) * 16);
+    for (int a = 0; a < 4; ++a) S[a][a] = scal;
+    /* sum_mu gamma_mu nabla^iso_mu : weight (d_mu/2) prod_{nu != mu} w_iso(d_nu) */
+    for (int mu = 0; mu < 4; ++mu) {
+        if (d[mu] == 0) continue;
+        double c = 0.5 * d[mu];
+        for (int nu = 0; nu < 4; ++nu)
+            if (nu != mu) c *= w_iso(d[nu]);
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) S[a][b] += c * GAM[mu][a][b];
+    }
+}
+
+void orc_spin_matrix(int j, double m0, cplx *out16) {
+    cplx S[4][4];
+    spin_matrix(j, m0, S);
+    memcpy(out16, S, sizeof(S));
+}
+
+/* ------------------------------------------------------- off-axis links */
+
+static void mat_mul(const cplx *A, const cplx *B, cplx *C) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx s = 0;
+            for (int c = 0; c < 3; ++c) s += A[3 * a + c] * B[3 * c + b];
+            C[3 * a + b] = s;
+        }
+}
+
+static void mat_mul_dag(const cplx *A, const cplx *B, cplx *C) { /* A B^dag */
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx s = 0;
+            for (int c = 0; c < 3; ++c) s += A[3 * a + c] * conj(B[3 * b + c]);
+            C[3 * a + b] = s;
+        }
+}
+
+/* all permutations of {0..k-1} for k = 0..4, generated once by recursive swapping */
+static int PERM[5][24][4];
+static int NPERM[5];
+static int perm_ready = 0;
+
+static void gen_perm(int k, int *a, int pos) {
+    if (pos == k) {
+        memcpy(PERM[k][NPERM[k]++], a, sizeof(int) * 4);
+        return;
+    }
+    for (int i = pos; i < k; ++i) {
+        int t = a[pos]; a[pos] = a[i]; a[i] = t;
+        gen_perm(k, a, pos + 1);
+        t = a[pos]; a[pos] = a[i]; a[i] = t;
+    }
+}
+
+static void init_perms(void) {
+    if (perm_ready) return;
+    for (int k = 0; k <= 4; ++k) {
+        int a[4] = {0, 1, 2, 3};
+        NPERM[k] = 0;
+        gen_perm(k, a, 0);
+    }
+    perm_ready = 1;
+}
+
+void orc_links(const int *L, int tbc, const cplx *U, cplx *W) {
+    const long V = vol(L);
+    init_perms();
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        int cx[4];
+        coords(L, x, cx);
+        for (int j = 0; j < 81; ++j) {
+            int d[4];
+            disp_of(j, d);
+            int axes[4], k = 0;
+            for (int mu = 0; mu < 4; ++mu)
+                if (d[mu] != 0) axes[k++] = mu;
+            cplx *out = W + ((size_t)x * 81 + j) * 9;
+            cplx acc[9] = {0};
+            /* enumerate the k! orderings of the non-zero axes */
+            const int np_local = NPERM[k];
+            const int (*pl)[4] = PERM[k];
+            for (int p = 0; p < np_local; ++p) {
+                cplx M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+                int cy[4] = {cx[0], cx[1], cx[2], cx[3]};
+                double sign = 1.0;
+                for (int st = 0; st < k; ++st) {
+                    int mu = axes[pl[p][st]];
+                    cplx T[9];
+                    if (d[mu] > 0) {
+                        /* step +mu: multiply by U_mu(y), then y -> y + mu */
+                        long sy = site_of(L, cy);
+                        mat_mul(M, U + ((size_t)mu * V + sy) * 9, T);
+                        if (tbc && mu == 3 && cy[3] == L[3] - 1) sign = -sign;
+                        cy[mu] += 1;
+                    } else {
+                        /* step -mu: y -> y - mu, multiply by U_mu(y)^dag */
+                        if (tbc && mu == 3 && cy[3] == 0) sign = -sign;
+                        cy[mu] -= 1;
+                        long sy = site_of(L, cy);
+                        mat_mul_dag(M, U + ((size_t)mu * V + sy) * 9, T);
+                    }
+                    memcpy(M, T, sizeof(T));
+                }
+                for (int e = 0; e < 9; ++e) acc[e] += sign * M[e];
+            }
+            for (int e = 0; e < 9; ++e) out[e] = acc[e] / (double)np_local;
+        }
+    }
+}
+
+/* ------------------------------------------------------------ the operator */
+
+static void neighbour_table(const int L[4], long x, long nb[81]) {
+    int cx[4];
+    coords(L, x, cx);
+    for (int j = 0; j < 81; ++j) {
+        int d[4], cy[4];
+        disp_of(j, d);
+        for (int mu = 0; mu < 4; ++mu) cy[mu] = cx[mu] + d[mu];
+        nb[j] = site_of(L, cy);
+    }
+}
+
+void orc_dirac(const int *L, const cplx *W, double m0, const cplx *in, cplx *out, int nrhs) {
+    const long V = vol(L);
+    cplx S[81][4][4];
+    for (int j = 0; j < 81; ++j) spin_matrix(j, m0, S[j]);
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *src = in + (size_t)r * V * 12;
+        cplx *dst = out + (size_t)r * V * 12;
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < V; ++x) {
+            long nb[81];
+            neighbour_table(L, x, nb);
+            cplx acc[4][3] = {{0}};
+            for (int j = 0; j < 81; ++j) {
+                const cplx *Wd = W + ((size_t)x * 81 + j) * 9;
+                const cplx *p = src + (size_t)nb[j] * 12;
+                cplx tp[4][3]; /* W_d(x) psi(x+d), colour rotated, per spin */
+                for (int s = 0; s < 4; ++s)
+                    for (int a = 0; a < 3; ++a) {
+                        cplx v = 0;
+                        for (int b = 0; b < 3; ++b) v += Wd[3 * a + b] * p[3 * s + b];
+                        tp[s][a] = v;
+                    }
+                for (int s = 0; s < 4; ++s)
+                    for (int a = 0; a < 3; ++a) {
+                        cplx v = 0;
+                        for (int t = 0; t < 4; ++t) v += S[j][s][t] * tp[t][a];
+                        acc[s][a] += v;
+                    }
+            }
+            for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a) dst[(size_t)x * 12 + 3 * s + a] = acc[s][a];
+        }
+    }
+}
+
+/* D^dag(x, x+d) = D(x+d, x)^dag = S_{-d}^dag (x) W_{-d}(x+d)^dag */
+void orc_dirac_adj(const int *L, const cplx *W, double m0, const cplx *in, cplx *out, int nrhs) {
+    const long V = vol(L);
+    cplx S[81][4][4];
+    for (int j = 0; j < 81; ++j) spin_matrix(j, m0, S[j]);
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *src = in + (size_t)r * V * 12;
+        cplx *dst = out + (size_t)r * V * 12;
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < V; ++x) {
+            long nb[81];
+            neighbour_table(L, x, nb);
+            cplx acc[4][3] = {{0}};
+            for (int j = 0; j < 81; ++j) {
+                int jm = 80 - j; /* the displacement -d */
+                long y = nb[j];  /* y = x + d */
+                const cplx *Wy = W + ((size_t)y * 81 + jm) * 9; /* W_{-d}(x+d) */
+                const cplx *p = src + (size_t)y * 12;
+                cplx tp[4][3];
+                for (int s = 0; s < 4; ++s)
+                    for (int a = 0; a < 3; ++a) {
+                        cplx v = 0;
+                        for (int b = 0; b < 3; ++b) v += conj(Wy[3 * b + a]) * p[3 * s + b];
+                        tp[s][a] = v;
+                    }
+                for (int s = 0; s < 4; ++s)
+                    for (int a = 0; a < 3; ++a) {
+                        cplx v = 0;
+                        for (int t = 0; t < 4; ++t) v += conj(S[jm][t][s]) * tp[t][a];
+                        acc[s][a] += v;
+                    }
+            }
+            for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a) dst[(size_t)x * 12 + 3 * s + a] = acc[s][a];
+        }
+    }
+}
+
+/* dense matrix, row/col index = 12*site + 3*spin + colour */
+void orc_dirac_dense(const int *L, const cplx *W, double m0, cplx *M) {
+    const long V = vol(L);
+    const long n = 12 * V;
+    cplx S[81][4][4];
+    for (int j = 0; j < 81; ++j) spin_matrix(j, m0, S[j]);
+    memset(M, 0, sizeof(cplx) * (size_t)n * n);
+    for (long x = 0; x < V; ++x) {
+        long nb[81];
+        neighbour_table(L, x, nb);
+        for (int j = 0; j < 81; ++j) {
+            const cplx *Wd = W + ((size_t)x * 81 + j) * 9;
+            for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a)
+                    for (int t = 0; t < 4; ++t)
+                        for (int b = 0; b < 3; ++b)
+                            M[(size_t)(12 * x + 3 * s + a) * n + 12 * nb[j] + 3 * t + b] +=
+                                S[j][s][t] * Wd[3 * a + b];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ solvers */
+
+static cplx dotc(const cplx *a, const cplx *b, long n) {
+    double re = 0, im = 0;
+#pragma omp parallel for reduction(+ : re, im) schedule(static)
+    for (long i = 0; i < n; ++i) {
+        cplx v = conj(a[i]) * b[i];
+        re += creal(v);
+        im += cimag(v);
+    }
+    return re + _Complex_I * im;
+}
+
+static double norm2(const cplx *a, long n) { return creal(dotc(a, a, n)); }
+
+/* y = (D^dag D + sigma) x */
+static void normal_op(const int *L, const cplx *W, double m0, double sigma, const cplx *x, cplx *y, cplx *tmp) {
+    const long n = 12 * vol(L);
+    orc_dirac(L, W, m0, x, tmp, 1);
+    orc_dirac_adj(L, W, m0, tmp, y, 1);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) y[i] += sigma * x[i];
+}
+
+/* Textbook CG for (D^dag D + sigma) x = b, x0 = 0.  Iterates until the
+ * recursive residual is below tol*|b|, then recomputes the true residual and
+ * restarts from the current x if that is still above tol*|b|.
+ * Returns the iteration count; *true_rel receives |b - (A+sigma)x|/|b|. */
+int orc_cg(const int *L, const cplx *W, double m0, double sigma, const cplx *b, cplx *x, double tol,
+           int maxit, double *true_rel) {
+    const long n = 12 * vol(L);
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *Ap = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
+    const double bn = sqrt(norm2(b, n));
+    memset(x, 0, sizeof(cplx) * n);
+    int it = 0;
+    double rel = 1.0;
+    if (bn == 0) {
+        *true_rel = 0;
+        free(r); free(p); free(Ap); free(tmp);
+        return 0;
+    }
+    while (it < maxit) {
+        /* (re)start: r = b - A x */
+        normal_op(L, W, m0, sigma, x, Ap, tmp);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - Ap[i];
+        double rr = norm2(r, n);
+        rel = sqrt(rr) / bn;
+        if (rel <= tol) break;
+        memcpy(p, r, sizeof(cplx) * n);
+        while (it < maxit) {
+            normal_op(L, W, m0, sigma, p, Ap, tmp);
+            double pAp = creal(dotc(p, Ap, n));
+            double alpha = rr / pAp;
+            for (long i = 0; i < n; ++i) {
+                x[i] += alpha * p[i];
+                r[i] -= alpha * Ap[i];
+            }
+            double rr_new = norm2(r, n);
+            ++it;
+            if (sqrt(rr_new) <= tol * bn) break;
+            double beta = rr_new / rr;
+            rr = rr_new;
+            for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        }
+    }
+    normal_op(L, W, m0, sigma, x, Ap, tmp);
+    double rr = 0;
+    for (long i = 0; i < n; ++i) {
+        cplx e = b[i] - Ap[i];
+        rr += creal(e) * creal(e) + cimag(e) * cimag(e);
+    }
+    *true_rel = sqrt(rr) / bn;
+    free(r); free(p); free(Ap); free(tmp);
+    return it;
+}
+
+/* y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, each shift separately.
+ * iters[i], rel[i] receive the per-shift CG iteration count and true residual. */
+int orc_rational(const int *L, const cplx *W, double m0, int nshift, double c0, const double *omega,
+                 const double *sigma, const cplx *b, cplx *y, double tol, int maxit, int *iters, double *rel) {
+    const long n = 12 * vol(L);
+    cplx *xs = malloc(sizeof(cplx) * n);
+    for (long i = 0; i < n; ++i) y[i] = c0 * b[i];
+    int worst = 0;
+    for (int s = 0; s < nshift; ++s) {
+        iters[s] = orc_cg(L, W, m0, sigma[s], b, xs, tol, maxit, &rel[s]);
+        if (rel[s] > tol) worst = 1;
+        for (long i = 0; i < n; ++i) y[i] += omega[s] * xs[i];
+    }
+    free(xs);
+    return worst;
+}
