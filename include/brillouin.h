@@ -1,0 +1,151 @@
+/*
+ * brillouin.h -- C ABI of the MI355X library for the Brillouin-kernel overlap
+ * operator (S. Duerr, G. Koutsou, arXiv:1701.00726).
+ *
+ * Operator conventions (lattice spacing a = 1):
+ *   D_bri(m0) = sum_mu gamma_mu nabla^iso_mu - (1/2) lap^bri + m0   eq. (def_bril), c_SW = 0
+ *   X         = D_bri(-rho),  H = gamma5 X,  A = X^dag X = H^2
+ *   D_ov      = rho (1 + gamma5 sign(H))                               eq. (def_over)
+ *   sign(H)  ~= g_{2n+1}(H) = H r_n(H^2),
+ *   r_n(t)    = c0 + sum_{i<n} omega_i / (t + sigma_i)                 eq. (KLnn_parfrac)
+ *   so D_ov psi ~= rho (psi + X r_n(A) psi), sign(H) psi ~= gamma5 X r_n(A) psi.
+ *
+ * Lattice and layouts.  Extents L = {Lx, Ly, Lz, Lt}, direction mu = 0..3 is
+ * x, y, z, t; site s = x + Lx*(y + Ly*(z + Lz*t)), V = Lx*Ly*Lz*Lt.  All fields
+ * are structure-of-arrays with the site index fastest and complex numbers
+ * interleaved (re, im):
+ *   U    [4][3][3][V]        thin (or smeared) gauge links, complex double
+ *   W    [40][3][3][V]       off-axis links, complex double / float / bfloat16
+ *   psi  [nrhs][4][3][V]     spinors: spin, colour, site
+ * Gamma matrices (chiral basis): gamma_k = [[0, -i s_k], [i s_k, 0]] with the
+ * Pauli matrices s_k, gamma_4 = [[0, 1], [1, 0]], gamma5 = diag(1, 1, -1, -1).
+ * Displacements d in {-1,0,1}^4 carry the index j = sum_mu (d_mu + 1) 3^mu,
+ * so that j and 80 - j are opposite and j = 40 is d = 0 (App. C.1).  Only the
+ * 40 links with j < 40 are stored; W_{80-j}(x) = W_j(x + d_{80-j})^dag.
+ *
+ * Memory: every pointer argument named U, W*, in, out, work is a DEVICE pointer
+ * owned by the caller; the library never frees caller memory.  Host pointers
+ * are the geometry, parameter and statistics structs and work_bytes.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream); every call is
+ * asynchronous on it, except ov_sign_apply / ov_apply, which synchronise the
+ * stream before returning (they read convergence flags on the host).
+ * Errors: no call aborts, prints or throws.  A call returns BRI_OK or a
+ * negative status; on BRI_EINVAL nothing was launched.
+ */
+#ifndef BRILLOUIN_H
+#define BRILLOUIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* lattice geometry; tbc = 1 makes the fermion field antiperiodic in t */
+typedef struct {
+    int32_t L[4];
+    int32_t tbc;
+} bri_geom;
+
+/* storage / arithmetic precision of a field */
+typedef enum {
+    BRI_F64 = 0,      /* complex double spinors, complex double links          */
+    BRI_F32 = 1,      /* complex float spinors, complex float links            */
+    BRI_F32_BF16W = 2 /* complex float spinors, links as (re, im) bfloat16     */
+} bri_prec;
+
+typedef enum {
+    BRI_OK = 0,
+    BRI_EINVAL = -1,  /* bad geometry, pointer, precision, size or workspace  */
+    BRI_ENOCONV = -2, /* solver hit max_iter; out holds the last iterate      */
+    BRI_ENAN = -3,    /* non-finite value met in a reduction                  */
+    BRI_EHIP = -4     /* a HIP runtime call failed                            */
+} bri_status;
+
+/* Largest supported Kenney-Laub order n (number of shifts). */
+#define BRI_MAX_SHIFTS 32
+
+/*
+ * bri_build_links -- off-axis links of the Brillouin stencil (App. C.1).
+ * W_d(x) is the average over the k! shortest paths from x to x + d
+ * (k = number of non-zero d_mu) of the ordered product of links along the
+ * path; a step +mu at y contributes U_mu(y), a step -mu contributes
+ * U_mu(y - mu)^dag.  No projection back to SU(3).  Computed in FP64 and rounded
+ * to `wprec` on store.
+ *   U  : [4][3][3][V] complex double (device, read)
+ *   W  : [40][3][3][V] in precision wprec (device, written)
+ * Returns BRI_EINVAL for L_mu < 1 or odd/zero sizes it cannot address,
+ * BRI_EHIP on a HIP failure (a temporary FP64 buffer of 5760*V bytes is
+ * allocated when wprec != BRI_F64).
+ */
+int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, void *stream);
+
+/*
+ * bri_apply -- out = D_bri(m0) in, the 81-point sum (App. C.1)
+ *   (D psi)(x) = (15/8 + m0) psi(x) + sum_{d != 0} S_d W_d(x) psi(x + d),
+ *   S_d = -2^{-(k+3)} + c_k sum_{mu in supp d} d_mu gamma_mu,
+ *   c_k = 4/27, 1/27, 1/108, 1/432 for k = 1..4 hops
+ * (position-space weights of the isotropic derivative and the Brillouin
+ * Laplacian, App. A momentum forms).
+ *   W   : [40][3][3][V] in precision prec (F64: double; F32: float;
+ *         F32_BF16W: bfloat16 links with float spinors)
+ *   in, out : [nrhs][4][3][V], complex double for BRI_F64, complex float
+ *         otherwise; in and out must not overlap.
+ */
+int bri_apply(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
+              void *stream);
+
+/* bri_apply_dag -- out = D_bri(m0)^dag in = gamma5 D_bri(m0) gamma5 in
+ * (gamma5-hermiticity, Sec. 4).  Arguments as bri_apply. */
+int bri_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
+                  void *stream);
+
+/* Parameters of the overlap applies. */
+typedef struct {
+    int kl_n;       /* Kenney-Laub order n: f_{n,n} = g_{2n+1}, 1..BRI_MAX_SHIFTS */
+    double rho;     /* 0 < rho < 2; kernel mass m0 = -rho                        */
+    double tol;     /* per-shift stop: |r_sigma| <= tol |psi|                    */
+    int max_iter;   /* multi-shift CG iteration cap                              */
+    int inner;      /* bri_prec of the inner solve (BRI_F64 only in this build)  */
+    int max_refine; /* reserved for defect correction; 0                         */
+} ov_params;
+
+/* Statistics of one overlap apply (the last right-hand side for nrhs > 1). */
+typedef struct {
+    int iters;                          /* multi-shift CG iterations            */
+    int refine;                         /* defect-correction passes             */
+    int shift_iters[BRI_MAX_SHIFTS];    /* iteration at which each shift stopped */
+    double rel_resid[BRI_MAX_SHIFTS];   /* |zeta_sigma r| / |psi| at that point  */
+    double seconds;                     /* host wall time of the call            */
+} ov_stats;
+
+/*
+ * ov_sign_apply -- out ~= sign(H) in = gamma5 X r_n(X^dag X) in, H = gamma5 D_bri(-rho)
+ * ov_apply      -- out ~= D_ov in   = rho (in + X r_n(X^dag X) in)          eq. (def_over)
+ * r_n(A) in is evaluated by one multi-shift CG on A + sigma_min for all n
+ * shifts at once (Sec. 3.3), with the coefficients of eq. (KLnn_parfrac).
+ *   W64 : [40][3][3][V] complex double off-axis links
+ *   Wlo : low-precision links for a mixed inner solve; NULL when inner = BRI_F64
+ *   in, out : [nrhs][4][3][V] complex double (device); must not overlap
+ *   work, work_bytes : device workspace; with work == NULL the call only writes
+ *         the required size into *work_bytes and returns BRI_OK.
+ *   stats : may be NULL.
+ * Returns BRI_ENOCONV when max_iter is reached before every shift met tol
+ * (out then holds the result of the last iterate), BRI_ENAN on a non-finite
+ * residual.
+ */
+int ov_sign_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params, const void *in,
+                  void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream);
+int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params, const void *in,
+             void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream);
+
+/* Kenney-Laub coefficients c0, omega[n], sigma[n] of f_{n,n} (eq. (KLnn_parfrac)),
+ * computed in double precision on the host; sigma ascending. */
+int bri_kl_coeffs(int n, double *c0, double *omega, double *sigma);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BRILLOUIN_H */

@@ -67,6 +67,7 @@ def _load():
             lib.orc_cg.restype = I
             lib.orc_rational.argtypes = [P, P, D, I, D, P, P, P, P, D, I, P, P]
             lib.orc_rational.restype = I
+            lib.orc_num_threads.restype = I
             _lib = lib
     return _lib
 
@@ -81,6 +82,11 @@ def _c128(a):
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().orc_num_threads())
 
 
 def volume(L):

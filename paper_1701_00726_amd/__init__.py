@@ -1,0 +1,286 @@
+"""MI355X library for the Brillouin-kernel overlap operator (arXiv:1701.00726).
+
+Thin ctypes binding of `libbrillouin.so` (the C ABI declared in
+include/brillouin.h).  Every step of the computation runs in the library's HIP
+kernels; this module only checks shapes, passes device pointers and the
+current HIP stream, and converts between the natural (site-major) layout of
+`synth` and the library's structure-of-arrays layout.
+
+torch tensors provide device memory:
+  U    complex128, shape (4, 3, 3, V)
+  W    (40, 3, 3, V): complex128 (BRI_F64), complex64 (BRI_F32),
+       int32 holding (re, im) bfloat16 pairs (BRI_F32_BF16W)
+  psi  (nrhs, 4, 3, V): complex128 (BRI_F64) or complex64 (BRI_F32*)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbrillouin.so")
+
+F64, F32, F32_BF16W = 0, 1, 2
+OK, EINVAL, ENOCONV, ENAN, EHIP = 0, -1, -2, -3, -4
+MAX_SHIFTS = 32
+STATUS_NAMES = {OK: "BRI_OK", EINVAL: "BRI_EINVAL", ENOCONV: "BRI_ENOCONV", ENAN: "BRI_ENAN", EHIP: "BRI_EHIP"}
+
+
+class BriError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__(f"{fn} returned {STATUS_NAMES.get(status, status)}")
+        self.status = status
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("tbc", ctypes.c_int32)]
+
+
+class _OvParams(ctypes.Structure):
+    _fields_ = [
+        ("kl_n", ctypes.c_int),
+        ("rho", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("inner", ctypes.c_int),
+        ("max_refine", ctypes.c_int),
+    ]
+
+
+class _OvStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("refine", ctypes.c_int),
+        ("shift_iters", ctypes.c_int * MAX_SHIFTS),
+        ("rel_resid", ctypes.c_double * MAX_SHIFTS),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+@dataclass
+class OvStats:
+    iters: int
+    refine: int
+    shift_iters: list = field(default_factory=list)
+    rel_resid: list = field(default_factory=list)
+    seconds: float = 0.0
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load():
+    """Load libbrillouin.so; raises if it was not built (no fallback path exists)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(
+                    f"{LIB_PATH} is missing: build it with `python -m paper_1701_00726_amd.build` "
+                    "(the library has no CPU fallback)"
+                )
+            lib = ctypes.CDLL(LIB_PATH)
+            P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+            G = ctypes.POINTER(_Geom)
+            lib.bri_build_links.argtypes = [G, P, P, I, P]
+            lib.bri_apply.argtypes = [G, P, I, D, P, P, I, P]
+            lib.bri_apply_dag.argtypes = [G, P, I, D, P, P, I, P]
+            ovargs = [G, P, P, ctypes.POINTER(_OvParams), P, P, I, P, ctypes.POINTER(ctypes.c_size_t),
+                      ctypes.POINTER(_OvStats), P]
+            lib.ov_sign_apply.argtypes = ovargs
+            lib.ov_apply.argtypes = ovargs
+            lib.bri_kl_coeffs.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
+            for fn in ("bri_build_links", "bri_apply", "bri_apply_dag", "ov_sign_apply", "ov_apply", "bri_kl_coeffs"):
+                getattr(lib, fn).restype = I
+            _lib = lib
+    return _lib
+
+
+EXPORTS = ("bri_build_links", "bri_apply", "bri_apply_dag", "ov_sign_apply", "ov_apply", "bri_kl_coeffs")
+
+
+# ------------------------------------------------------------------ helpers
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _geom(L, tbc=0):
+    g = _Geom()
+    for i in range(4):
+        g.L[i] = int(L[i])
+    g.tbc = int(tbc)
+    return g
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(fn, status, allow=()):
+    if status != OK and status not in allow:
+        raise BriError(fn, status)
+    return status
+
+
+def spinor_dtype(prec):
+    torch = _torch()
+    return torch.complex128 if prec == F64 else torch.complex64
+
+
+def link_dtype(prec):
+    torch = _torch()
+    return {F64: torch.complex128, F32: torch.complex64, F32_BF16W: torch.int32}[prec]
+
+
+# ------------------------------------------------------------ layout helpers
+
+
+def links_to_device(U_np, device="cuda"):
+    """(4, V, 3, 3) complex128 numpy -> (4, 3, 3, V) device tensor."""
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(U_np, (0, 2, 3, 1)))).to(device)
+
+
+def spinor_to_device(psi_np, prec=F64, device="cuda"):
+    """(nrhs, V, 4, 3) numpy -> (nrhs, 4, 3, V) device tensor."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.transpose(psi_np, (0, 2, 3, 1)))
+    return torch.from_numpy(a).to(device=device, dtype=spinor_dtype(prec))
+
+
+def spinor_to_host(psi_t):
+    """(nrhs, 4, 3, V) tensor -> (nrhs, V, 4, 3) complex128 numpy."""
+    a = psi_t.detach().to("cpu").numpy().astype(np.complex128)
+    return np.ascontiguousarray(np.transpose(a, (0, 3, 1, 2)))
+
+
+def links_W_to_host(W_t, prec=F64):
+    """(40, 3, 3, V) tensor -> (V, 40, 3, 3) complex128 numpy (bfloat16 pairs unpacked)."""
+    if prec == F32_BF16W:
+        u = W_t.detach().to("cpu").numpy().view(np.uint32)
+        re = ((u & 0xFFFF).astype(np.uint32) << 16).view(np.float32)
+        im = (u & 0xFFFF0000).astype(np.uint32).view(np.float32)
+        a = re.astype(np.complex128) + 1j * im.astype(np.float64)
+    else:
+        a = W_t.detach().to("cpu").numpy().astype(np.complex128)
+    return np.ascontiguousarray(np.transpose(a, (3, 0, 1, 2)))
+
+
+# ------------------------------------------------------------------ the ABI
+
+
+def build_links(L, U, prec=F64, tbc=0, stream=None, out=None):
+    """Off-axis links W [40][3][3][V] in precision `prec` from device links U [4][3][3][V]."""
+    torch = _torch()
+    V = int(np.prod(L))
+    if U.dtype != torch.complex128 or tuple(U.shape) != (4, 3, 3, V):
+        raise ValueError("U must be complex128 of shape (4, 3, 3, V)")
+    if out is None:
+        out = torch.empty((40, 3, 3, V), dtype=link_dtype(prec), device=U.device)
+    g = _geom(L, tbc)
+    _check("bri_build_links", load().bri_build_links(ctypes.byref(g), _dptr(U), _dptr(out), int(prec), _stream(stream)))
+    return out
+
+
+def _apply(fn, L, W, prec, m0, psi, out=None, stream=None):
+    torch = _torch()
+    V = int(np.prod(L))
+    if psi.dim() != 4 or tuple(psi.shape[1:]) != (4, 3, V) or psi.dtype != spinor_dtype(prec):
+        raise ValueError("psi must be (nrhs, 4, 3, V) of the spinor dtype of prec")
+    if W.dtype != link_dtype(prec) or tuple(W.shape) != (40, 3, 3, V):
+        raise ValueError("W must be (40, 3, 3, V) of the link dtype of prec")
+    if out is None:
+        out = torch.empty_like(psi)
+    g = _geom(L)
+    st = getattr(load(), fn)(ctypes.byref(g), _dptr(W), int(prec), float(m0), _dptr(psi), _dptr(out),
+                             int(psi.shape[0]), _stream(stream))
+    _check(fn, st)
+    return out
+
+
+def apply(L, W, prec, m0, psi, out=None, stream=None):
+    """out = D_bri(m0) psi."""
+    return _apply("bri_apply", L, W, prec, m0, psi, out, stream)
+
+
+def apply_dag(L, W, prec, m0, psi, out=None, stream=None):
+    """out = D_bri(m0)^dag psi."""
+    return _apply("bri_apply_dag", L, W, prec, m0, psi, out, stream)
+
+
+class OverlapOp:
+    """Holds the workspace of ov_apply / ov_sign_apply for one lattice and parameter set."""
+
+    def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0):
+        self.L = tuple(int(v) for v in L)
+        self.g = _geom(self.L, tbc)
+        self.W64 = W64
+        self.Wlo = Wlo
+        self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), 0)
+        nbytes = ctypes.c_size_t(0)
+        _check(
+            "ov_apply",
+            load().ov_apply(ctypes.byref(self.g), None, None, ctypes.byref(self.params), None, None, 1, None,
+                            ctypes.byref(nbytes), None, None),
+        )
+        torch = _torch()
+        self.work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=W64.device)
+        self.work_bytes = nbytes.value
+
+    def _run(self, fn, psi, out, stream, allow_noconv):
+        torch = _torch()
+        V = int(np.prod(self.L))
+        if psi.dtype != torch.complex128 or psi.dim() != 4 or tuple(psi.shape[1:]) != (4, 3, V):
+            raise ValueError("psi must be complex128 (nrhs, 4, 3, V)")
+        if out is None:
+            out = torch.empty_like(psi)
+        stats = _OvStats()
+        wb = ctypes.c_size_t(self.work_bytes)
+        st = getattr(load(), fn)(
+            ctypes.byref(self.g), _dptr(self.W64), None if self.Wlo is None else _dptr(self.Wlo),
+            ctypes.byref(self.params), _dptr(psi), _dptr(out), int(psi.shape[0]), _dptr(self.work), ctypes.byref(wb),
+            ctypes.byref(stats), _stream(stream),
+        )
+        _check(fn, st, allow=(ENOCONV,) if allow_noconv else ())
+        n = self.params.kl_n
+        s = OvStats(stats.iters, stats.refine, list(stats.shift_iters[:n]), list(stats.rel_resid[:n]), stats.seconds)
+        s.status = st
+        return out, s
+
+    def apply(self, psi, out=None, stream=None, allow_noconv=False):
+        """out = D_ov psi = rho (psi + X r_n(X^dag X) psi)."""
+        return self._run("ov_apply", psi, out, stream, allow_noconv)
+
+    def sign(self, psi, out=None, stream=None, allow_noconv=False):
+        """out = sign(H) psi ~= gamma5 X r_n(X^dag X) psi."""
+        return self._run("ov_sign_apply", psi, out, stream, allow_noconv)
+
+
+def kl_coeffs(n):
+    """(c0, omega[n], sigma[n]) as computed by the library's host code."""
+    c0 = ctypes.c_double()
+    om = (ctypes.c_double * n)()
+    sg = (ctypes.c_double * n)()
+    _check("bri_kl_coeffs", load().bri_kl_coeffs(int(n), ctypes.byref(c0), om, sg))
+    return c0.value, list(om), list(sg)

@@ -1,0 +1,130 @@
+// Device-side building blocks of the Brillouin / overlap library (gfx950).
+//
+// Field layouts (structure of arrays, site index fastest, complex interleaved):
+//   U   [4][3][3][V]     W   [40][3][3][V]     psi [nrhs][4][3][V]
+// Displacement index j = sum_mu (d_mu + 1) 3^mu; the 40 stored off-axis links
+// are the j < 40 ones, whose last non-zero d_mu is -1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/brillouin.h"
+
+namespace bri {
+
+// ---------------------------------------------------------------- geometry
+
+struct Geom {
+    int L[4];
+    int V;
+    int tbc;
+};
+
+__host__ __device__ inline int disp_comp(int j, int mu) {
+    int p = 1;
+    for (int i = 0; i < mu; ++i) p *= 3;
+    return (j / p) % 3 - 1;
+}
+
+// ---------------------------------------------------------- stencil weights
+//
+// S_d = a_k + c_k sum_mu d_mu gamma_mu for a k-hop displacement d (k >= 1),
+// and 15/8 + m0 on the 0-hop term.  a_k is the Brillouin-Laplacian weight
+// -(1/2) * (1/4) * (1/2)^k, c_k the isotropic-derivative weight
+// (1/2) (1/6)^(k-1) (2/3)^(4-k); both are the position-space coefficients of
+// the momentum forms (cos p + 1)/2 and sin p (cos p + 2)/3 per axis.
+
+__host__ __device__ constexpr double lap_weight(int k) { return -1.0 / (double)(8 << k); }
+
+__host__ __device__ constexpr double iso_weight(int k) {
+    return k == 1 ? 4.0 / 27.0 : k == 2 ? 1.0 / 27.0 : k == 3 ? 1.0 / 108.0 : k == 4 ? 1.0 / 432.0 : 0.0;
+}
+
+// ----------------------------------------------------------- complex types
+
+template <typename R> struct Cx;
+template <> struct Cx<double> { using T = double2; };
+template <> struct Cx<float> { using T = float2; };
+
+template <typename C> __device__ __forceinline__ C cmake(decltype(C{}.x) r, decltype(C{}.x) i) {
+    C c;
+    c.x = r;
+    c.y = i;
+    return c;
+}
+
+// acc += w * v   (complex multiply-accumulate, 4 FMA)
+template <typename C> __device__ __forceinline__ void cmac(C &acc, const C &w, const C &v) {
+    acc.x = fma(w.x, v.x, acc.x);
+    acc.x = fma(-w.y, v.y, acc.x);
+    acc.y = fma(w.x, v.y, acc.y);
+    acc.y = fma(w.y, v.x, acc.y);
+}
+
+// acc += conj(w) * v
+template <typename C> __device__ __forceinline__ void cmac_conj(C &acc, const C &w, const C &v) {
+    acc.x = fma(w.x, v.x, acc.x);
+    acc.x = fma(w.y, v.y, acc.x);
+    acc.y = fma(w.x, v.y, acc.y);
+    acc.y = fma(-w.y, v.x, acc.y);
+}
+
+// ----------------------------------------------------------------- bfloat16
+// round-to-nearest-even from float; NaN kept quiet.
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    union {
+        float f;
+        uint32_t u;
+    } v;
+    v.f = f;
+    if ((v.u & 0x7f800000u) == 0x7f800000u && (v.u & 0x007fffffu)) return (uint16_t)((v.u >> 16) | 0x40u);
+    uint32_t lsb = (v.u >> 16) & 1u;
+    v.u += 0x7fffu + lsb;
+    return (uint16_t)(v.u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+    union {
+        float f;
+        uint32_t u;
+    } v;
+    v.u = (uint32_t)h << 16;
+    return v.f;
+}
+
+// ------------------------------------------------------- link storage types
+// LinkStore<P>::load returns element e of link slab j at site x as Cx<R>.
+
+struct LinkF64 {
+    using store_t = double2;
+    using R = double;
+    __device__ __forceinline__ static double2 load(const store_t *W, size_t idx) { return W[idx]; }
+};
+struct LinkF32 {
+    using store_t = float2;
+    using R = float;
+    __device__ __forceinline__ static float2 load(const store_t *W, size_t idx) { return W[idx]; }
+};
+struct LinkBF16 {
+    using store_t = uint32_t;  // (re, im) packed: re in the low half
+    using R = float;
+    __device__ __forceinline__ static float2 load(const store_t *W, size_t idx) {
+        uint32_t u = W[idx];
+        float2 c;
+        c.x = __uint_as_float(u << 16);
+        c.y = __uint_as_float(u & 0xffff0000u);
+        return c;
+    }
+};
+
+// ---------------------------------------------------------------- launches
+
+#define BRI_HIP_CHECK(expr)                           \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return BRI_EHIP;        \
+    } while (0)
+
+}  // namespace bri

@@ -1,0 +1,178 @@
+// bri_build_links: off-axis links of the Brillouin stencil (App. C.1).
+//
+// The average over the k! shortest paths from x to x+d obeys the hop-by-hop
+// recursion
+//   W_d(x) = (1/k) sum_{mu in supp d} T_mu(x) W_{d - s_mu e_mu}(x + s_mu e_mu),
+// with s_mu = d_mu, T_mu(x) = U_mu(x) for s_mu = +1 and U_mu(x - e_mu)^dag for
+// s_mu = -1: grouping the paths by their first step, each first step mu is
+// followed by all (k-1)! orderings of the remaining axes.  The links are built
+// level by level (k = 1..4 hops), one kernel per level, in FP64.  A level-(k-1)
+// link that is not stored is the hermitian conjugate of a stored one at the
+// far end, W_{d'}(y) = W_{-d'}(y + d')^dag.
+#include "common.hpp"
+
+namespace bri {
+
+__device__ __forceinline__ int wrap(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+__device__ __forceinline__ int site_index(const Geom &g, const int c[4]) {
+    return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+
+__global__ void build_level_kernel(Geom g, const double2 *__restrict__ U, double2 *__restrict__ W, int k) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.V) return;
+    const size_t V = (size_t)g.V;
+    int cx[4];
+    {
+        int s = x;
+        for (int mu = 0; mu < 4; ++mu) {
+            cx[mu] = s % g.L[mu];
+            s /= g.L[mu];
+        }
+    }
+    for (int j = 0; j < 40; ++j) {
+        int d[4], nh = 0;
+        for (int mu = 0; mu < 4; ++mu) {
+            d[mu] = disp_comp(j, mu);
+            nh += d[mu] != 0;
+        }
+        if (nh != k) continue;
+        double2 acc[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc[a][b] = make_double2(0.0, 0.0);
+        for (int mu = 0; mu < 4; ++mu) {
+            if (d[mu] == 0) continue;
+            const int s = d[mu];
+            // first step T_mu(x)
+            double2 T[3][3];
+            double sgn = 1.0;
+            if (s > 0) {
+                const int xs = x;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) T[a][b] = U[((size_t)(mu * 3 + a) * 3 + b) * V + xs];
+                if (g.tbc && mu == 3 && cx[3] == g.L[3] - 1) sgn = -1.0;
+            } else {
+                int cm[4] = {cx[0], cx[1], cx[2], cx[3]};
+                cm[mu] = wrap(cm[mu] - 1, g.L[mu]);
+                const int xs = site_index(g, cm);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double2 u = U[((size_t)(mu * 3 + b) * 3 + a) * V + xs];
+                        T[a][b] = make_double2(u.x, -u.y);
+                    }
+                if (g.tbc && mu == 3 && cx[3] == 0) sgn = -1.0;
+            }
+            // remainder W_{d - s e_mu}(x + s e_mu)
+            int cy[4] = {cx[0], cx[1], cx[2], cx[3]};
+            cy[mu] = wrap(cy[mu] + s, g.L[mu]);
+            int dr[4] = {d[0], d[1], d[2], d[3]};
+            dr[mu] = 0;
+            double2 M[3][3];
+            if (k == 1) {
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) M[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+            } else {
+                const int jr = (dr[0] + 1) + 3 * (dr[1] + 1) + 9 * (dr[2] + 1) + 27 * (dr[3] + 1);
+                if (jr < 40) {
+                    const int ys = site_index(g, cy);
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) M[a][b] = W[((size_t)jr * 9 + a * 3 + b) * V + ys];
+                } else {
+                    // W_{dr}(y) = W_{-dr}(y + dr)^dag, -dr stored at index 80 - jr
+                    int cz[4];
+                    for (int nu = 0; nu < 4; ++nu) cz[nu] = wrap(cy[nu] + dr[nu], g.L[nu]);
+                    const int zs = site_index(g, cz);
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            double2 w = W[((size_t)(80 - jr) * 9 + b * 3 + a) * V + zs];
+                            M[a][b] = make_double2(w.x, -w.y);
+                        }
+                }
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double2 t = make_double2(0.0, 0.0);
+                    for (int c = 0; c < 3; ++c) cmac(t, T[a][c], M[c][b]);
+                    acc[a][b].x = fma(sgn, t.x, acc[a][b].x);
+                    acc[a][b].y = fma(sgn, t.y, acc[a][b].y);
+                }
+        }
+        const double inv_k = 1.0 / (double)k;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double2 v = acc[a][b];
+                W[((size_t)j * 9 + a * 3 + b) * V + x] = make_double2(v.x * inv_k, v.y * inv_k);
+            }
+    }
+}
+
+__global__ void convert_f32_kernel(size_t n, const double2 *__restrict__ src, float2 *__restrict__ dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double2 v = src[i];
+        dst[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void convert_bf16_kernel(size_t n, const double2 *__restrict__ src, uint32_t *__restrict__ dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double2 v = src[i];
+        // round the double to float first (exact for the bfloat16 grid), then to bfloat16
+        uint32_t re = f32_to_bf16((float)v.x), im = f32_to_bf16((float)v.y);
+        dst[i] = re | (im << 16);
+    }
+}
+
+int geom_check(const bri_geom *geom, Geom *g) {
+    if (!geom) return BRI_EINVAL;
+    long long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (geom->L[mu] < 1 || geom->L[mu] > 4096) return BRI_EINVAL;
+        g->L[mu] = geom->L[mu];
+        V *= geom->L[mu];
+    }
+    // 40 link slabs of 9 complex entries per site must stay addressable by a 32-bit element offset
+    if (V * 360LL >= (1LL << 31)) return BRI_EINVAL;
+    if (geom->tbc != 0 && geom->tbc != 1) return BRI_EINVAL;
+    g->V = (int)V;
+    g->tbc = geom->tbc;
+    return BRI_OK;
+}
+
+int build_links_f64(const Geom &g, const double2 *U, double2 *W, hipStream_t st) {
+    const int threads = 128;
+    const int blocks = (g.V + threads - 1) / threads;
+    for (int k = 1; k <= 4; ++k) {
+        hipLaunchKernelGGL(build_level_kernel, dim3(blocks), dim3(threads), 0, st, g, U, W, k);
+        BRI_HIP_CHECK(hipGetLastError());
+    }
+    return BRI_OK;
+}
+
+}  // namespace bri
+
+extern "C" int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, void *stream) {
+    using namespace bri;
+    Geom g;
+    int st = geom_check(geom, &g);
+    if (st != BRI_OK) return st;
+    if (!U || !W) return BRI_EINVAL;
+    if (wprec != BRI_F64 && wprec != BRI_F32 && wprec != BRI_F32_BF16W) return BRI_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (wprec == BRI_F64) return build_links_f64(g, (const double2 *)U, (double2 *)W, s);
+    const size_t n = (size_t)360 * g.V;
+    double2 *tmp = nullptr;
+    BRI_HIP_CHECK(hipMalloc(&tmp, n * sizeof(double2)));
+    st = build_links_f64(g, (const double2 *)U, tmp, s);
+    if (st == BRI_OK) {
+        const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+        if (wprec == BRI_F32)
+            hipLaunchKernelGGL(convert_f32_kernel, dim3(blocks), dim3(256), 0, s, n, tmp, (float2 *)W);
+        else
+            hipLaunchKernelGGL(convert_bf16_kernel, dim3(blocks), dim3(256), 0, s, n, tmp, (uint32_t *)W);
+        if (hipGetLastError() != hipSuccess) st = BRI_EHIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) st = BRI_EHIP;
+    if (hipFree(tmp) != hipSuccess) st = BRI_EHIP;
+    return st;
+}

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/brillouin.h declares, computes the Kenney-Laub
+coefficients of eq. (KLnn_parfrac) on the host, sizes its workspace and rejects
+bad arguments before launching anything."""
+
+import ctypes
+import os
+import re
+
+import mpmath as mp
+import pytest
+
+import paper_1701_00726_amd as bri
+from oracle import kl
+from tests.conftest import ROOT
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "brillouin.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*int\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    lib = bri.load()
+    names = _declared()
+    assert set(names) == set(bri.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 13, 16, 32])
+def test_host_kl_coefficients_match_oracle(n):
+    c0, om, sg = bri.kl_coeffs(n)
+    rc0, rom, rsg = kl.kl_diag_coeffs(n)
+    assert abs(c0 - float(rc0)) == 0
+    assert sg == sorted(sg)
+    for a, b in zip(om, rom):
+        assert abs(mp.mpf(a) - b) <= 6e-16 * abs(b)
+    for a, b in zip(sg, rsg):
+        assert abs(mp.mpf(a) - b) <= 6e-16 * abs(b)
+
+
+def _ov_query(L, **kw):
+    g = bri._geom(L)
+    prm = bri._OvParams(kw.get("kl_n", 8), kw.get("rho", 1.0), kw.get("tol", 1e-10), kw.get("max_iter", 100),
+                        kw.get("inner", 0), kw.get("max_refine", 0))
+    nb = ctypes.c_size_t(0)
+    st = bri.load().ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb),
+                             None, None)
+    return st, nb.value
+
+
+def test_workspace_query():
+    st, nbytes = _ov_query((16, 16, 16, 16), kl_n=16)
+    V = 16**4
+    assert st == bri.OK
+    # r, p, t, y and 15 shifted directions of 12 V complex doubles, plus small state
+    assert 19 * 12 * V * 16 <= nbytes < 19 * 12 * V * 16 + (1 << 20)
+
+
+@pytest.mark.parametrize(
+    "L,kw",
+    [
+        ((16, 16, 16, 16), dict(kl_n=0)),
+        ((16, 16, 16, 16), dict(kl_n=33)),
+        ((16, 16, 16, 16), dict(rho=2.0)),
+        ((16, 16, 16, 16), dict(rho=0.0)),
+        ((16, 16, 16, 16), dict(tol=0.0)),
+        ((16, 16, 16, 16), dict(max_iter=0)),
+        ((16, 16, 16, 16), dict(inner=7)),
+        ((3, 3, 3, 3), dict()),
+        ((0, 4, 4, 4), dict()),
+    ],
+)
+def test_invalid_arguments(L, kw):
+    st, _ = _ov_query(L, **kw)
+    assert st == bri.EINVAL
+
+
+def test_invalid_stencil_arguments():
+    lib = bri.load()
+    g = bri._geom((5, 5, 4, 4))  # V = 400 is not a whole number of 64-site tiles
+    assert lib.bri_apply(ctypes.byref(g), ctypes.c_void_p(16), 0, -1.0, ctypes.c_void_p(16), ctypes.c_void_p(32), 1,
+                         None) == bri.EINVAL
+    g = bri._geom((4, 4, 4, 4))
+    assert lib.bri_apply(ctypes.byref(g), None, 0, -1.0, ctypes.c_void_p(16), ctypes.c_void_p(32), 1, None) == bri.EINVAL
+    assert lib.bri_apply_dag(ctypes.byref(g), ctypes.c_void_p(16), 9, -1.0, ctypes.c_void_p(16), ctypes.c_void_p(32),
+                             1, None) == bri.EINVAL
+    assert lib.bri_build_links(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None) == bri.EINVAL
+    assert lib.bri_build_links(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 5, None) == bri.EINVAL
+    g.tbc = 2
+    assert lib.bri_build_links(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None) == bri.EINVAL
