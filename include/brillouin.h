@@ -105,10 +105,11 @@ int bri_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, cons
 typedef struct {
     int kl_n;       /* Kenney-Laub order n: f_{n,n} = g_{2n+1}, 1..BRI_MAX_SHIFTS */
     double rho;     /* 0 < rho < 2; kernel mass m0 = -rho                        */
-    double tol;     /* per-shift stop: |r_sigma| <= tol |psi|                    */
-    int max_iter;   /* multi-shift CG iteration cap                              */
-    int inner;      /* bri_prec of the inner solve (BRI_F64 only in this build)  */
-    int max_refine; /* reserved for defect correction; 0                         */
+    double tol;     /* per-shift stop: |b - (A + sigma) x_sigma| <= tol |psi|    */
+    int max_iter;   /* CG iteration cap of each (multi-shift or correction) solve */
+    int inner;      /* bri_prec of the multi-shift: BRI_F64, or BRI_F32 /
+                       BRI_F32_BF16W with FP64 defect correction of every shift */
+    int max_refine; /* mixed precision: FP64 residual + correction passes, 0..100 */
 } ov_params;
 
 /* Statistics of one overlap apply (the last right-hand side for nrhs > 1). */
@@ -124,9 +125,13 @@ typedef struct {
  * ov_sign_apply -- out ~= sign(H) in = gamma5 X r_n(X^dag X) in, H = gamma5 D_bri(-rho)
  * ov_apply      -- out ~= D_ov in   = rho (in + X r_n(X^dag X) in)          eq. (def_over)
  * r_n(A) in is evaluated by one multi-shift CG on A + sigma_min for all n
- * shifts at once (Sec. 3.3), with the coefficients of eq. (KLnn_parfrac).
+ * shifts at once (Sec. 3.3), with the coefficients of eq. (KLnn_parfrac); the
+ * nrhs right-hand sides run side by side, each with its own Krylov space.
+ * With a low-precision inner solve the multi-shift runs on Wlo, every shift
+ * solution is kept, and each (shift, source) column is corrected against its
+ * FP64 residual (formed with W64) until it meets tol.
  *   W64 : [40][3][3][V] complex double off-axis links
- *   Wlo : low-precision links for a mixed inner solve; NULL when inner = BRI_F64
+ *   Wlo : links in precision `inner` (from bri_build_links); NULL when inner = BRI_F64
  *   in, out : [nrhs][4][3][V] complex double (device); must not overlap
  *   work, work_bytes : device workspace; with work == NULL the call only writes
  *         the required size into *work_bytes and returns BRI_OK.

@@ -232,16 +232,25 @@ def apply_dag(L, W, prec, m0, psi, out=None, stream=None):
 class OverlapOp:
     """Holds the workspace of ov_apply / ov_sign_apply for one lattice and parameter set."""
 
-    def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0):
+    def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0,
+                 max_refine=None, nrhs=1):
+        """Workspace for up to `nrhs` right-hand sides per call.  inner = F32 or
+        F32_BF16W runs the multi-shift with the low-precision links `Wlo` and refines
+        every shift in FP64 (at most max_refine passes, default 10)."""
         self.L = tuple(int(v) for v in L)
         self.g = _geom(self.L, tbc)
         self.W64 = W64
         self.Wlo = Wlo
-        self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), 0)
+        if inner != F64 and Wlo is None:
+            raise ValueError("a low-precision inner solve needs Wlo")
+        if max_refine is None:
+            max_refine = 0 if inner == F64 else 10
+        self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine))
+        self.nrhs = int(nrhs)
         nbytes = ctypes.c_size_t(0)
         _check(
             "ov_apply",
-            load().ov_apply(ctypes.byref(self.g), None, None, ctypes.byref(self.params), None, None, 1, None,
+            load().ov_apply(ctypes.byref(self.g), None, None, ctypes.byref(self.params), None, None, self.nrhs, None,
                             ctypes.byref(nbytes), None, None),
         )
         torch = _torch()
@@ -253,6 +262,8 @@ class OverlapOp:
         V = int(np.prod(self.L))
         if psi.dtype != torch.complex128 or psi.dim() != 4 or tuple(psi.shape[1:]) != (4, 3, V):
             raise ValueError("psi must be complex128 (nrhs, 4, 3, V)")
+        if psi.shape[0] > self.nrhs:
+            raise ValueError(f"workspace sized for {self.nrhs} right-hand sides, got {psi.shape[0]}")
         if out is None:
             out = torch.empty_like(psi)
         stats = _OvStats()

@@ -1,11 +1,11 @@
 // Overlap operator apply: D_ov psi = rho (psi + X r_n(X^dag X) psi), X = D_bri(-rho)
 // (eq. (def_over)), with the Kenney-Laub partial fractions
 //   r_n(t) = c0 + sum_i omega_i / (t + sigma_i)            (eq. (KLnn_parfrac))
-// evaluated by one multi-shift conjugate gradient on A + sigma_0, A = X^dag X,
-// sigma_0 the smallest shift (Sec. 3.3).
+// evaluated by a multi-shift conjugate gradient on A + sigma_0, A = X^dag X,
+// sigma_0 the smallest shift (Sec. 3.3).  Many right-hand sides ("columns")
+// run side by side, each with its own Krylov space and FP64 scalars.
 //
-// Multi-shift CG (Krylov space shared by all shifted systems).  The base
-// system (A + sigma_0) x = b runs plain CG:
+// Multi-shift CG.  The base system (A + sigma_0) x = b runs plain CG:
 //   alpha_k = (r_k, r_k) / (p_k, (A + sigma_0) p_k),  r_{k+1} = r_k - alpha_k (A + sigma_0) p_k,
 //   beta_k = (r_{k+1}, r_{k+1}) / (r_k, r_k),          p_{k+1} = r_{k+1} + beta_k p_k.
 // For sigma = sigma_0 + delta the residuals stay collinear, r^sigma_k = zeta^sigma_k r_k,
@@ -17,40 +17,33 @@
 //   x^sigma_{k+1} = x^sigma_k + alpha^sigma_k p^sigma_k,
 //   p^sigma_{k+1} = zeta_{k+1} r_{k+1} + beta^sigma_k p^sigma_k,
 // with zeta_0 = zeta_{-1} = 1, alpha_{-1} = 1, beta_{-1} = 0.  Shift sigma stops once
-// |zeta^sigma| |r| <= tol |b|.  Only y = c0 b + sum_sigma omega_sigma x^sigma is
-// needed, so the x^sigma are never stored: y accumulates omega_sigma alpha^sigma p^sigma.
-// The base shift has zeta = 1, so its search direction is p itself.
+// |zeta^sigma| |r| <= tol |b|.  The base shift has zeta = 1, so its search
+// direction is p itself.  When only y = c0 b + sum_sigma omega_sigma x^sigma is
+// needed the x^sigma are never stored: y accumulates omega_sigma alpha^sigma p^sigma.
 //
-// All scalars live on the device (MsState) and are updated by single-block
-// kernels; the host only polls the `done` flag every few iterations, and every
-// loop kernel returns at once when `done` is set.
+// Mixed precision (inner = BRI_F32 or BRI_F32_BF16W): the multi-shift runs with
+// low-precision links and vectors, keeping every x^sigma.  Then, repeatedly, the
+// residual r^sigma = b - (A + sigma) x^sigma of every (shift, source) column is
+// formed in FP64 with the FP64 links, and the corrections (A + sigma) e = r^sigma
+// are solved in low precision as a batch of single-shift CGs (one shift per
+// column); x^sigma += e in FP64.  Finally y and the output are formed in FP64.
+//
+// All solver scalars live on the device (ColState) and are updated by small
+// kernels; the host only polls a done flag every few iterations, and every
+// loop kernel returns at once for columns that are done.
 #include <math.h>
 
 #include <chrono>
 #include <cstring>
+#include <vector>
 
 #include "stencil.hpp"
 
 namespace bri {
 
-constexpr int MAXS = BRI_MAX_SHIFTS;
 constexpr int RED_THREADS = 256;
 constexpr int CHECK_EVERY = 8;
-
-struct MsState {
-    double rr, bnorm2, tol2;
-    double alpha, alpha_old, beta, beta_old;
-    double sigma0;
-    int iter, done, status, nshift;
-    double c0;
-    double delta[MAXS], omega[MAXS];
-    double zeta[MAXS], zeta_old[MAXS], zeta_new[MAXS];
-    double alpha_s[MAXS], beta_s[MAXS];
-    int active[MAXS];       // shift still iterating
-    int upd_x[MAXS];        // shift contributes alpha^sigma p^sigma in this iteration
-    int conv_iter[MAXS];
-    double conv_res[MAXS];  // |zeta r| / |b| when the shift stopped
-};
+constexpr int INIT_BLOCKS = 256;  // vector-kernel blocks per column
 
 // --------------------------------------------------------------- reductions
 
@@ -72,18 +65,35 @@ __device__ double block_sum(const double *partial, int n, int comp) {
 
 // ------------------------------------------------------------------ kernels
 
-// r = p = b, p_sigma = b (sigma >= 1), y = c0 b; partial |b|^2
-template <typename C>
-__global__ void ms_init_kernel(size_t n, const C *__restrict__ b, C *__restrict__ r, C *__restrict__ p,
-                               C *__restrict__ y, C *__restrict__ ps, int nps, double c0, double *partial) {
+// column c = blockIdx.y.  r = p = b, p_sigma = b, and y = c0 b (or x_sigma = 0);
+// partial |b|^2.  B is the input type (double2 or float2), C the solver type.
+template <typename B, typename C>
+__global__ void ms_init_kernel(size_t n, const B *__restrict__ b, C *__restrict__ r, C *__restrict__ p,
+                               C *__restrict__ y, C *__restrict__ x, C *__restrict__ ps, int ncol, int nshift,
+                               double c0, double *partial) {
+    const int col = blockIdx.y;
+    const size_t off = (size_t)col * n;
     double s = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const C v = b[i];
-        r[i] = v;
-        p[i] = v;
-        y[i].x = c0 * v.x;
-        y[i].y = c0 * v.y;
-        for (int k = 0; k < nps; ++k) ps[(size_t)k * n + i] = v;
+        const B bv = b[off + i];
+        C v;
+        v.x = bv.x;
+        v.y = bv.y;
+        r[off + i] = v;
+        p[off + i] = v;
+        if (y) {
+            C yv;
+            yv.x = c0 * bv.x;
+            yv.y = c0 * bv.y;
+            y[off + i] = yv;
+        }
+        if (x) {
+            C z;
+            z.x = 0;
+            z.y = 0;
+            for (int k = 0; k < nshift; ++k) x[((size_t)k * ncol + col) * n + i] = z;
+        }
+        for (int k = 1; k < nshift; ++k) ps[((size_t)(k - 1) * ncol + col) * n + i] = v;
         s += (double)v.x * v.x + (double)v.y * v.y;
     }
     __shared__ double sh[256];
@@ -94,13 +104,15 @@ __global__ void ms_init_kernel(size_t n, const C *__restrict__ b, C *__restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = sh[0];
-        partial[2 * blockIdx.x + 1] = 0.0;
+        partial[2 * ((size_t)col * gridDim.x + blockIdx.x)] = sh[0];
+        partial[2 * ((size_t)col * gridDim.x + blockIdx.x) + 1] = 0.0;
     }
 }
 
-__global__ void ms_scalar_init_kernel(MsState *st, const double *partial, int nblk, double tol) {
-    const double b2 = block_sum(partial, nblk, 0);
+// one block per column
+__global__ void ms_scalar_init_kernel(ColState *states, const double *partial, int nblk, double tol) {
+    ColState *st = states + blockIdx.x;
+    const double b2 = block_sum(partial + 2 * (size_t)blockIdx.x * nblk, nblk, 0);
     if (threadIdx.x == 0) {
         st->bnorm2 = b2;
         st->rr = b2;
@@ -131,10 +143,12 @@ __global__ void ms_scalar_init_kernel(MsState *st, const double *partial, int nb
 }
 
 // alpha and the shifted alpha^sigma after t = X p (partials: |t|^2, |p|^2)
-__global__ void ms_alpha_kernel(MsState *st, const double *partial, int nblk) {
+__global__ void ms_alpha_kernel(ColState *states, const double *partial, int nblk) {
+    ColState *st = states + blockIdx.x;
     if (st->done) return;
-    const double tt = block_sum(partial, nblk, 0);
-    const double pp = block_sum(partial, nblk, 1);
+    const double *pt = partial + 2 * (size_t)blockIdx.x * nblk;
+    const double tt = block_sum(pt, nblk, 0);
+    const double pp = block_sum(pt, nblk, 1);
     if (threadIdx.x == 0) {
         const double pAp = tt + st->sigma0 * pp;
         const double alpha = st->rr / pAp;
@@ -159,16 +173,20 @@ __global__ void ms_alpha_kernel(MsState *st, const double *partial, int nblk) {
 }
 
 // beta, beta^sigma, convergence after r -= alpha (A + sigma0) p (partials: |r|^2)
-__global__ void ms_beta_kernel(MsState *st, const double *partial, int nblk) {
+__global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk) {
+    ColState *st = states + blockIdx.x;
     if (st->done) return;
-    const double rr_new = block_sum(partial, nblk, 0);
+    const double rr_new = block_sum(partial + 2 * (size_t)blockIdx.x * nblk, nblk, 0);
     if (threadIdx.x == 0) {
         const int it = st->iter + 1;
         st->iter = it;
         if (!isfinite(rr_new)) {
             st->status = BRI_ENAN;
             st->done = 1;
-            for (int i = 0; i < st->nshift; ++i) st->active[i] = 0;
+            for (int i = 0; i < st->nshift; ++i) {
+                st->active[i] = 0;
+                st->upd_x[i] = 0;
+            }
             return;
         }
         const double beta = rr_new / st->rr;
@@ -192,53 +210,103 @@ __global__ void ms_beta_kernel(MsState *st, const double *partial, int nblk) {
         st->beta_old = beta;
         st->beta = beta;
         st->rr = rr_new;
-        if (!any) st->done = 2;  // converged: the last vector update still runs
+        if (!any) st->done = 2;  // converged: this iteration's vector update still runs
     }
 }
 
-// y += sum_sigma omega alpha^sigma p^sigma (base shift: p); then
-// p^sigma = zeta^sigma r + beta^sigma p^sigma, p = r + beta p
+// column c = blockIdx.y:
+//   y += sum_sigma omega alpha^sigma p^sigma   (or x^sigma += alpha^sigma p^sigma)
+//   p^sigma = zeta^sigma r + beta^sigma p^sigma,  p = r + beta p
 template <typename C>
-__global__ void ms_update_kernel(const MsState *__restrict__ st, size_t n, const C *__restrict__ r,
-                                 C *__restrict__ p, C *__restrict__ y, C *__restrict__ ps) {
+__global__ void ms_update_kernel(const ColState *__restrict__ states, size_t n, int ncol, const C *__restrict__ r,
+                                 C *__restrict__ p, C *__restrict__ y, C *__restrict__ x, C *__restrict__ ps) {
+    const int col = blockIdx.y;
+    const ColState *st = states + col;
     const int done = st->done;
     if (done == 1) return;
     const int ns = st->nshift;
     const double beta = st->beta;
+    const size_t off = (size_t)col * n;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const C ri = r[i];
-        C pi = p[i];
-        C yi = y[i];
-        if (st->upd_x[0]) {
-            const double w = st->omega[0] * st->alpha_s[0];
-            yi.x += w * pi.x;
-            yi.y += w * pi.y;
-        }
-        for (int k = 1; k < ns; ++k) {
+        const C ri = r[off + i];
+        C pi = p[off + i];
+        C yi;
+        if (y) yi = y[off + i];
+        for (int k = 0; k < ns; ++k) {
             if (!st->upd_x[k]) continue;
-            C *pk = ps + (size_t)(k - 1) * n;
-            C v = pk[i];
-            const double w = st->omega[k] * st->alpha_s[k];
-            yi.x += w * v.x;
-            yi.y += w * v.y;
-            if (st->active[k]) {
+            C *pk = k == 0 ? nullptr : ps + ((size_t)(k - 1) * ncol + col) * n;
+            C v = k == 0 ? pi : pk[i];
+            const double as = st->alpha_s[k];
+            if (y) {
+                const double w = st->omega[k] * as;
+                yi.x += w * v.x;
+                yi.y += w * v.y;
+            } else {
+                C *xk = x + ((size_t)k * ncol + col) * n;
+                C xv = xk[i];
+                xv.x += as * v.x;
+                xv.y += as * v.y;
+                xk[i] = xv;
+            }
+            if (k > 0 && st->active[k]) {
                 const double z = st->zeta[k], bs = st->beta_s[k];
                 v.x = z * ri.x + bs * v.x;
                 v.y = z * ri.y + bs * v.y;
                 pk[i] = v;
             }
         }
-        y[i] = yi;
+        if (y) y[off + i] = yi;
         if (done == 0) {
             pi.x = ri.x + beta * pi.x;
             pi.y = ri.y + beta * pi.y;
-            p[i] = pi;
+            p[off + i] = pi;
         }
     }
 }
 
-__global__ void ms_finish_kernel(MsState *st) {
-    if (st->done == 2) st->done = 1;
+// done 2 -> 1 for every column; *alldone = 1 once every column is done
+__global__ void ms_finish_kernel(ColState *states, int ncol, int *alldone) {
+    __shared__ int cnt[256];
+    int mine = 0;
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+        if (states[c].done == 2) states[c].done = 1;
+        mine += states[c].done != 0;
+    }
+    cnt[threadIdx.x] = mine;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *alldone = (cnt[0] == ncol) ? 1 : 0;
+}
+
+// y = c0 b + sum_k omega_k x_k (FP64), column c = blockIdx.y
+__global__ void combine_kernel(size_t n, int ncol, int nshift, double c0, const double *__restrict__ omega,
+                               const double2 *__restrict__ b, const double2 *__restrict__ x, double2 *__restrict__ y) {
+    const int col = blockIdx.y;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 bv = b[(size_t)col * n + i];
+        double2 v = make_double2(c0 * bv.x, c0 * bv.y);
+        for (int k = 0; k < nshift; ++k) {
+            const double2 xv = x[((size_t)k * ncol + col) * n + i];
+            v.x += omega[k] * xv.x;
+            v.y += omega[k] * xv.y;
+        }
+        y[(size_t)col * n + i] = v;
+    }
+}
+
+// dst = src (widened to FP64), or dst += src with accumulate
+template <typename S>
+__global__ void widen_kernel(size_t count, const S *__restrict__ src, double2 *__restrict__ dst, int accumulate) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const S v = src[i];
+        double2 d = accumulate ? dst[i] : make_double2(0.0, 0.0);
+        d.x += (double)v.x;
+        d.y += (double)v.y;
+        dst[i] = d;
+    }
 }
 
 // ----------------------------------------------------------------- host side
@@ -265,26 +333,313 @@ void kl_coeffs(int n, double *c0, double *omega, double *sigma) {
     }
 }
 
-struct Workspace {
-    size_t bytes;
-    size_t off_state, off_partial, off_vec;
-    int nblk_red;
-};
-
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static Workspace plan_workspace(const Geom &g, int nshift) {
-    Workspace w;
-    const size_t vec = (size_t)12 * g.V * sizeof(double2);
-    const int nblk_st = stencil_blocks(g);
-    const int nblk_init = 1024;
-    w.nblk_red = nblk_st > nblk_init ? nblk_st : nblk_init;
-    w.off_state = 0;
-    w.off_partial = align256(sizeof(MsState));
-    w.off_vec = align256(w.off_partial + sizeof(double) * 2 * (size_t)w.nblk_red);
-    // r, p, t, y, and nshift - 1 shifted directions
-    w.bytes = w.off_vec + align256(vec) * (size_t)(4 + nshift - 1);
-    return w;
+// bump allocator over the caller's workspace (only counts bytes when base is NULL)
+struct Arena {
+    char *base;
+    size_t used = 0;
+    explicit Arena(void *b) : base((char *)b) {}
+    void *take(size_t bytes) {
+        void *p = base ? base + used : nullptr;
+        used += align256(bytes);
+        return p;
+    }
+};
+
+// One batched multi-shift solve: ncol columns, nshift shifts each.
+struct MsSolve {
+    Geom g;
+    int prec = BRI_F64;  // vector / stencil precision
+    const void *W = nullptr;
+    double m0 = 0.0;
+    int ncol = 1, nshift = 1;
+    bool store_x = false;  // keep x^sigma (else accumulate y)
+    double c0 = 0.0;
+    std::vector<double> omega;  // [nshift]
+    std::vector<double> sigma;  // [ncol][nshift], ascending per column
+    double tol = 1e-12;
+    int max_iter = 1000;
+    // workspace pieces
+    ColState *st = nullptr;
+    double *partial = nullptr;
+    int *alldone = nullptr;
+    void *r = nullptr, *p = nullptr, *t = nullptr, *y = nullptr, *x = nullptr, *ps = nullptr;
+    int nblk_st = 0;
+
+    size_t csize() const { return prec == BRI_F64 ? sizeof(double2) : sizeof(float2); }
+
+    void carve(Arena &ar) {
+        nblk_st = stencil_blocks(g);
+        const int nb = nblk_st > INIT_BLOCKS ? nblk_st : INIT_BLOCKS;
+        st = (ColState *)ar.take(sizeof(ColState) * ncol);
+        partial = (double *)ar.take(sizeof(double) * 2 * (size_t)nb * ncol);
+        alldone = (int *)ar.take(sizeof(int));
+        const size_t vb = (size_t)12 * g.V * csize() * ncol;
+        r = ar.take(vb);
+        p = ar.take(vb);
+        t = ar.take(vb);
+        if (store_x)
+            x = ar.take(vb * nshift);
+        else
+            y = ar.take(vb);
+        if (nshift > 1) ps = ar.take(vb * (nshift - 1));
+    }
+};
+
+struct RunStats {
+    int iters = 0;
+    int status = BRI_OK;
+    std::vector<ColState> fin;
+};
+
+// Runs one batched multi-shift solve; b is [ncol][12 V] complex double (or
+// complex float when b_is_f64 is false).  Returns a HIP / argument status;
+// convergence and NaN status land in rs.
+static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, int *hflag, RunStats &rs) {
+    const size_t n = (size_t)12 * s.g.V;
+    std::vector<ColState> h(s.ncol);
+    for (int c = 0; c < s.ncol; ++c) {
+        ColState &cs = h[c];
+        std::memset(&cs, 0, sizeof(cs));
+        cs.nshift = s.nshift;
+        cs.c0 = s.c0;
+        cs.sigma0 = s.sigma[(size_t)c * s.nshift];
+        for (int i = 0; i < s.nshift; ++i) {
+            cs.omega[i] = s.omega[i];
+            cs.delta[i] = s.sigma[(size_t)c * s.nshift + i] - cs.sigma0;
+        }
+    }
+    BRI_HIP_CHECK(hipMemcpyAsync(s.st, h.data(), sizeof(ColState) * s.ncol, hipMemcpyHostToDevice, strm));
+    const dim3 vgrid(INIT_BLOCKS, s.ncol);
+    if (s.prec == BRI_F64) {
+        hipLaunchKernelGGL((ms_init_kernel<double2, double2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
+                           (double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x, (double2 *)s.ps, s.ncol,
+                           s.nshift, s.c0, s.partial);
+    } else if (b_is_f64) {
+        hipLaunchKernelGGL((ms_init_kernel<double2, float2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
+                           (float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps, s.ncol,
+                           s.nshift, s.c0, s.partial);
+    } else {
+        hipLaunchKernelGGL((ms_init_kernel<float2, float2>), vgrid, dim3(256), 0, strm, n, (const float2 *)b,
+                           (float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps, s.ncol,
+                           s.nshift, s.c0, s.partial);
+    }
+    hipLaunchKernelGGL(ms_scalar_init_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, INIT_BLOCKS,
+                       s.tol);
+    BRI_HIP_CHECK(hipGetLastError());
+
+    const StencilConfig cfg = default_config(s.g, s.prec, s.ncol);
+    StencilArgs a1{};
+    a1.g = s.g;
+    a1.W = s.W;
+    a1.ncol = s.ncol;
+    a1.in = s.p;
+    a1.out = s.t;
+    a1.diag = 15.0 / 8.0 + s.m0;
+    a1.partial = s.partial;
+    a1.st = s.st;
+    StencilArgs a2 = a1;
+    a2.in = s.t;
+    a2.out = nullptr;
+    a2.p = s.p;
+    a2.r = s.r;
+
+    int it = 0;
+    for (;;) {
+        for (int k = 0; k < CHECK_EVERY && it < s.max_iter; ++k, ++it) {
+            const int e1 = stencil_launch(a1, s.prec, false, EPI_NORMS, cfg, strm);
+            hipLaunchKernelGGL(ms_alpha_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, s.nblk_st);
+            const int e2 = stencil_launch(a2, s.prec, true, EPI_CG_R, cfg, strm);
+            hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, s.nblk_st);
+            if (s.prec == BRI_F64)
+                hipLaunchKernelGGL(ms_update_kernel<double2>, vgrid, dim3(256), 0, strm, s.st, n, s.ncol,
+                                   (const double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x,
+                                   (double2 *)s.ps);
+            else
+                hipLaunchKernelGGL(ms_update_kernel<float2>, vgrid, dim3(256), 0, strm, s.st, n, s.ncol,
+                                   (const float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps);
+            hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(256), 0, strm, s.st, s.ncol, s.alldone);
+            if (e1 != BRI_OK || e2 != BRI_OK) return e1 != BRI_OK ? e1 : e2;
+            BRI_HIP_CHECK(hipGetLastError());
+        }
+        BRI_HIP_CHECK(hipMemcpyAsync(hflag, s.alldone, sizeof(int), hipMemcpyDeviceToHost, strm));
+        BRI_HIP_CHECK(hipStreamSynchronize(strm));
+        if (*hflag || it >= s.max_iter) break;
+    }
+    rs.fin.resize(s.ncol);
+    BRI_HIP_CHECK(hipMemcpyAsync(rs.fin.data(), s.st, sizeof(ColState) * s.ncol, hipMemcpyDeviceToHost, strm));
+    BRI_HIP_CHECK(hipStreamSynchronize(strm));
+    rs.iters = 0;
+    rs.status = BRI_OK;
+    for (const ColState &c : rs.fin) {
+        if (c.iter > rs.iters) rs.iters = c.iter;
+        if (c.status == BRI_ENAN)
+            rs.status = BRI_ENAN;
+        else if (c.done == 0 && rs.status == BRI_OK)
+            rs.status = BRI_ENOCONV;
+    }
+    return BRI_OK;
+}
+
+// ---------------------------------------------------------------- overlap
+
+constexpr int REFINE_CHUNK = 32;  // (shift, source) columns per refinement batch
+
+struct OvPlan {
+    int n = 0, nrhs = 0, chunk = 0;
+    bool mixed = false;
+    double c0 = 0.0, om[MAXS], sg[MAXS];
+    MsSolve main;                 // FP64: y accumulated; mixed: every x^sigma kept
+    MsSolve corr;                 // mixed: batched single-shift corrections
+    double2 *x64 = nullptr;       // mixed: [n][nrhs][12V] FP64 shift solutions
+    double2 *res64 = nullptr;     // mixed: residual columns of one chunk
+    double2 *t64 = nullptr;       // mixed: X x for one chunk
+    double2 *y64 = nullptr;       // mixed: combined y [nrhs][12V]
+    double *sig_dev = nullptr;    // mixed: shift per residual column
+    double *omega_dev = nullptr;  // mixed: omega [n]
+    double *partial = nullptr;    // mixed: residual norms [chunk][nblk][2]
+    size_t bytes = 0;
+};
+
+static void plan_overlap(OvPlan &pl, const Geom &g, const ov_params *prm, int nrhs, const void *W64, const void *Wlo,
+                         void *work) {
+    pl.n = prm->kl_n;
+    pl.nrhs = nrhs;
+    pl.mixed = prm->inner != BRI_F64;
+    kl_coeffs(pl.n, &pl.c0, pl.om, pl.sg);
+    Arena ar(work);
+    MsSolve &m = pl.main;
+    m.g = g;
+    m.prec = pl.mixed ? prm->inner : BRI_F64;
+    m.W = pl.mixed ? Wlo : W64;
+    m.m0 = -prm->rho;
+    m.ncol = nrhs;
+    m.nshift = pl.n;
+    m.store_x = pl.mixed;
+    m.c0 = pl.c0;
+    m.omega.assign(pl.om, pl.om + pl.n);
+    m.sigma.resize((size_t)nrhs * pl.n);
+    for (int c = 0; c < nrhs; ++c)
+        for (int i = 0; i < pl.n; ++i) m.sigma[(size_t)c * pl.n + i] = pl.sg[i];
+    // the low-precision stage stops near its rounding floor; refinement delivers tol
+    m.tol = pl.mixed ? (prm->tol > 1e-5 ? prm->tol : 1e-5) : prm->tol;
+    m.max_iter = prm->max_iter;
+    m.carve(ar);
+    if (pl.mixed) {
+        // a chunk is a whole number of sources, so chunk column k reads source k % nrhs
+        const int per = REFINE_CHUNK / nrhs > 0 ? REFINE_CHUNK / nrhs : 1;
+        pl.chunk = nrhs * (per < pl.n ? per : pl.n);
+        const size_t vb = (size_t)12 * g.V * sizeof(double2);
+        pl.x64 = (double2 *)ar.take(vb * nrhs * pl.n);
+        pl.res64 = (double2 *)ar.take(vb * pl.chunk);
+        pl.t64 = (double2 *)ar.take(vb * pl.chunk);
+        pl.y64 = (double2 *)ar.take(vb * nrhs);
+        pl.sig_dev = (double *)ar.take(sizeof(double) * pl.chunk);
+        pl.omega_dev = (double *)ar.take(sizeof(double) * pl.n);
+        pl.partial = (double *)ar.take(sizeof(double) * 2 * (size_t)stencil_blocks(g) * pl.chunk);
+        MsSolve &e = pl.corr;
+        e.g = g;
+        e.prec = prm->inner;
+        e.W = Wlo;
+        e.m0 = -prm->rho;
+        e.ncol = pl.chunk;
+        e.nshift = 1;
+        e.store_x = true;
+        e.c0 = 0.0;
+        e.omega.assign(1, 1.0);
+        e.sigma.assign(pl.chunk, 0.0);
+        e.tol = 1e-5;  // the corrections only need a few digits
+        e.max_iter = prm->max_iter;
+        e.carve(ar);
+    }
+    pl.bytes = ar.used;
+}
+
+// Mixed precision: refine every (shift, source) column of x64 until its FP64
+// residual is below tol.  shift_res receives the worst residual per shift of
+// the last check.
+static int refine(OvPlan &pl, const Geom &g, const ov_params *prm, const void *W64, const void *in, hipStream_t s,
+                  int *hflag, int &passes, std::vector<double> &shift_res) {
+    const int n = pl.n, nrhs = pl.nrhs, total = n * nrhs, chunk = pl.chunk;
+    const size_t nel = (size_t)12 * g.V;
+    const int nblk = stencil_blocks(g);
+    std::vector<double> part, hsig(chunk), b2(nrhs, 0.0);
+    // |b|^2 per source from the main solve's states
+    {
+        std::vector<ColState> st(nrhs);
+        BRI_HIP_CHECK(hipMemcpyAsync(st.data(), pl.main.st, sizeof(ColState) * nrhs, hipMemcpyDeviceToHost, s));
+        BRI_HIP_CHECK(hipStreamSynchronize(s));
+        for (int c = 0; c < nrhs; ++c) b2[c] = st[c].bnorm2;
+    }
+    passes = 0;
+    for (int pass = 0;; ++pass) {
+        bool all_ok = true;
+        for (int i = 0; i < n; ++i) shift_res[i] = 0.0;
+        for (int c0i = 0; c0i < total; c0i += chunk) {
+            const int nc = total - c0i < chunk ? total - c0i : chunk;
+            for (int k = 0; k < nc; ++k) hsig[k] = pl.sg[(c0i + k) / nrhs];
+            BRI_HIP_CHECK(hipMemcpyAsync(pl.sig_dev, hsig.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+            double2 *xc = pl.x64 + (size_t)c0i * nel;
+            // t = X x ; res = b - (X^dag t + sigma x), all FP64
+            StencilArgs a{};
+            a.g = g;
+            a.W = W64;
+            a.ncol = nc;
+            a.in = xc;
+            a.out = pl.t64;
+            a.diag = 15.0 / 8.0 - prm->rho;
+            const StencilConfig cfg = default_config(g, BRI_F64, nc);
+            int rc = stencil_launch(a, BRI_F64, false, EPI_PLAIN, cfg, s);
+            if (rc != BRI_OK) return rc;
+            StencilArgs a2 = a;
+            a2.in = pl.t64;
+            a2.out = pl.res64;
+            a2.b = in;
+            a2.b_mod = nrhs;
+            a2.xs = xc;
+            a2.sig = pl.sig_dev;
+            a2.partial = pl.partial;
+            rc = stencil_launch(a2, BRI_F64, true, EPI_RESID, cfg, s);
+            if (rc != BRI_OK) return rc;
+            part.resize((size_t)2 * nblk * nc);
+            BRI_HIP_CHECK(
+                hipMemcpyAsync(part.data(), pl.partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
+            BRI_HIP_CHECK(hipStreamSynchronize(s));
+            bool chunk_ok = true;
+            for (int k = 0; k < nc; ++k) {
+                double r2 = 0.0;
+                for (int bk = 0; bk < nblk; ++bk) r2 += part[2 * ((size_t)k * nblk + bk)];
+                const int col = c0i + k;
+                const double bb = b2[col % nrhs];
+                const double rel = bb > 0 ? sqrt(r2 / bb) : 0.0;
+                if (!isfinite(rel)) return BRI_ENAN;
+                const int sh = col / nrhs;
+                if (rel > shift_res[sh]) shift_res[sh] = rel;
+                if (rel > prm->tol) chunk_ok = false;
+            }
+            if (chunk_ok || pass >= prm->max_refine) {
+                all_ok = all_ok && chunk_ok;
+                continue;
+            }
+            all_ok = false;
+            // corrections (A + sigma_k) e_k = res_k in low precision; x64 += e
+            MsSolve &e = pl.corr;
+            e.ncol = nc;
+            for (int k = 0; k < nc; ++k) e.sigma[k] = hsig[k];
+            RunStats rs;
+            rc = ms_run(e, pl.res64, true, s, hflag, rs);
+            e.ncol = chunk;
+            if (rc != BRI_OK) return rc;
+            if (rs.status == BRI_ENAN) return BRI_ENAN;
+            hipLaunchKernelGGL(widen_kernel<float2>, dim3(4096), dim3(256), 0, s, nel * nc, (const float2 *)e.x, xc,
+                               1);
+            BRI_HIP_CHECK(hipGetLastError());
+        }
+        if (all_ok) return BRI_OK;
+        if (pass >= prm->max_refine) return BRI_ENOCONV;
+        ++passes;
+    }
 }
 
 static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *prm, const void *in,
@@ -298,147 +653,82 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     const int n = prm->kl_n;
     if (n < 1 || n > MAXS || !(prm->rho > 0.0 && prm->rho < 2.0) || !(prm->tol > 0.0) || prm->max_iter < 1)
         return BRI_EINVAL;
-    if (prm->inner != BRI_F64 || prm->max_refine != 0) return BRI_EINVAL;
-    if (g.V % 64 || nrhs < 1) return BRI_EINVAL;
-    (void)Wlo;
-    const Workspace ws = plan_workspace(g, n);
+    if (prm->inner != BRI_F64 && prm->inner != BRI_F32 && prm->inner != BRI_F32_BF16W) return BRI_EINVAL;
+    if (prm->max_refine < 0 || prm->max_refine > 100) return BRI_EINVAL;
+    if (g.V % 64 || nrhs < 1 || nrhs > 4096) return BRI_EINVAL;
+    OvPlan pl;
+    plan_overlap(pl, g, prm, nrhs, W64, Wlo, nullptr);
     if (!work) {
-        *work_bytes = ws.bytes;
+        *work_bytes = pl.bytes;
         return BRI_OK;
     }
-    if (*work_bytes < ws.bytes || !W64 || !in || !out) return BRI_EINVAL;
+    if (*work_bytes < pl.bytes || !W64 || !in || !out || (pl.mixed && !Wlo)) return BRI_EINVAL;
+    plan_overlap(pl, g, prm, nrhs, W64, Wlo, work);
     hipStream_t s = (hipStream_t)stream;
+    const size_t nel = (size_t)12 * g.V;
 
-    char *base = (char *)work;
-    MsState *st = (MsState *)(base + ws.off_state);
-    double *partial = (double *)(base + ws.off_partial);
-    const size_t vbytes = align256((size_t)12 * g.V * sizeof(double2));
-    double2 *r = (double2 *)(base + ws.off_vec);
-    double2 *p = (double2 *)(base + ws.off_vec + vbytes);
-    double2 *t = (double2 *)(base + ws.off_vec + 2 * vbytes);
-    double2 *y = (double2 *)(base + ws.off_vec + 3 * vbytes);
-    double2 *ps = (double2 *)(base + ws.off_vec + 4 * vbytes);
-    // ps is laid out with stride n = 12 V complex between shifts; vbytes is n * 16 rounded
-    // to 256 bytes and 12 V * 16 is a multiple of 256 whenever V % 64 == 0.
+    int *hflag = nullptr;
+    BRI_HIP_CHECK(hipHostMalloc((void **)&hflag, sizeof(int), hipHostMallocDefault));
+    int result = BRI_OK;
+    RunStats rs;
+    int passes = 0;
+    std::vector<double> shift_res((size_t)n, 0.0);
+    const void *yfinal = nullptr;
 
-    // coefficients, shifts ascending (sigma_0 smallest)
-    MsState hst;
-    std::memset(&hst, 0, sizeof(hst));
-    double c0, om[MAXS], sg[MAXS];
-    kl_coeffs(n, &c0, om, sg);
-    hst.nshift = n;
-    hst.c0 = c0;
-    hst.sigma0 = sg[0];
-    for (int i = 0; i < n; ++i) {
-        hst.omega[i] = om[i];
-        hst.delta[i] = sg[i] - sg[0];
+    rc = ms_run(pl.main, in, true, s, hflag, rs);
+    result = rc != BRI_OK ? rc : rs.status;
+    if (result == BRI_OK && !pl.mixed) {
+        yfinal = pl.main.y;
+    } else if ((result == BRI_OK || result == BRI_ENOCONV) && pl.mixed) {
+        hipLaunchKernelGGL(widen_kernel<float2>, dim3(4096), dim3(256), 0, s, nel * nrhs * n,
+                           (const float2 *)pl.main.x, pl.x64, 0);
+        if (hipMemcpyAsync(pl.omega_dev, pl.om, sizeof(double) * n, hipMemcpyHostToDevice, s) != hipSuccess)
+            result = BRI_EHIP;
+        else {
+            rc = refine(pl, g, prm, W64, in, s, hflag, passes, shift_res);
+            if (rc != BRI_OK) result = rc;
+        }
+        if (result == BRI_OK || result == BRI_ENOCONV) {
+            hipLaunchKernelGGL(combine_kernel, dim3(INIT_BLOCKS, nrhs), dim3(256), 0, s, nel, nrhs, n, pl.c0,
+                               (const double *)pl.omega_dev, (const double2 *)in, (const double2 *)pl.x64, pl.y64);
+            yfinal = pl.y64;
+        }
+    } else if (result == BRI_ENOCONV) {
+        yfinal = pl.main.y;  // best iterate
     }
 
-    const double m0 = -prm->rho;
-    const StencilConfig cfg = default_config(g, BRI_F64);
-    const int nblk = stencil_blocks(g);
-    const size_t nel = (size_t)12 * g.V;
-    const int vblocks = 1024;
-
-    int *hdone = nullptr;
-    BRI_HIP_CHECK(hipHostMalloc((void **)&hdone, 2 * sizeof(int), hipHostMallocDefault));
-    int result = BRI_OK;
-    MsState fin;
-    for (int rhs = 0; rhs < nrhs && result != BRI_EHIP; ++rhs) {
-        const double2 *b = (const double2 *)in + rhs * nel;
-        double2 *o = (double2 *)out + rhs * nel;
-        if (hipMemcpyAsync(st, &hst, sizeof(MsState), hipMemcpyHostToDevice, s) != hipSuccess) {
-            result = BRI_EHIP;
-            break;
-        }
-        hipLaunchKernelGGL(ms_init_kernel<double2>, dim3(vblocks), dim3(256), 0, s, nel, b, r, p, y, ps, n - 1, c0,
-                           partial);
-        hipLaunchKernelGGL(ms_scalar_init_kernel, dim3(1), dim3(RED_THREADS), 0, s, st, partial, vblocks,
-                           prm->tol);
-        if (hipGetLastError() != hipSuccess) {
-            result = BRI_EHIP;
-            break;
-        }
-
-        StencilArgs a1{};
-        a1.g = g;
-        a1.W = W64;
-        a1.in = p;
-        a1.out = t;
-        a1.diag = 15.0 / 8.0 + m0;
-        a1.partial = partial;
-        a1.done = &st->done;
-        StencilArgs a2 = a1;
-        a2.in = t;
-        a2.out = nullptr;
-        a2.p = p;
-        a2.r = r;
-        a2.alpha = &st->alpha;
-        a2.sigma0 = sg[0];
-
-        int it = 0;
-        bool finished = false;
-        while (!finished) {
-            for (int k = 0; k < CHECK_EVERY && it < prm->max_iter; ++k, ++it) {
-                int e1 = stencil_launch(a1, BRI_F64, false, EPI_NORMS, 1, cfg, s);
-                hipLaunchKernelGGL(ms_alpha_kernel, dim3(1), dim3(RED_THREADS), 0, s, st, partial, nblk);
-                int e2 = stencil_launch(a2, BRI_F64, true, EPI_CG_R, 1, cfg, s);
-                hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(RED_THREADS), 0, s, st, partial, nblk);
-                hipLaunchKernelGGL(ms_update_kernel<double2>, dim3(vblocks), dim3(256), 0, s, st, nel, r, p, y,
-                                   ps);
-                hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(1), 0, s, st);
-                if (e1 != BRI_OK || e2 != BRI_OK || hipGetLastError() != hipSuccess) {
-                    result = BRI_EHIP;
-                    break;
-                }
-            }
-            if (result == BRI_EHIP) break;
-            if (hipMemcpyAsync(hdone, &st->done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
-                result = BRI_EHIP;
-                break;
-            }
-            if (hdone[0] != 0 || it >= prm->max_iter) finished = true;
-        }
-        if (result == BRI_EHIP) break;
-
-        // out = rho (b + X y)  or  gamma5 X y
+    if (yfinal) {
+        // out = rho (b + X y)  or  gamma5 X y, in FP64
         StencilArgs a3{};
         a3.g = g;
         a3.W = W64;
-        a3.in = y;
-        a3.out = o;
-        a3.diag = 15.0 / 8.0 + m0;
-        a3.b = b;
+        a3.ncol = nrhs;
+        a3.in = yfinal;
+        a3.out = out;
+        a3.diag = 15.0 / 8.0 - prm->rho;
+        a3.b = in;
         a3.rho = prm->rho;
-        if (stencil_launch(a3, BRI_F64, false, overlap ? EPI_OV : EPI_SIGN, 1, cfg, s) != BRI_OK) {
-            result = BRI_EHIP;
-            break;
-        }
-        if (hipMemcpyAsync(&fin, st, sizeof(MsState), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            result = BRI_EHIP;
-            break;
-        }
-        if (fin.status == BRI_ENAN)
-            result = BRI_ENAN;
-        else if (fin.done == 0 && result == BRI_OK)
-            result = BRI_ENOCONV;
-        if (stats) {
-            stats->iters = fin.iter;
-            stats->refine = 0;
-            for (int i = 0; i < MAXS; ++i) {
-                stats->shift_iters[i] = i < n ? (fin.conv_iter[i] ? fin.conv_iter[i] : fin.iter) : 0;
+        rc = stencil_launch(a3, BRI_F64, false, overlap ? EPI_OV : EPI_SIGN, default_config(g, BRI_F64, nrhs), s);
+        if (rc != BRI_OK && result == BRI_OK) result = rc;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) result = BRI_EHIP;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iters = rs.iters;
+        stats->refine = passes;
+        if (!rs.fin.empty()) {
+            const ColState &fin = rs.fin.back();
+            for (int i = 0; i < n; ++i) {
+                stats->shift_iters[i] = fin.conv_iter[i] ? fin.conv_iter[i] : fin.iter;
                 stats->rel_resid[i] =
-                    i < n ? (fin.conv_iter[i] ? fin.conv_res[i]
-                                              : fabs(fin.zeta[i]) * sqrt(fin.rr / (fin.bnorm2 > 0 ? fin.bnorm2 : 1)))
-                          : 0.0;
+                    pl.mixed ? shift_res[i]
+                             : (fin.conv_iter[i] ? fin.conv_res[i]
+                                                 : fabs(fin.zeta[i]) * sqrt(fin.rr / (fin.bnorm2 > 0 ? fin.bnorm2 : 1)));
             }
         }
-    }
-    (void)hipHostFree(hdone);
-    if (stats)
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    (void)hipHostFree(hflag);
     return result;
 }
 

@@ -1,17 +1,37 @@
-// Internal interface of the Brillouin stencil kernels.
+// Internal interface of the Brillouin stencil kernels and of the per-column
+// state the multi-shift solver shares with their fused epilogues.
 #pragma once
 
 #include "common.hpp"
 
 namespace bri {
 
-// fused epilogues of the stencil kernel
+constexpr int MAXS = BRI_MAX_SHIFTS;
+
+// FP64 scalars of one column (one right-hand side) of a batched multi-shift CG.
+struct ColState {
+    double rr, bnorm2, tol2;
+    double alpha, alpha_old, beta, beta_old;
+    double sigma0;
+    int iter, done, status, nshift;
+    double c0;
+    double delta[MAXS], omega[MAXS];
+    double zeta[MAXS], zeta_old[MAXS], zeta_new[MAXS];
+    double alpha_s[MAXS], beta_s[MAXS];
+    int active[MAXS];       // shift still iterating
+    int upd_x[MAXS];        // shift takes its alpha^sigma step in this iteration
+    int conv_iter[MAXS];
+    double conv_res[MAXS];  // |zeta r| / |b| when the shift stopped
+};
+
+// fused epilogues of the stencil kernels (per column c)
 enum EpiMode {
     EPI_PLAIN = 0,  // out = D in
     EPI_NORMS = 1,  // out = D in; partial sums of |out|^2 and |in|^2
-    EPI_CG_R = 2,   // r -= alpha (D in + sigma0 p); partial sums of |r|^2
+    EPI_CG_R = 2,   // r -= alpha_c (D in + sigma0_c p); partial sums of |r|^2
     EPI_OV = 3,     // out = rho (b + D in)
-    EPI_SIGN = 4    // out = gamma5 D in
+    EPI_SIGN = 4,   // out = gamma5 D in
+    EPI_RESID = 5   // out = b_{c mod b_mod} - (D in + sig_c xs); partial sums of |out|^2
 };
 
 struct StencilArgs {
@@ -19,31 +39,34 @@ struct StencilArgs {
     int tile[4];  // 64-site tile extents
     int nb[4];    // tiles per axis
     int xcd_remap;
+    int ncol;     // columns (right-hand sides); column c lives at offset c * 12 V
     const void *W;
     const void *in;
     void *out;
     double diag;  // 15/8 + m0
     // epilogue operands
-    double *partial;       // EPI_NORMS / EPI_CG_R: 2 doubles per block
-    const void *p;         // EPI_CG_R
-    void *r;               // EPI_CG_R
-    const double *alpha;   // EPI_CG_R (device scalar)
-    double sigma0;         // EPI_CG_R
-    const void *b;         // EPI_OV
-    double rho;            // EPI_OV
-    const int *done;       // solver loop: skip the launch body once converged
+    double *partial;        // EPI_NORMS / EPI_CG_R / EPI_RESID: [ncol][nblk][2]
+    const void *p;          // EPI_CG_R
+    void *r;                // EPI_CG_R
+    const ColState *st;     // EPI_NORMS / EPI_CG_R: alpha, sigma0 and the done flag per column
+    const void *b;          // EPI_OV / EPI_RESID
+    int b_mod;              // EPI_RESID: column c uses b column (c % b_mod)
+    const void *xs;         // EPI_RESID
+    const double *sig;      // EPI_RESID: shift per column
+    double rho;             // EPI_OV
 };
 
 struct StencilConfig {
     int tile[4];    // 0 = automatic
-    int nsplit;     // waves per 64-site tile (1, 2, 4)
+    int nsplit;     // 1-RHS kernel: waves per 64-site tile (1, 2, 4)
+    int rpt;        // multi-RHS kernel: right-hand sides per thread (0 = use the 1-RHS kernel)
     int xcd_remap;  // 1 = give each XCD a contiguous range of tiles
 };
 
 int geom_check(const bri_geom *geom, Geom *g);
 int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]);
-StencilConfig default_config(const Geom &g, int prec);
-int stencil_launch(StencilArgs a, int prec, bool dag, int mode, int nrhs, const StencilConfig &cfg, hipStream_t st);
+StencilConfig default_config(const Geom &g, int prec, int ncol);
+int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilConfig &cfg, hipStream_t st);
 
 inline int stencil_blocks(const Geom &g) { return g.V / 64; }
 

@@ -1,0 +1,204 @@
+// Device helpers shared by the Brillouin stencil kernels: complex axpy forms,
+// the spin weights S_d = a + sum_mu c_mu gamma_mu, the colour transport
+// W psi / W^dag psi, and site / neighbour addressing.
+//
+// Gamma matrices, chiral basis: gamma_k = [[0, -i s_k], [i s_k, 0]],
+// gamma_4 = [[0, 1], [1, 0]].  Acting on the four spin components chi_s:
+//   gamma_1 chi = (-i chi3, -i chi2,  i chi1,  i chi0)
+//   gamma_2 chi = (  -chi3,    chi2,    chi1,   -chi0)
+//   gamma_3 chi = (-i chi2,  i chi3,  i chi0, -i chi1)
+//   gamma_4 chi = (   chi2,    chi3,    chi0,    chi1)
+#pragma once
+
+#include "common.hpp"
+
+namespace bri {
+
+template <typename C, typename R>
+__device__ __forceinline__ void axpy_c(C &acc, R a, const C &v) {
+    acc.x = fma(a, v.x, acc.x);
+    acc.y = fma(a, v.y, acc.y);
+}
+
+// acc += i * a * v
+template <typename C, typename R>
+__device__ __forceinline__ void axpy_ic(C &acc, R a, const C &v) {
+    acc.x = fma(-a, v.y, acc.x);
+    acc.y = fma(a, v.x, acc.y);
+}
+
+// acc[s][c] += (a + sum_mu cmu gamma_mu) chi[s][c];  branches are wave-uniform.
+template <typename C, typename R>
+__device__ __forceinline__ void spin_accumulate(C (&acc)[4][3], const C (&chi)[4][3], R a, R c0, R c1, R c2, R c3) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) axpy_c(acc[s][c], a, chi[s][c]);
+    }
+    if (c0 != (R)0) {  // gamma_1 (x)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            axpy_ic(acc[0][c], -c0, chi[3][c]);
+            axpy_ic(acc[1][c], -c0, chi[2][c]);
+            axpy_ic(acc[2][c], c0, chi[1][c]);
+            axpy_ic(acc[3][c], c0, chi[0][c]);
+        }
+    }
+    if (c1 != (R)0) {  // gamma_2 (y)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            axpy_c(acc[0][c], -c1, chi[3][c]);
+            axpy_c(acc[1][c], c1, chi[2][c]);
+            axpy_c(acc[2][c], c1, chi[1][c]);
+            axpy_c(acc[3][c], -c1, chi[0][c]);
+        }
+    }
+    if (c2 != (R)0) {  // gamma_3 (z)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            axpy_ic(acc[0][c], -c2, chi[2][c]);
+            axpy_ic(acc[1][c], c2, chi[3][c]);
+            axpy_ic(acc[2][c], c2, chi[0][c]);
+            axpy_ic(acc[3][c], -c2, chi[1][c]);
+        }
+    }
+    if (c3 != (R)0) {  // gamma_4 (t)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            axpy_c(acc[0][c], c3, chi[2][c]);
+            axpy_c(acc[1][c], c3, chi[3][c]);
+            axpy_c(acc[2][c], c3, chi[0][c]);
+            axpy_c(acc[3][c], c3, chi[1][c]);
+        }
+    }
+}
+
+template <class LS, bool ADJ>
+__device__ __forceinline__ void transport(typename Cx<typename LS::R>::T (&chi)[4][3],
+                                          const typename LS::store_t *__restrict__ Wj, unsigned ws,
+                                          const typename Cx<typename LS::R>::T *__restrict__ ps, unsigned ys,
+                                          unsigned V) {
+    using R = typename LS::R;
+    using C = typename Cx<R>::T;
+    C w[3][3], p[4][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) w[a][b] = LS::load(Wj, (size_t)(a * 3 + b) * V + ws);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) p[s][b] = ps[(size_t)(s * 3 + b) * V + ys];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C v = cmake<C>((R)0, (R)0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (ADJ)
+                    cmac_conj(v, w[b][a], p[s][b]);
+                else
+                    cmac(v, w[a][b], p[s][b]);
+            }
+            chi[s][a] = v;
+        }
+}
+
+__device__ __forceinline__ unsigned sel3(int d, unsigned m, unsigned z, unsigned p) {
+    return d < 0 ? m : (d > 0 ? p : z);
+}
+
+
+// the nine entries of link slab Wj at site ws, converted to the compute type
+template <class LS>
+__device__ __forceinline__ void load_link(typename Cx<typename LS::R>::T (&w)[3][3],
+                                          const typename LS::store_t *__restrict__ Wj, unsigned ws, unsigned V) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) w[a][b] = LS::load(Wj, (size_t)(a * 3 + b) * V + ws);
+}
+
+// chi = w psi(ys) (ADJ: w^dag psi(ys)) with the link already in registers
+template <typename C, typename R, bool ADJ>
+__device__ __forceinline__ void transport_reg(C (&chi)[4][3], const C (&w)[3][3], const C *__restrict__ ps,
+                                              unsigned ys, unsigned V) {
+    C p[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) p[s][b] = ps[(size_t)(s * 3 + b) * V + ys];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C v = cmake<C>((R)0, (R)0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (ADJ)
+                    cmac_conj(v, w[b][a], p[s][b]);
+                else
+                    cmac(v, w[a][b], p[s][b]);
+            }
+            chi[s][a] = v;
+        }
+}
+
+// Site of lane `lane` in tile `blk` (after the optional XCD-aware reordering of
+// tiles) and the wrapped neighbour offsets om/o0/op per axis, premultiplied by
+// the axis stride.  Returns the site index.
+__device__ __forceinline__ unsigned tile_site(const Geom &g, const int tile[4], const int nb[4], int blk, int lane,
+                                              unsigned om[4], unsigned o0[4], unsigned op[4]) {
+    int t = blk;
+    int c[4];
+    int l = lane;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int bm = t % nb[mu];
+        t /= nb[mu];
+        c[mu] = bm * tile[mu] + l % tile[mu];
+        l /= tile[mu];
+    }
+    unsigned stride = 1;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int Lm = g.L[mu];
+        const int cm = c[mu] == 0 ? Lm - 1 : c[mu] - 1;
+        const int cp = c[mu] == Lm - 1 ? 0 : c[mu] + 1;
+        om[mu] = (unsigned)cm * stride;
+        o0[mu] = (unsigned)c[mu] * stride;
+        op[mu] = (unsigned)cp * stride;
+        stride *= (unsigned)Lm;
+    }
+    return o0[0] + o0[1] + o0[2] + o0[3];
+}
+
+__device__ __forceinline__ int xcd_order(int blk, int nblk, int remap) {
+    return (remap && (nblk & 7) == 0) ? (blk & 7) * (nblk >> 3) + (blk >> 3) : blk;
+}
+
+// neighbour x + s*d of a stored displacement index j (s = +1 or -1)
+__device__ __forceinline__ unsigned neighbour(int j, int s, const unsigned om[4], const unsigned o0[4],
+                                              const unsigned op[4]) {
+    const int d0 = s * (j % 3 - 1), d1 = s * ((j / 3) % 3 - 1), d2 = s * ((j / 9) % 3 - 1), d3 = s * (j / 27 - 1);
+    return sel3(d0, om[0], o0[0], op[0]) + sel3(d1, om[1], o0[1], op[1]) + sel3(d2, om[2], o0[2], op[2]) +
+           sel3(d3, om[3], o0[3], op[3]);
+}
+
+// weights of stored displacement j: a_k and c_mu = c_k d_mu (negated for the adjoint)
+template <typename R, bool DAG> struct DirW {
+    R a, c0, c1, c2, c3;
+    __device__ __forceinline__ explicit DirW(int j) {
+        const int d0 = j % 3 - 1, d1 = (j / 3) % 3 - 1, d2 = (j / 9) % 3 - 1, d3 = j / 27 - 1;
+        const int k = (d0 != 0) + (d1 != 0) + (d2 != 0) + (d3 != 0);
+        a = (R)lap_weight(k);
+        const R ck = (R)(DAG ? -iso_weight(k) : iso_weight(k));
+        c0 = ck * (R)d0;
+        c1 = ck * (R)d1;
+        c2 = ck * (R)d2;
+        c3 = ck * (R)d3;
+    }
+};
+
+}  // namespace bri

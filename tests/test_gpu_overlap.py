@@ -20,9 +20,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
-def _op(L, U, n, tol=1e-12, max_iter=2000, tbc=0):
+def _op(L, U, n, tol=1e-12, max_iter=2000, tbc=0, nrhs=1):
     W = bri.build_links(L, bri.links_to_device(U), bri.F64, tbc=tbc)
-    return bri.OverlapOp(L, W, kl_n=n, rho=1.0, tol=tol, max_iter=max_iter, tbc=tbc)
+    return bri.OverlapOp(L, W, kl_n=n, rho=1.0, tol=tol, max_iter=max_iter, tbc=tbc, nrhs=nrhs)
 
 
 @pytest.mark.parametrize("kind", ["unit", "cfg1"])
@@ -48,7 +48,7 @@ def test_overlap_against_dense_eigendecomposition():
     L = (4, 4, 4, 4)
     U, Wo = field(L, "cfg1")
     dov = odense.DenseOverlap(oracle.dense_matrix(L, Wo, -1.0), 256, 1.0)
-    op = _op(L, U, 8)
+    op = _op(L, U, 8, nrhs=2)
     g = synth.gaussian_source(L, synth.SOURCE_SEED_BASE + 1, nrhs=2)
     out, _ = op.apply(bri.spinor_to_device(g))
     got = bri.spinor_to_host(out)
