@@ -145,6 +145,44 @@ int ov_sign_apply(const bri_geom *geom, const void *W64, const void *Wlo, const 
 int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params, const void *in,
              void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream);
 
+/*
+ * Stencil launch configuration and autotuner.  A configuration picks the
+ * 64-site tile (tile_x * tile_y * tile_z * tile_t = 64, each dividing its
+ * lattice extent; all zero = automatic), the traversal (col_z > 0: tiles of
+ * tile_x x tile_y x 1 x 1 walked z-fastest then t inside columns of col_z
+ * z-planes, so that stencil neighbours run together on one XCD; col_z = 0:
+ * lexicographic tiles), the work split (rpt = 0: one right-hand side per
+ * block row with nsplit = 1, 2 or 4 waves sharing the 80 displacements;
+ * rpt = 1..4: rpt right-hand sides per thread) and xcd = 1 to give each XCD a
+ * contiguous range of tiles.
+ */
+typedef struct {
+    int tile_x, tile_y, tile_z, tile_t;
+    int col_z;
+    int nsplit;
+    int rpt;
+    int xcd;
+} bri_stencil_cfg;
+
+/* bri_stencil_time -- average time of `reps` back-to-back bri_apply launches
+ * (after one warm-up) with configuration cfg (NULL: the current default), in
+ * microseconds, measured with HIP events on `stream` (synchronises it).
+ * in / out as bri_apply; out is overwritten.  BRI_EINVAL if cfg does not fit. */
+int bri_stencil_time(const bri_geom *geom, const void *W, int prec, const void *in, void *out, int nrhs,
+                     const bri_stencil_cfg *cfg, int reps, double *us_per_launch, void *stream);
+
+/* bri_autotune -- times every candidate configuration for (geom, prec, nrhs)
+ * as bri_stencil_time does and installs the fastest in a process-wide table
+ * used by bri_apply, bri_apply_dag and the overlap solvers for that lattice,
+ * precision and column count.  best / best_us may be NULL. */
+int bri_autotune(const bri_geom *geom, const void *W, int prec, const void *in, void *out, int nrhs, int reps,
+                 bri_stencil_cfg *best, double *best_us, void *stream);
+
+/* bri_set_stencil_cfg -- installs cfg for (geom, prec, nrhs); cfg = NULL removes
+ * the entry.  bri_get_stencil_cfg -- the configuration a launch would use. */
+int bri_set_stencil_cfg(const bri_geom *geom, int prec, int nrhs, const bri_stencil_cfg *cfg);
+int bri_get_stencil_cfg(const bri_geom *geom, int prec, int nrhs, bri_stencil_cfg *cfg);
+
 /* Kenney-Laub coefficients c0, omega[n], sigma[n] of f_{n,n} (eq. (KLnn_parfrac)),
  * computed in double precision on the host; sigma ascending. */
 int bri_kl_coeffs(int n, double *c0, double *omega, double *sigma);

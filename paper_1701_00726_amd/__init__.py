@@ -62,6 +62,24 @@ class _OvStats(ctypes.Structure):
     ]
 
 
+class StencilCfg(ctypes.Structure):
+    """Launch configuration of the stencil kernels (see include/brillouin.h)."""
+
+    _fields_ = [
+        ("tile_x", ctypes.c_int),
+        ("tile_y", ctypes.c_int),
+        ("tile_z", ctypes.c_int),
+        ("tile_t", ctypes.c_int),
+        ("col_z", ctypes.c_int),
+        ("nsplit", ctypes.c_int),
+        ("rpt", ctypes.c_int),
+        ("xcd", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 @dataclass
 class OvStats:
     iters: int
@@ -96,13 +114,29 @@ def load():
             lib.ov_sign_apply.argtypes = ovargs
             lib.ov_apply.argtypes = ovargs
             lib.bri_kl_coeffs.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
-            for fn in ("bri_build_links", "bri_apply", "bri_apply_dag", "ov_sign_apply", "ov_apply", "bri_kl_coeffs"):
+            SC = ctypes.POINTER(StencilCfg)
+            lib.bri_stencil_time.argtypes = [G, P, I, P, P, I, SC, I, ctypes.POINTER(D), P]
+            lib.bri_autotune.argtypes = [G, P, I, P, P, I, I, SC, ctypes.POINTER(D), P]
+            lib.bri_set_stencil_cfg.argtypes = [G, I, I, SC]
+            lib.bri_get_stencil_cfg.argtypes = [G, I, I, SC]
+            for fn in EXPORTS:
                 getattr(lib, fn).restype = I
             _lib = lib
     return _lib
 
 
-EXPORTS = ("bri_build_links", "bri_apply", "bri_apply_dag", "ov_sign_apply", "ov_apply", "bri_kl_coeffs")
+EXPORTS = (
+    "bri_build_links",
+    "bri_apply",
+    "bri_apply_dag",
+    "ov_sign_apply",
+    "ov_apply",
+    "bri_kl_coeffs",
+    "bri_stencil_time",
+    "bri_autotune",
+    "bri_set_stencil_cfg",
+    "bri_get_stencil_cfg",
+)
 
 
 # ------------------------------------------------------------------ helpers
@@ -295,3 +329,55 @@ def kl_coeffs(n):
     sg = (ctypes.c_double * n)()
     _check("bri_kl_coeffs", load().bri_kl_coeffs(int(n), ctypes.byref(c0), om, sg))
     return c0.value, list(om), list(sg)
+
+
+# ------------------------------------------------------------------ autotuner
+
+
+def _tune_check(L, W, prec, psi):
+    V = int(np.prod(L))
+    torch = _torch()
+    if psi.dim() != 4 or tuple(psi.shape[1:]) != (4, 3, V) or psi.dtype != spinor_dtype(prec):
+        raise ValueError("psi must be (nrhs, 4, 3, V) of the spinor dtype of prec")
+    if W.dtype != link_dtype(prec) or tuple(W.shape) != (40, 3, 3, V):
+        raise ValueError("W must be (40, 3, 3, V) of the link dtype of prec")
+    return torch.empty_like(psi)
+
+
+def stencil_time(L, W, prec, psi, cfg=None, reps=10, stream=None):
+    """Microseconds per bri_apply launch with configuration cfg (None: current default)."""
+    out = _tune_check(L, W, prec, psi)
+    us = ctypes.c_double()
+    g = _geom(L)
+    _check("bri_stencil_time", load().bri_stencil_time(ctypes.byref(g), _dptr(W), int(prec), _dptr(psi), _dptr(out),
+                                                       int(psi.shape[0]), None if cfg is None else ctypes.byref(cfg),
+                                                       int(reps), ctypes.byref(us), _stream(stream)))
+    return us.value
+
+
+def autotune(L, W, prec, psi, reps=5, stream=None):
+    """Time the candidate stencil configurations for this lattice, precision and
+    number of right-hand sides; the fastest is installed for later calls.
+    Returns (StencilCfg, microseconds per launch)."""
+    out = _tune_check(L, W, prec, psi)
+    best = StencilCfg()
+    us = ctypes.c_double()
+    g = _geom(L)
+    _check("bri_autotune", load().bri_autotune(ctypes.byref(g), _dptr(W), int(prec), _dptr(psi), _dptr(out),
+                                               int(psi.shape[0]), int(reps), ctypes.byref(best), ctypes.byref(us),
+                                               _stream(stream)))
+    return best, us.value
+
+
+def get_stencil_cfg(L, prec, nrhs):
+    cfg = StencilCfg()
+    g = _geom(L)
+    _check("bri_get_stencil_cfg", load().bri_get_stencil_cfg(ctypes.byref(g), int(prec), int(nrhs), ctypes.byref(cfg)))
+    return cfg
+
+
+def set_stencil_cfg(L, prec, nrhs, cfg):
+    """Install cfg (a StencilCfg) for (L, prec, nrhs); None removes the entry."""
+    g = _geom(L)
+    _check("bri_set_stencil_cfg", load().bri_set_stencil_cfg(ctypes.byref(g), int(prec), int(nrhs),
+                                                             None if cfg is None else ctypes.byref(cfg)))

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, blk, lane, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
 
     const C *__restrict__ in = (const C *)a.in + (size_t)col * 12 * V;
     const typename LS::store_t *__restrict__ W = (const typename LS::store_t *)a.W;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void stencil_mrhs_kernel(StencilArgs a) {
 
     const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, blk, lane, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
     const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
     const typename LS::store_t *__restrict__ W = (const typename LS::store_t *)a.W;
 
@@ -322,9 +322,23 @@ static hipError_t launch_prec(const StencilArgs &a, int mode, const StencilConfi
     }
 }
 
-// A 64-site tile that divides the lattice: x first (coalescing), then y, z, t.
+// A 64-site tile that divides the lattice.  Column traversal: tile
+// tile[0] x tile[1] x 1 x 1 with colz | Lz.  Otherwise x first (coalescing),
+// then y, z, t.
 int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
     if (g.V % 64) return BRI_EINVAL;
+    if (cfg.colz > 0) {
+        const int tx = cfg.tile[0], ty = cfg.tile[1];
+        if (tx < 1 || ty < 1 || tx * ty != 64 || g.L[0] % tx || g.L[1] % ty || g.L[2] % cfg.colz) return BRI_EINVAL;
+        tile[0] = tx;
+        tile[1] = ty;
+        tile[2] = tile[3] = 1;
+        nb[0] = g.L[0] / tx;
+        nb[1] = g.L[1] / ty;
+        nb[2] = g.L[2];
+        nb[3] = g.L[3];
+        return BRI_OK;
+    }
     if (cfg.tile[0] > 0) {
         int prod = 1;
         for (int mu = 0; mu < 4; ++mu) {
@@ -359,6 +373,7 @@ int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilCon
     if (a.ncol < 1 || a.ncol > 65535 * 4) return BRI_EINVAL;
     int rc = plan_tile(a.g, cfg, a.tile, a.nb);
     if (rc != BRI_OK) return rc;
+    a.colz = cfg.colz;
     a.xcd_remap = cfg.xcd_remap;
     if (cfg.rpt == 0 && a.ncol > 65535) return BRI_EINVAL;
     hipError_t e;
@@ -373,12 +388,31 @@ int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilCon
     return e == hipSuccess ? BRI_OK : (e == hipErrorInvalidValue ? BRI_EINVAL : BRI_EHIP);
 }
 
+// Column traversal when the lattice allows an 8 x 8 (or 16 x 4) tile and a
+// column depth of 8 (or 4) z-planes; lexicographic tiles otherwise.
+static void default_traversal(const Geom &g, StencilConfig &c) {
+    for (int mu = 0; mu < 4; ++mu) c.tile[mu] = 0;
+    c.colz = 0;
+    const int tx_opts[3][2] = {{8, 8}, {16, 4}, {4, 16}};
+    for (const auto &t : tx_opts) {
+        if (g.L[0] % t[0] || g.L[1] % t[1]) continue;
+        for (int cz : {8, 4, 2}) {
+            if (g.L[2] % cz) continue;
+            c.tile[0] = t[0];
+            c.tile[1] = t[1];
+            c.colz = cz;
+            return;
+        }
+    }
+}
+
 StencilConfig default_config(const Geom &g, int prec, int ncol) {
     StencilConfig c;
-    for (int mu = 0; mu < 4; ++mu) c.tile[mu] = 0;
+    if (tuned_config(g, prec, ncol, &c)) return c;
+    default_traversal(g, c);
     c.xcd_remap = 1;
     if (ncol >= 4) {
-        // link loads amortised over R right-hand sides per thread; FP64 keeps R = 2 for registers
+        // link loads amortised over R right-hand sides per thread
         c.nsplit = 1;
         c.rpt = prec == BRI_F64 ? 2 : 4;
         if (ncol % c.rpt) c.rpt = (ncol % 3 == 0) ? 3 : (prec == BRI_F64 ? 1 : 2);

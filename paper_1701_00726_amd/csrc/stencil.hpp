@@ -38,6 +38,7 @@ struct StencilArgs {
     Geom g;
     int tile[4];  // 64-site tile extents
     int nb[4];    // tiles per axis
+    int colz;     // column traversal depth in z (0 = lexicographic tiles)
     int xcd_remap;
     int ncol;     // columns (right-hand sides); column c lives at offset c * 12 V
     const void *W;
@@ -58,10 +59,15 @@ struct StencilArgs {
 
 struct StencilConfig {
     int tile[4];    // 0 = automatic
+    int colz;       // column traversal: z-planes per column (0 = lexicographic tiles)
     int nsplit;     // 1-RHS kernel: waves per 64-site tile (1, 2, 4)
     int rpt;        // multi-RHS kernel: right-hand sides per thread (0 = use the 1-RHS kernel)
     int xcd_remap;  // 1 = give each XCD a contiguous range of tiles
 };
+
+// process-wide table of tuned configurations, keyed by lattice, precision and
+// number of columns; default_config consults it first
+bool tuned_config(const Geom &g, int prec, int ncol, StencilConfig *out);
 
 int geom_check(const bri_geom *geom, Geom *g);
 int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]);

@@ -145,20 +145,38 @@ __device__ __forceinline__ void transport_reg(C (&chi)[4][3], const C (&w)[3][3]
         }
 }
 
-// Site of lane `lane` in tile `blk` (after the optional XCD-aware reordering of
-// tiles) and the wrapped neighbour offsets om/o0/op per axis, premultiplied by
-// the axis stride.  Returns the site index.
-__device__ __forceinline__ unsigned tile_site(const Geom &g, const int tile[4], const int nb[4], int blk, int lane,
-                                              unsigned om[4], unsigned o0[4], unsigned op[4]) {
-    int t = blk;
+// Site of lane `lane` in (logical) tile `blk`, and the wrapped neighbour
+// offsets om/o0/op per axis, premultiplied by the axis stride.  Two traversals:
+//   colz == 0: tiles of extents tile[4] in lexicographic order (x fastest);
+//   colz  > 0: tiles of tile[0] x tile[1] x 1 x 1 sites grouped in columns of
+//              colz z-planes and all t; inside a column the tiles run z fastest,
+//              then t, and the columns run x, y, z.  Consecutive tiles (which an
+//              XCD runs together) then hold every stencil neighbour of each other
+//              except across the column walls, so re-read links and spinors stay
+//              in that XCD's L2.
+__device__ __forceinline__ unsigned tile_site(const Geom &g, const int tile[4], const int nb[4], int colz, int blk,
+                                              int lane, unsigned om[4], unsigned o0[4], unsigned op[4]) {
     int c[4];
-    int l = lane;
+    if (colz > 0) {
+        const int per_col = colz * g.L[3];
+        const int col = blk / per_col, rem = blk - col * per_col;
+        const int zt = rem % colz, tt = rem / colz;
+        const int cx = col % nb[0], r2 = col / nb[0];
+        const int cy = r2 % nb[1], cz = r2 / nb[1];
+        c[0] = cx * tile[0] + lane % tile[0];
+        c[1] = cy * tile[1] + lane / tile[0];
+        c[2] = cz * colz + zt;
+        c[3] = tt;
+    } else {
+        int t = blk;
+        int l = lane;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const int bm = t % nb[mu];
-        t /= nb[mu];
-        c[mu] = bm * tile[mu] + l % tile[mu];
-        l /= tile[mu];
+        for (int mu = 0; mu < 4; ++mu) {
+            const int bm = t % nb[mu];
+            t /= nb[mu];
+            c[mu] = bm * tile[mu] + l % tile[mu];
+            l /= tile[mu];
+        }
     }
     unsigned stride = 1;
 #pragma unroll

@@ -175,3 +175,112 @@ def gaussian_source(L, seed: int, nrhs: int = 1, normalize: bool = True) -> np.n
     if normalize:
         psi /= np.linalg.norm(psi.reshape(nrhs, -1), axis=1)[:, None, None, None]
     return psi
+
+
+# --------------------------------------------------------------- torch variant
+# The same link recipe evaluated with torch on any device, for lattices where
+# numpy would take minutes.  The Gaussian algebra elements are drawn by numpy
+# with the same seed as `random_links`, so both variants agree to rounding.
+
+
+def _t_dag(M):
+    return M.conj().transpose(-1, -2).contiguous()
+
+
+def _t_expi_hermitian(A, eps: float, squarings: int = 6, order: int = 12):
+    """exp(i eps A) by a Taylor series of i eps A / 2^s followed by s squarings
+    (matrix products only; |i eps A / 2^s| stays below 0.1 for these inputs)."""
+    import torch
+
+    X = (1j * eps / (1 << squarings)) * A
+    eye = torch.eye(3, dtype=A.dtype, device=A.device).expand_as(A)
+    E = eye.clone()
+    term = eye.clone()
+    for k in range(1, order + 1):
+        term = (term @ X) / k
+        E = E + term
+    for _ in range(squarings):
+        E = E @ E
+    return E
+
+
+def _t_inv3(M):
+    """Inverse of a batch of 3x3 matrices by the adjugate."""
+    import torch
+
+    a = M
+    c00 = a[..., 1, 1] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 1]
+    c01 = a[..., 1, 2] * a[..., 2, 0] - a[..., 1, 0] * a[..., 2, 2]
+    c02 = a[..., 1, 0] * a[..., 2, 1] - a[..., 1, 1] * a[..., 2, 0]
+    c10 = a[..., 0, 2] * a[..., 2, 1] - a[..., 0, 1] * a[..., 2, 2]
+    c11 = a[..., 0, 0] * a[..., 2, 2] - a[..., 0, 2] * a[..., 2, 0]
+    c12 = a[..., 0, 1] * a[..., 2, 0] - a[..., 0, 0] * a[..., 2, 1]
+    c20 = a[..., 0, 1] * a[..., 1, 2] - a[..., 0, 2] * a[..., 1, 1]
+    c21 = a[..., 0, 2] * a[..., 1, 0] - a[..., 0, 0] * a[..., 1, 2]
+    c22 = a[..., 0, 0] * a[..., 1, 1] - a[..., 0, 1] * a[..., 1, 0]
+    det = a[..., 0, 0] * c00 + a[..., 0, 1] * c01 + a[..., 0, 2] * c02
+    adj = torch.stack([torch.stack([c00, c10, c20], -1), torch.stack([c01, c11, c21], -1),
+                       torch.stack([c02, c12, c22], -1)], -2)
+    return adj / det.unsqueeze(-1).unsqueeze(-1), det
+
+
+def _t_project_su3(M, iters: int = 12):
+    """Polar unitary factor by the Newton iteration X <- (X + X^{-dag}) / 2 (matrix
+    products and 3x3 inverses only), then divided by the cube root of its det."""
+    import torch
+
+    scale = torch.linalg.vector_norm(M, dim=(-2, -1)) / np.sqrt(3.0)
+    X = M / scale.unsqueeze(-1).unsqueeze(-1)
+    for _ in range(iters):
+        Xi, _ = _t_inv3(X)
+        X = 0.5 * (X + _t_dag(Xi))
+    _, det = _t_inv3(X)
+    return X / torch.exp(1j * torch.angle(det) / 3).unsqueeze(-1).unsqueeze(-1)
+
+
+def _t_shift(field, L, mu: int, step: int):
+    import torch
+
+    Lx, Ly, Lz, Lt = L
+    f = field.reshape((Lt, Lz, Ly, Lx) + tuple(field.shape[1:]))
+    return torch.roll(f, shifts=-step, dims=3 - mu).reshape(field.shape)
+
+
+def smeared_links_torch(L, eps: float, seed: int, ape_alpha: float = 0.6, ape_steps: int = 3, device="cuda",
+                        chunk: int = 1 << 20):
+    """`smeared_links` evaluated with torch on `device`; returns a (4, V, 3, 3)
+    complex128 tensor on that device."""
+    import torch
+
+    V = volume(L)
+    rng = np.random.default_rng(seed)
+    lam = torch.from_numpy(gell_mann() / 2).to(device)
+    U = torch.empty((4 * V, 3, 3), dtype=torch.complex128, device=device)
+    for s in range(0, 4 * V, chunk):
+        n = min(chunk, 4 * V - s)
+        xi = torch.from_numpy(rng.standard_normal((n, 8))).to(device=device, dtype=torch.complex128)
+        A = torch.einsum("na,aij->nij", xi, lam)
+        U[s:s + n] = _t_expi_hermitian(A, eps)
+    U = U.reshape(4, V, 3, 3)
+    for _ in range(ape_steps):
+        new = torch.empty_like(U)
+        for mu in range(4):
+            staple = torch.zeros_like(U[mu])
+            for nu in range(4):
+                if nu == mu:
+                    continue
+                Unu = U[nu]
+                Umu_xnu = _t_shift(U[mu], L, nu, +1)
+                Unu_xmu = _t_shift(Unu, L, mu, +1)
+                staple += Unu @ Umu_xnu @ _t_dag(Unu_xmu)
+                Unu_m = _t_shift(Unu, L, nu, -1)
+                Umu_m = _t_shift(U[mu], L, nu, -1)
+                Unu_mp = _t_shift(Unu_xmu, L, nu, -1)
+                staple += _t_dag(Unu_m) @ Umu_m @ Unu_mp
+            M = (1 - ape_alpha) * U[mu] + (ape_alpha / 6) * staple
+            out = torch.empty_like(M)
+            for s in range(0, V, chunk):
+                out[s:s + chunk] = _t_project_su3(M[s:s + chunk])
+            new[mu] = out
+        U = new
+    return U
