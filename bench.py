@@ -1,25 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the Brillouin-kernel overlap hot path on one MI355X.
 
-Step = one pass of the whole hot path over one synthetic batch:
-  bri_build_links (U -> FP64 off-axis links) + ov_apply (multi-shift CG for the
-  Kenney-Laub [16/16] rational, 2 stencil applies per iteration, final apply)
-on a 16^4 lattice with smeared links (exp(0.5 i A), 3 APE steps at alpha 0.6)
-and one normalised Gaussian source, FP64, rho = 1, CG tolerance 1e-12.
+Step (the timed unit behind `value`) = one pass of the whole hot path over one
+synthetic batch: bri_build_links (U -> FP64 off-axis links) + ov_apply (FP64
+multi-shift CG for the Kenney-Laub [16/16] rational, two stencil applies per
+iteration, final apply) on a 16^4 lattice with smeared links (exp(0.5 i A),
+3 APE steps at alpha 0.6), one normalised Gaussian source, rho = 1, CG
+tolerance 1e-12 per shift.  This is the plain FP64 single-RHS GPU path.
 
-value      = overlap applies (right-hand sides) per second over the timed steps
-roofline   = the dominant kernel, the FP64 stencil bri_apply, timed live with
-             HIP events on the library's stream: algorithmic bytes per launch
-             (6144 B/site: 40 stored links + spinor in + spinor out) / average
-             launch time, against the 8 TB/s HBM peak
-cpu_baseline = the FP64 CPU oracle on a bounded sample (see `sample`)
+value        overlap applies (right-hand sides) per second of that step
+roofline     dominant kernel, the FP64 stencil bri_apply, timed live with HIP
+             events on the library's stream: algorithmic bytes per launch
+             (6144 B/site: the 40 stored links, spinor in and out) / average
+             launch time, against the 8 TB/s HBM peak; `traffic` from the
+             committed rocprofv3 counter summary when the kernel sources match
+cpu_baseline the FP64 CPU oracle on a bounded sample (see `sample`)
+extra        the same apply batched over the 12 spin-colour point sources and
+             with mixed precision (FP32 / bfloat16-link inner solve, FP64
+             refinement), each with its error against the FP64 result
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+       python bench.py --stencil-only     (copy calibration + stencil launches, for counters)
 """
 
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -39,12 +47,41 @@ CG_TOL = 1e-12
 LINK_EPS, APE_ALPHA, APE_STEPS = 0.5, 0.6, 3
 LINK_SEED = 1701 + 2
 SRC_SEED = 726 + 2
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_f64_16x16x16x16_counters.txt")
 
 
 def stencil_bytes_per_site(spinor_bytes_per_real: int, link_bytes_per_real: int, nrhs: int = 1) -> int:
     """Algorithmic bytes of one stencil apply per site: 24 reals in and 24 out per
     right-hand side, and the 40 stored 3x3 complex links (720 reals)."""
     return (24 + 24) * nrhs * spinor_bytes_per_real + 720 * link_bytes_per_real
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1701_00726_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 stencil at 16^4 from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel factor), or
+    None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for ln in f:
+            if "=" in ln and not ln.startswith("#"):
+                k, v = ln.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_src_sha") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -54,6 +91,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--stencil-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and mixed-precision measurements")
+    ap.add_argument("--tune", action="store_true", help="autotune the stencil launch before timing")
+    ap.add_argument("--survey", action="store_true",
+                    help="stencil (tuned, FP64/FP32/BF16-link, 1 and 12 RHS) and overlap timings at 16^4, 24^3x48, 32^3x64")
+    ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
     return ap.parse_args()
 
@@ -63,14 +105,14 @@ def cpu_baseline(L, U_np, shift_iters, budget_s):
     to one overlap apply: oracle links + sum over shifts of (per-shift CG iterations
     x measured time per CG iteration) + the final stencil apply."""
     import oracle
+    import synth
+    from oracle import kl
 
     t0 = time.perf_counter()
     Wo = oracle.links(L, U_np)
     t_links = time.perf_counter() - t0
-    b = __import__("synth").gaussian_source(L, SRC_SEED)[0]
-    c0, om, sg = __import__("oracle.kl", fromlist=["kl"]).kl_diag_coeffs_f64(KL_N)
-    # CG iterations on the smallest shift until the budget is used (at least 2)
-    t_iter = None
+    b = synth.gaussian_source(L, SRC_SEED)[0]
+    _, _, sg = kl.kl_diag_coeffs_f64(KL_N)
     its = 2
     while True:
         t0 = time.perf_counter()
@@ -100,6 +142,50 @@ def cpu_baseline(L, U_np, shift_iters, budget_s):
     }
 
 
+def survey(torch, bri, synth):
+    """Tuned stencil and overlap timings at the three workload lattices (links
+    exp(i eps A) + 3 APE(0.6) built on the device; one JSON line per lattice)."""
+    cfgs = [((16, 16, 16, 16), 0.5, 1703), ((24, 24, 24, 48), 0.7, 1704), ((32, 32, 32, 64), 0.7, 1705)]
+    name = {bri.F64: "f64", bri.F32: "f32", bri.F32_BF16W: "bf16w"}
+    bps = {bri.F64: 8, bri.F32: 4, bri.F32_BF16W: 4}
+    bpl = {bri.F64: 8, bri.F32: 4, bri.F32_BF16W: 2}
+    for L, eps, seed in cfgs:
+        V = int(np.prod(L))
+        U = synth.smeared_links_torch(L, eps, seed, APE_ALPHA, APE_STEPS, device="cuda", chunk=1 << 18)
+        U = U.permute(0, 2, 3, 1).contiguous()
+        W = {p: bri.build_links(L, U, p) for p in (bri.F64, bri.F32, bri.F32_BF16W)}
+        del U
+        rec = {"lattice": list(L), "link_eps": eps}
+        g = torch.randn((12, 4, 3, V), dtype=torch.complex128, device="cuda")
+        for p in (bri.F64, bri.F32, bri.F32_BF16W):
+            for nr in (1, 12):
+                x = g[:nr].to(bri.spinor_dtype(p)).contiguous()
+                best, us = bri.autotune(L, W[p], p, x, reps=3)
+                key = f"stencil_{name[p]}_{nr}rhs"
+                rec[key] = {"us": us, "GBps_alg": stencil_bytes_per_site(bps[p], bpl[p], nr) * V / us / 1e3,
+                            "config": best.as_dict()}
+                print(f"[survey] {L} {key} {us:.1f} us", file=sys.stderr, flush=True)
+        b1 = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED), bri.F64)
+        b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64)
+        for nm, inner, b in (("fp64_1src", bri.F64, b1), ("fp64_12src", bri.F64, b12), ("mixed_f32_1src", bri.F32, b1)):
+            op = bri.OverlapOp(L, W[bri.F64], kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000,
+                               Wlo=None if inner == bri.F64 else W[inner], inner=inner, nrhs=b.shape[0])
+            op.apply(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = op.apply(b)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec["overlap_" + nm] = {"ms_per_call": dt * 1e3, "applies_per_s": b.shape[0] / dt, "cg_iters": st.iters,
+                                    "refine_passes": st.refine}
+            print(f"[survey] {L} overlap {nm} {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+            del op
+            torch.cuda.empty_cache()
+        print(json.dumps(rec), flush=True)
+        del W, g
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,11 +204,23 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.survey:
+        survey(torch, bri, synth)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     L = L_BENCH
     V = int(np.prod(L))
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps  # ms
 
     print(f"[bench] generating links {L} eps={LINK_EPS} APE {APE_STEPS}x{APE_ALPHA}", file=sys.stderr, flush=True)
     U_np = synth.smeared_links(L, LINK_EPS, LINK_SEED, APE_ALPHA, APE_STEPS)
@@ -131,6 +229,25 @@ def main():
     W = torch.empty((40, 3, 3, V), dtype=torch.complex128, device=dev)
     out = torch.empty_like(b)
     bri.build_links(L, U, bri.F64, out=W)
+    if args.tune:
+        cfg, us = bri.autotune(L, W, bri.F64, b, reps=5)
+        print(f"[bench] tuned FP64 stencil: {us:.1f} us {cfg.as_dict()}", file=sys.stderr, flush=True)
+    tuned = bri.get_stencil_cfg(L, bri.F64, 1).as_dict()
+
+    if args.stencil_only:
+        # calibration copy of 1 GiB (beyond the 256 MB Infinity Cache), then the stencil
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        t_in, t_out = b.clone(), torch.empty_like(b)
+        for _ in range(args.stencil_reps):
+            bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
+        torch.cuda.synchronize()
+        print(json.dumps({"stencil_only": True, "launches": args.stencil_reps, "copy_bytes": 1 << 30,
+                          "kernel_src_sha": kernel_source_digest(), "config": tuned}), flush=True)
+        return
+
     op = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
 
     def step():
@@ -155,25 +272,20 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
-    value = args.steps * b.shape[0] / (ms_step * args.steps / 1e3)
+    value = b.shape[0] / (ms_step / 1e3)
+    ref64 = out.clone()
     print(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step (host wall {wall:.3f} s)", file=sys.stderr, flush=True)
 
     # dominant kernel: the FP64 stencil, timed live with events on the same stream
-    t_in = torch.empty_like(b)
-    t_out = torch.empty_like(b)
-    t_in.copy_(b)
+    t_in, t_out = b.clone(), torch.empty_like(b)
     for _ in range(5):
         bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
     torch.cuda.synchronize()
-    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s0.record(stream)
-    for _ in range(args.stencil_reps):
-        bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
-    s1.record(stream)
-    torch.cuda.synchronize()
-    us_launch = s0.elapsed_time(s1) * 1e3 / args.stencil_reps
+    ms_launch = timed(lambda: bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps)
+    us_launch = ms_launch * 1e3
     alg_bytes = stencil_bytes_per_site(8, 8) * V
     achieved = alg_bytes / (us_launch * 1e-6) / 1e9
+    traffic = measured_traffic()
     print(f"[bench] bri_apply FP64 {us_launch:.1f} us/launch, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
 
     result = {
@@ -197,6 +309,7 @@ def main():
             "nrhs": int(b.shape[0]),
             "precision": "fp64",
             "cg_iterations": int(np.median(iters)),
+            "stencil_config": tuned,
         },
         "roofline": {
             "bound": "hbm",
@@ -205,12 +318,52 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": None if traffic is None else traffic / (us_launch * 1e-6) / 1e9,
+            "traffic_bytes_per_launch": traffic,
             "us_per_launch": us_launch,
             "alg_bytes_per_launch": alg_bytes,
         },
-        "bri_apply_fp64_GBps": achieved,
     }
+
+    if not args.no_extra:
+        extra = {}
+        # 12 spin-colour point sources, batched FP64
+        b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
+        o12 = torch.empty_like(b12)
+        if args.tune:
+            bri.autotune(L, W, bri.F64, b12, reps=3)
+        op12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, nrhs=12)
+        op12.apply(b12, out=o12)
+        ms = timed(lambda: op12.apply(b12, out=o12), 3)
+        extra["batched_fp64_12src"] = {"applies_per_s": 12 / (ms / 1e3), "ms_per_call": ms}
+        ref12 = o12.clone()
+        # single-source FP64 on the point source 0 for the per-solve error of the mixed runs
+        for name, inner in (("mixed_f32", bri.F32), ("mixed_bf16w", bri.F32_BF16W)):
+            Wlo = bri.build_links(L, U, inner)
+            opm = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, Wlo=Wlo, inner=inner)
+            om = torch.empty_like(b)
+            _, stm = opm.apply(b, out=om)
+            ms = timed(lambda: opm.apply(b, out=om), 2)
+            err = float(torch.linalg.vector_norm(om - ref64) / torch.linalg.vector_norm(ref64))
+            extra[name + "_1src"] = {"applies_per_s": 1 / (ms / 1e3), "ms_per_call": ms, "refine_passes": stm.refine,
+                                     "rel_err_vs_fp64": err}
+            opm12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, Wlo=Wlo, inner=inner, nrhs=12)
+            om12 = torch.empty_like(b12)
+            opm12.apply(b12, out=om12)
+            ms = timed(lambda: opm12.apply(b12, out=om12), 1)
+            errs = [float(torch.linalg.vector_norm(om12[r] - ref12[r]) / torch.linalg.vector_norm(ref12[r]))
+                    for r in range(12)]
+            extra[name + "_12src"] = {"applies_per_s": 12 / (ms / 1e3), "ms_per_call": ms,
+                                      "max_rel_err_vs_fp64": max(errs)}
+            del opm, opm12, Wlo
+            torch.cuda.empty_cache()
+        best_mixed = max(extra[k]["applies_per_s"] for k in extra if k.startswith("mixed"))
+        extra["fp64_1src_applies_per_s"] = value
+        extra["speedup_batched_fp64_vs_fp64_1src"] = extra["batched_fp64_12src"]["applies_per_s"] / value
+        extra["speedup_best_mixed_vs_fp64_1src"] = best_mixed / value
+        result["extra"] = extra
+        print(f"[bench] extra: {json.dumps(extra)}", file=sys.stderr, flush=True)
+
     if not args.no_cpu:
         print("[bench] CPU oracle sample ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(L, U_np, st.shift_iters, args.cpu_seconds)

@@ -388,12 +388,12 @@ int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilCon
     return e == hipSuccess ? BRI_OK : (e == hipErrorInvalidValue ? BRI_EINVAL : BRI_EHIP);
 }
 
-// Column traversal when the lattice allows an 8 x 8 (or 16 x 4) tile and a
-// column depth of 8 (or 4) z-planes; lexicographic tiles otherwise.
+// Column traversal when the lattice allows a 16 x 4 (or 8 x 8) tile and a
+// column depth of 8 (or 4, 2) z-planes; lexicographic tiles otherwise.
 static void default_traversal(const Geom &g, StencilConfig &c) {
     for (int mu = 0; mu < 4; ++mu) c.tile[mu] = 0;
     c.colz = 0;
-    const int tx_opts[3][2] = {{8, 8}, {16, 4}, {4, 16}};
+    const int tx_opts[3][2] = {{16, 4}, {8, 8}, {4, 16}};
     for (const auto &t : tx_opts) {
         if (g.L[0] % t[0] || g.L[1] % t[1]) continue;
         for (int cz : {8, 4, 2}) {
