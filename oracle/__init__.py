@@ -17,6 +17,12 @@ Functions and the passages they follow:
   rational_apply   c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, eq. (KLnn_parfrac)
   sign_apply       gamma5 g_{2n+1}(H) b with H = gamma5 D(-rho), Sec. 3.3 / eq. (def_over)
   ov_apply         rho (1 + gamma5 g_{2n+1}(H)) b, eq. (def_over)
+  link_force       dS/d omega for S = Re sum_p w_p u_p^dag D v_p, U -> exp(i omega^a
+                   lambda_a / 2) U (Sec. 9: derivative with respect to the Gell-Mann
+                   components of log U), product rule along every path of App. C.1
+  ov_force         the same derivative for S = Re chi^dag D_ov psi with the fixed-order
+                   rational of eq. (KLnn_parfrac) inside eq. (def_over) (Sec. 9), and
+                   the spinor gradient D_ov^dag chi
 """
 
 from __future__ import annotations
@@ -68,6 +74,8 @@ def _load():
             lib.orc_rational.argtypes = [P, P, D, I, D, P, P, P, P, D, I, P, P]
             lib.orc_rational.restype = I
             lib.orc_num_threads.restype = I
+            lib.orc_lambda.argtypes = [I, P]
+            lib.orc_link_force.argtypes = [P, I, P, I, P, P, P, P]
             _lib = lib
     return _lib
 
@@ -204,3 +212,54 @@ def ov_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit:
     """D_ov b = rho (1 + gamma5 g_{2n+1}(H)) b = rho (b + D(-rho) r_n(D^dag D) b), eq. (def_over)."""
     y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit)
     return rho * (b + dirac(L, W, -rho, y)), iters, rel
+
+
+# ----------------------------------------------------------------- link force
+
+
+def gell_mann(a: int) -> np.ndarray:
+    """lambda_{a+1} (a = 0..7) as the oracle writes it out."""
+    out = np.zeros(9, dtype=np.complex128)
+    _load().orc_lambda(int(a), _ptr(out))
+    return out.reshape(3, 3)
+
+
+def link_force(L, U: np.ndarray, tbc: int, pairs) -> np.ndarray:
+    """F (4, V, 8): dS/d omega^a_mu(z) at omega = 0 for U_mu(z) -> exp(i omega lambda_a / 2) U_mu(z),
+    S = Re sum_p w_p u_p^dag D_bri v_p; pairs = [(w, u, v), ...] with u, v of shape (V, 4, 3)."""
+    V = volume(L)
+    U = _c128(U)
+    assert U.shape == (4, V, 3, 3)
+    w = np.ascontiguousarray([float(p[0]) for p in pairs], dtype=np.float64)
+    u = _c128(np.stack([np.asarray(p[1]).reshape(V, 4, 3) for p in pairs]))
+    v = _c128(np.stack([np.asarray(p[2]).reshape(V, 4, 3) for p in pairs]))
+    F = np.zeros((4, V, 8), dtype=np.float64)
+    _load().orc_link_force(_ptr(_geom(L)), int(tbc), _ptr(U), len(pairs), _ptr(w), _ptr(u), _ptr(v), _ptr(F))
+    return F
+
+
+def ov_force(L, U: np.ndarray, tbc: int, rho: float, n: int, chi: np.ndarray, psi: np.ndarray,
+             tol: float = 1e-13, maxit: int = 10000):
+    """Gradient of S = Re chi^dag D_ov psi, D_ov = rho (1 + X r_n(X^dag X)), X = D_bri(-rho).
+
+    With a_i = (A + sigma_i)^{-1} psi, b_i = (A + sigma_i)^{-1} X^dag chi, A = X^dag X and
+    y = c0 psi + sum_i omega_i a_i, the derivative of the partial fractions gives
+      dS = rho Re[chi^dag dX y] - rho sum_i omega_i Re[(X a_i)^dag dX b_i + (X b_i)^dag dX a_i],
+    and grad_psi S = D_ov^dag chi = rho (chi + c0 X^dag chi + sum_i omega_i b_i).
+    Returns (F (4, V, 8), grad_psi (V, 4, 3))."""
+    c0, om, sg = kl.kl_diag_coeffs_f64(n)
+    W = links(L, U, tbc)
+    m0 = -rho
+    xdc = dirac_adj(L, W, m0, chi)
+    pairs = []
+    y = c0 * _c128(psi)
+    gpsi = _c128(chi) + c0 * xdc
+    for i in range(n):
+        a, _, _ = cg(L, W, m0, sg[i], psi, tol, maxit)
+        b, _, _ = cg(L, W, m0, sg[i], xdc, tol, maxit)
+        y = y + om[i] * a
+        gpsi = gpsi + om[i] * b
+        pairs.append((-rho * om[i], dirac(L, W, m0, a), b))
+        pairs.append((-rho * om[i], dirac(L, W, m0, b), a))
+    pairs.insert(0, (rho, chi, y))
+    return link_force(L, U, tbc, pairs), rho * gpsi

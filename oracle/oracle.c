@@ -37,6 +37,9 @@
  *   orc_rational   y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, every
  *                  shift solved separately (eq. (KLnn_parfrac) with
  *                  X^dag X = D^dag D).
+ *   orc_link_force derivative of Re sum_p w_p u_p^dag D v_p with respect to
+ *                  the Gell-Mann components of log U (Sec. 9), by the product
+ *                  rule along every path of every W_d(x).
  *
  * Gamma matrices: the paper only says "chiral representation" (App. C.1).
  * Used here: gamma_k = [[0, -i s_k], [i s_k, 0]] (s_k the Pauli matrices),
@@ -476,4 +479,157 @@ int orc_rational(const int *L, const cplx *W, double m0, int nshift, double c0, 
     }
     free(xs);
     return worst;
+}
+
+/* ------------------------------------------------------------- link force */
+
+/* Gell-Mann matrices lambda_1..lambda_8, written out from their definition */
+static cplx LAM[8][3][3];
+static int lam_ready = 0;
+
+static void init_lambdas(void) {
+    if (lam_ready) return;
+    const cplx iu = _Complex_I;
+    memset(LAM, 0, sizeof(LAM));
+    LAM[0][0][1] = 1;   LAM[0][1][0] = 1;
+    LAM[1][0][1] = -iu; LAM[1][1][0] = iu;
+    LAM[2][0][0] = 1;   LAM[2][1][1] = -1;
+    LAM[3][0][2] = 1;   LAM[3][2][0] = 1;
+    LAM[4][0][2] = -iu; LAM[4][2][0] = iu;
+    LAM[5][1][2] = 1;   LAM[5][2][1] = 1;
+    LAM[6][1][2] = -iu; LAM[6][2][1] = iu;
+    LAM[7][0][0] = 1.0 / sqrt(3.0);
+    LAM[7][1][1] = 1.0 / sqrt(3.0);
+    LAM[7][2][2] = -2.0 / sqrt(3.0);
+    lam_ready = 1;
+}
+
+void orc_lambda(int a, cplx *out9) {
+    init_lambdas();
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) out9[3 * i + k] = LAM[a][i][k];
+}
+
+/* Link force of S = Re sum_p w_p u_p^dag D v_p (D the Brillouin operator; the
+ * 0-hop term does not depend on the links).  Sec. 9 takes the derivative with
+ * respect to the Gell-Mann components of log U; here
+ *   F[mu][z][a] = dS/d omega at omega = 0 for U_mu(z) -> exp(i omega lambda_a / 2) U_mu(z).
+ * Each W_d(x) is the average over its k! paths of the ordered product of the
+ * step matrices (orc_links); the product rule puts the perturbed step between
+ * the product of the steps before it (P) and of those after it (Q):
+ *   a +mu step from z carries U = U_mu(z),       dU   = X U,
+ *   a -mu step onto z carries U_mu(z)^dag,       dU^dag = -U^dag X,
+ * with X = i lambda_a / 2 (anti-hermitian).  With
+ *   M_ab = sum_p w_p sum_{s,t} conj(u_p(x)_{s a}) (S_d)_{s t} v_p(x+d)_{t b},
+ * a step contributes Re sum_ab M_ab (P dT Q)_ab = Re tr(Q M^T P dT).
+ * Layouts: U [4][V][3][3]; u, v [npairs][V][4][3]; F [4][V][8]. */
+void orc_link_force(const int *L, int tbc, const cplx *U, int npairs, const double *w, const cplx *u,
+                    const cplx *v, double *F) {
+    const long V = vol(L);
+    init_perms();
+    init_lambdas();
+    cplx S[81][4][4];
+    for (int j = 0; j < 81; ++j) spin_matrix(j, 0.0, S[j]);
+    int nthr = orc_num_threads();
+    double *part = calloc((size_t)nthr * 4 * V * 8, sizeof(double));
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        double *Fl = part + (size_t)omp_get_thread_num() * 4 * V * 8;
+#else
+        double *Fl = part;
+#endif
+#pragma omp for schedule(dynamic, 1)
+        for (long x = 0; x < V; ++x) {
+            int cx[4];
+            coords(L, x, cx);
+            for (int j = 0; j < 81; ++j) {
+                if (j == 40) continue;
+                int d[4];
+                disp_of(j, d);
+                int cy[4];
+                for (int mu = 0; mu < 4; ++mu) cy[mu] = cx[mu] + d[mu];
+                const long y = site_of(L, cy);
+                /* M (colour 3x3) */
+                cplx M[9] = {0};
+                for (int p = 0; p < npairs; ++p) {
+                    const cplx *up = u + ((size_t)p * V + x) * 12;
+                    const cplx *vp = v + ((size_t)p * V + y) * 12;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            cplx acc = 0;
+                            for (int s = 0; s < 4; ++s)
+                                for (int t = 0; t < 4; ++t) acc += conj(up[3 * s + a]) * S[j][s][t] * vp[3 * t + b];
+                            M[3 * a + b] += w[p] * acc;
+                        }
+                }
+                cplx MT[9];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) MT[3 * a + b] = M[3 * b + a];
+                int axes[4], k = 0;
+                for (int mu = 0; mu < 4; ++mu)
+                    if (d[mu] != 0) axes[k++] = mu;
+                const int np_local = NPERM[k];
+                for (int pth = 0; pth < np_local; ++pth) {
+                    /* the steps of this path */
+                    cplx T[4][9];
+                    int smu[4], plus[4];
+                    long lsite[4];
+                    double sign = 1.0;
+                    int cz[4] = {cx[0], cx[1], cx[2], cx[3]};
+                    for (int st = 0; st < k; ++st) {
+                        const int mu = axes[PERM[k][pth][st]];
+                        smu[st] = mu;
+                        if (d[mu] > 0) {
+                            if (tbc && mu == 3 && ((cz[3] % L[3]) + L[3]) % L[3] == L[3] - 1) sign = -sign;
+                            lsite[st] = site_of(L, cz);
+                            memcpy(T[st], U + ((size_t)mu * V + lsite[st]) * 9, sizeof(cplx) * 9);
+                            plus[st] = 1;
+                            cz[mu] += 1;
+                        } else {
+                            if (tbc && mu == 3 && ((cz[3] % L[3]) + L[3]) % L[3] == 0) sign = -sign;
+                            cz[mu] -= 1;
+                            lsite[st] = site_of(L, cz);
+                            const cplx *Um = U + ((size_t)mu * V + lsite[st]) * 9;
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = 0; b < 3; ++b) T[st][3 * a + b] = conj(Um[3 * b + a]);
+                            plus[st] = 0;
+                        }
+                    }
+                    /* prefix P[i] = T_0 ... T_{i-1}, suffix Q[i] = T_i ... T_{k-1} */
+                    cplx P[5][9], Q[5][9];
+                    const cplx I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+                    memcpy(P[0], I3, sizeof(I3));
+                    for (int i = 0; i < k; ++i) mat_mul(P[i], T[i], P[i + 1]);
+                    memcpy(Q[k], I3, sizeof(I3));
+                    for (int i = k - 1; i >= 0; --i) mat_mul(T[i], Q[i + 1], Q[i]);
+                    const double f = sign / (double)np_local;
+                    for (int i = 0; i < k; ++i) {
+                        cplx R[9], t1[9], Y[9];
+                        mat_mul(Q[i + 1], MT, t1);
+                        mat_mul(t1, P[i], R);
+                        const cplx *Ul = U + ((size_t)smu[i] * V + lsite[i]) * 9;
+                        if (plus[i]) {
+                            mat_mul(Ul, R, Y); /* Re tr(R X U) = Re tr(U R X) */
+                        } else {
+                            mat_mul_dag(R, Ul, t1); /* -Re tr(R U^dag X) */
+                            for (int e = 0; e < 9; ++e) Y[e] = -t1[e];
+                        }
+                        double *Fz = Fl + ((size_t)smu[i] * V + lsite[i]) * 8;
+                        for (int a = 0; a < 8; ++a) {
+                            cplx tr = 0;
+                            for (int r = 0; r < 3; ++r)
+                                for (int c = 0; c < 3; ++c) tr += Y[3 * r + c] * LAM[a][c][r];
+                            /* Re tr(Y i lambda / 2) */
+                            Fz[a] += f * creal(0.5 * _Complex_I * tr);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    memset(F, 0, sizeof(double) * 4 * V * 8);
+    for (int t = 0; t < nthr; ++t)
+        for (long e = 0; e < 4 * V * 8; ++e) F[e] += part[(size_t)t * 4 * V * 8 + e];
+    free(part);
 }

@@ -158,7 +158,7 @@ def test_wouldbe_zero_mode_table():
 
 @pytest.mark.parametrize("ell", [3, 9, 17, 33])
 def test_derivative_closed_form(ell):
-    """g_l'(x) = 4 l (1-x^2)^{l-1} / [(1+x)^l + (1-x)^l]^2 (Sec. 8)."""
+    """g_l'(x) = 4 l (1-x^2)^{l-1} / [(1+x)^l + (1-x)^l]^2 (Sec. 9)."""
     n = (ell - 1) // 2
     with mp.workdps(50):
         for x in ["0.1", "0.9", "1.5", "6"]:
