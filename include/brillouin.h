@@ -187,6 +187,62 @@ int bri_get_stencil_cfg(const bri_geom *geom, int prec, int nrhs, bri_stencil_cf
  * computed in double precision on the host; sigma ascending. */
 int bri_kl_coeffs(int n, double *c0, double *omega, double *sigma);
 
+/*
+ * Differentiation (Sec. 9: the molecular-dynamics force is the derivative with
+ * respect to the Gell-Mann components of log U).  The links are perturbed as
+ *   U_mu(x) -> exp(i omega^a lambda_a / 2) U_mu(x),  a = 1..8,
+ * and the force is F^a_mu(x) = dS/d omega^a at omega = 0, stored
+ *   F    [4][8][V]     double
+ * The complex gradient with respect to the link entries, in the convention
+ * dS/dRe U + i dS/dIm U (the one torch uses for a real loss), is stored
+ *   GU   [4][3][3][V]  complex double (same layout as U).
+ * Both follow the off-axis links through their path averages (App. C.1) down
+ * to U, with the t-boundary sign of tbc.  The 0-hop term does not depend on U.
+ */
+
+/* Most (u, v) pairs bri_link_grad takes in one call. */
+#define BRI_MAX_PAIRS (2 * BRI_MAX_SHIFTS + 1)
+
+/*
+ * bri_link_grad -- force of S = Re sum_p weights[p] u_p^dag D_bri v_p.
+ *   U       [4][3][3][V] complex double links the FP64 W was built from, with
+ *           the same geom->tbc
+ *   W       [40][3][3][V] complex double off-axis links (bri_build_links, BRI_F64)
+ *   npairs  1..BRI_MAX_PAIRS; weights[npairs] on the host
+ *   u, v    [npairs][4][3][V] complex double spinors
+ *   F       [4][8][V] double, or NULL;  GU [4][3][3][V] complex double, or NULL
+ *           (at least one of the two); both overwritten
+ *   work, work_bytes: device workspace of 81 * 9 * V complex doubles; with
+ *           work == NULL the call only writes the size into *work_bytes.
+ * Asynchronous on `stream`.  BRI_EINVAL for bad geometry, npairs or pointers.
+ */
+int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
+                  const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream);
+
+/*
+ * ov_apply_grad -- gradient of S = Re chi^dag D_ov psi (one right-hand side),
+ * D_ov = rho (1 + X r_n(A)), with the fixed-order rational of eq.
+ * (KLnn_parfrac) differentiated through its partial fractions (Sec. 9):
+ *   a_i = (A + sigma_i)^{-1} psi, b_i = (A + sigma_i)^{-1} X^dag chi,
+ *   y = c0 psi + sum_i omega_i a_i,
+ *   dS = rho Re[chi^dag dX y] - rho sum_i omega_i Re[(X a_i)^dag dX b_i + (X b_i)^dag dX a_i],
+ *   gpsi = D_ov^dag chi = rho (chi + c0 X^dag chi + sum_i omega_i b_i)
+ *        (= dS/dRe psi + i dS/dIm psi).
+ * The a_i and b_i come from one FP64 two-column multi-shift solve (params->inner
+ * must be BRI_F64; max_refine is ignored).
+ *   U, W64  as bri_link_grad (W64 built from U with geom->tbc)
+ *   chi, psi, gpsi  [4][3][V] complex double
+ *   F, GU   as bri_link_grad (at least one non-NULL)
+ *   work, work_bytes  device workspace (query with work == NULL)
+ *   stats   may be NULL: iterations and the stopping residual of each shift
+ * Synchronises `stream`.  Returns BRI_ENOCONV when a shift missed tol within
+ * max_iter (the outputs then use the last iterates), BRI_ENAN on a non-finite
+ * residual, BRI_EINVAL for bad arguments (V must be a multiple of 64).
+ */
+int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov_params *params, const void *chi,
+                  const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes, ov_stats *stats,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

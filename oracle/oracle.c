@@ -563,6 +563,9 @@ void orc_link_force(const int *L, int tbc, const cplx *U, int npairs, const doub
                             M[3 * a + b] += w[p] * acc;
                         }
                 }
+                int nonzero = 0;
+                for (int e = 0; e < 9; ++e) nonzero |= (M[e] != 0);
+                if (!nonzero) continue; /* this (x, d) term does not enter S */
                 cplx MT[9];
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) MT[3 * a + b] = M[3 * b + a];

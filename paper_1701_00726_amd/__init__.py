@@ -11,6 +11,9 @@ torch tensors provide device memory:
   W    (40, 3, 3, V): complex128 (BRI_F64), complex64 (BRI_F32),
        int32 holding (re, im) bfloat16 pairs (BRI_F32_BF16W)
   psi  (nrhs, 4, 3, V): complex128 (BRI_F64) or complex64 (BRI_F32*)
+  F    float64, shape (4, 8, V): link force, dS/d omega^a for
+       U -> exp(i omega^a lambda_a / 2) U
+  GU   complex128, shape (4, 3, 3, V): dS/dRe U + i dS/dIm U
 """
 
 from __future__ import annotations
@@ -119,6 +122,10 @@ def load():
             lib.bri_autotune.argtypes = [G, P, I, P, P, I, I, SC, ctypes.POINTER(D), P]
             lib.bri_set_stencil_cfg.argtypes = [G, I, I, SC]
             lib.bri_get_stencil_cfg.argtypes = [G, I, I, SC]
+            SZ = ctypes.POINTER(ctypes.c_size_t)
+            lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
+            lib.ov_apply_grad.argtypes = [G, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
+                                          ctypes.POINTER(_OvStats), P]
             for fn in EXPORTS:
                 getattr(lib, fn).restype = I
             _lib = lib
@@ -136,7 +143,10 @@ EXPORTS = (
     "bri_autotune",
     "bri_set_stencil_cfg",
     "bri_get_stencil_cfg",
+    "bri_link_grad",
+    "ov_apply_grad",
 )
+MAX_PAIRS = 2 * MAX_SHIFTS + 1
 
 
 # ------------------------------------------------------------------ helpers
@@ -321,6 +331,46 @@ class OverlapOp:
         """out = sign(H) psi ~= gamma5 X r_n(X^dag X) psi."""
         return self._run("ov_sign_apply", psi, out, stream, allow_noconv)
 
+    def grad(self, U, chi, psi, force=True, link_grad=False, stream=None, allow_noconv=False):
+        """Gradient of S = Re chi^dag D_ov psi for one right-hand side (FP64 only).
+
+        U is the (4, 3, 3, V) complex128 field W64 was built from (with this
+        operator's tbc).  Returns (F or None, GU or None, grad_psi, OvStats) with
+        F (4, 8, V) the force, GU (4, 3, 3, V) = dS/dRe U + i dS/dIm U and
+        grad_psi = D_ov^dag chi of the shape of psi."""
+        torch = _torch()
+        V = int(np.prod(self.L))
+        if self.params.inner != F64:
+            raise ValueError("the gradient runs its shift solves in FP64 (inner = F64)")
+        for name, t in (("chi", chi), ("psi", psi)):
+            if t.dtype != torch.complex128 or t.numel() != 12 * V:
+                raise ValueError(f"{name} must be complex128 with 12 V elements")
+        if U.dtype != torch.complex128 or tuple(U.shape) != (4, 3, 3, V):
+            raise ValueError("U must be complex128 of shape (4, 3, 3, V)")
+        if not (force or link_grad):
+            raise ValueError("ask for the force, the link gradient or both")
+        if getattr(self, "_gwork", None) is None:
+            nb = ctypes.c_size_t(0)
+            _check("ov_apply_grad", load().ov_apply_grad(ctypes.byref(self.g), None, None, ctypes.byref(self.params),
+                                                         None, None, None, None, None, None, ctypes.byref(nb), None,
+                                                         None))
+            self._gwork = torch.empty(int(nb.value), dtype=torch.uint8, device=self.W64.device)
+        F = torch.empty((4, 8, V), dtype=torch.float64, device=U.device) if force else None
+        GU = torch.empty_like(U) if link_grad else None
+        gpsi = torch.empty_like(psi)
+        stats = _OvStats()
+        wb = ctypes.c_size_t(self._gwork.numel())
+        st = load().ov_apply_grad(
+            ctypes.byref(self.g), _dptr(U), _dptr(self.W64), ctypes.byref(self.params), _dptr(chi), _dptr(psi),
+            None if F is None else _dptr(F), None if GU is None else _dptr(GU), _dptr(gpsi), _dptr(self._gwork),
+            ctypes.byref(wb), ctypes.byref(stats), _stream(stream),
+        )
+        _check("ov_apply_grad", st, allow=(ENOCONV,) if allow_noconv else ())
+        n = self.params.kl_n
+        s = OvStats(stats.iters, stats.refine, list(stats.shift_iters[:n]), list(stats.rel_resid[:n]), stats.seconds)
+        s.status = st
+        return F, GU, gpsi, s
+
 
 def kl_coeffs(n):
     """(c0, omega[n], sigma[n]) as computed by the library's host code."""
@@ -381,3 +431,126 @@ def set_stencil_cfg(L, prec, nrhs, cfg):
     g = _geom(L)
     _check("bri_set_stencil_cfg", load().bri_set_stencil_cfg(ctypes.byref(g), int(prec), int(nrhs),
                                                              None if cfg is None else ctypes.byref(cfg)))
+
+
+# -------------------------------------------------------------- differentiation
+
+
+def link_grad(L, U, W, pairs, tbc=0, force=True, link_grad=False, stream=None):
+    """Gradient of S = Re sum_p w_p u_p^dag D_bri v_p with respect to the links.
+
+    pairs = [(w, u, v), ...] with u, v complex128 tensors of 12 V elements in the
+    (4, 3, V) spinor layout; W the FP64 off-axis links built from U with `tbc`.
+    Returns (F (4, 8, V) or None, GU (4, 3, 3, V) or None)."""
+    torch = _torch()
+    V = int(np.prod(L))
+    if not 1 <= len(pairs) <= MAX_PAIRS:
+        raise ValueError(f"1..{MAX_PAIRS} pairs")
+    if U.dtype != torch.complex128 or tuple(U.shape) != (4, 3, 3, V):
+        raise ValueError("U must be complex128 of shape (4, 3, 3, V)")
+    if W.dtype != torch.complex128 or tuple(W.shape) != (40, 3, 3, V):
+        raise ValueError("W must be the complex128 (40, 3, 3, V) links")
+    if not (force or link_grad):
+        raise ValueError("ask for the force, the link gradient or both")
+    for _, u, v in pairs:
+        if u.dtype != torch.complex128 or v.dtype != torch.complex128 or u.numel() != 12 * V or v.numel() != 12 * V:
+            raise ValueError("u and v must be complex128 with 12 V elements")
+    uu = torch.stack([p[1].reshape(4, 3, V) for p in pairs]).contiguous()
+    vv = torch.stack([p[2].reshape(4, 3, V) for p in pairs]).contiguous()
+    w = (ctypes.c_double * len(pairs))(*[float(p[0]) for p in pairs])
+    g = _geom(L, tbc)
+    nb = ctypes.c_size_t(0)
+    lib = load()
+    _check("bri_link_grad", lib.bri_link_grad(ctypes.byref(g), None, None, len(pairs), w, None, None, None, None, None,
+                                              ctypes.byref(nb), None))
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device=U.device)
+    F = torch.empty((4, 8, V), dtype=torch.float64, device=U.device) if force else None
+    GU = torch.empty_like(U) if link_grad else None
+    _check("bri_link_grad", lib.bri_link_grad(ctypes.byref(g), _dptr(U), _dptr(W), len(pairs), w, _dptr(uu),
+                                              _dptr(vv), None if F is None else _dptr(F),
+                                              None if GU is None else _dptr(GU), _dptr(work), ctypes.byref(nb),
+                                              _stream(stream)))
+    return F, GU
+
+
+
+class BrillouinApply:
+    """out = D_bri(m0)[U] psi as a torch.autograd.Function over (U, psi).
+
+    Forward builds the FP64 off-axis links from U and applies the stencil; backward
+    returns D_bri^dag grad_out for psi and dS/dRe U + i dS/dIm U (torch's complex
+    convention) for U, both from the library's kernels.  psi has shape (nrhs, 4, 3, V)."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, U, psi, L, m0, tbc=0):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, U, psi, L, m0, tbc):
+                    W = build_links(L, U, F64, tbc)
+                    out = apply(L, W, F64, m0, psi.contiguous())
+                    ctx.save_for_backward(U, W, psi)
+                    ctx.L, ctx.m0, ctx.tbc = L, m0, tbc
+                    return out
+
+                @staticmethod
+                def backward(ctx, gout):
+                    U, W, psi = ctx.saved_tensors
+                    gout = gout.contiguous()
+                    gU = gpsi = None
+                    if ctx.needs_input_grad[1]:
+                        gpsi = apply_dag(ctx.L, W, F64, ctx.m0, gout)
+                    if ctx.needs_input_grad[0]:
+                        pairs = [(1.0, gout[r], psi[r]) for r in range(psi.shape[0])]
+                        GU = None
+                        for k in range(0, len(pairs), MAX_PAIRS):
+                            _, part = link_grad(ctx.L, U, W, pairs[k:k + MAX_PAIRS], ctx.tbc, force=False,
+                                                link_grad=True)
+                            GU = part if GU is None else GU + part
+                        gU = GU
+                    return gU, gpsi, None, None, None
+
+            cls._fn = _Fn
+        return cls._fn.apply(U, psi, tuple(int(v) for v in L), float(m0), int(tbc))
+
+
+class OverlapApply:
+    """out = D_ov[U] psi (one right-hand side, FP64) as a torch.autograd.Function.
+
+    Forward: off-axis links from U, then ov_apply.  Backward: ov_apply_grad, which
+    re-solves the shifted systems for psi and X^dag grad_out and returns
+    dS/dRe U + i dS/dIm U for U and D_ov^dag grad_out for psi."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, U, psi, L, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, tbc=0):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, U, psi, L, kl_n, rho, tol, max_iter, tbc):
+                    W = build_links(L, U, F64, tbc)
+                    op = OverlapOp(L, W, kl_n=kl_n, rho=rho, tol=tol, max_iter=max_iter, tbc=tbc)
+                    out, _ = op.apply(psi.reshape(1, 4, 3, -1).contiguous())
+                    ctx.save_for_backward(U, psi)
+                    ctx.op = op
+                    return out.reshape(psi.shape)
+
+                @staticmethod
+                def backward(ctx, gout):
+                    U, psi = ctx.saved_tensors
+                    _, GU, gpsi, _ = ctx.op.grad(U, gout.contiguous(), psi.contiguous(), force=False,
+                                                 link_grad=True)
+                    return (GU if ctx.needs_input_grad[0] else None,
+                            gpsi.reshape(psi.shape) if ctx.needs_input_grad[1] else None,
+                            None, None, None, None, None, None)
+
+            cls._fn = _Fn
+        return cls._fn.apply(U, psi, tuple(int(v) for v in L), int(kl_n), float(rho), float(tol), int(max_iter),
+                             int(tbc))

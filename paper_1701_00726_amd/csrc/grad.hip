@@ -1,0 +1,507 @@
+// Link force of S = Re sum_p w_p u_p^dag D_bri v_p, and of S = Re chi^dag D_ov psi.
+//
+// Convention: U_mu(x) -> exp(i omega^a lambda_a / 2) U_mu(x), F^a_mu(x) = dS/d omega^a at 0.
+// For any complex matrix M entering S write dS = Re tr(G_M^T dM) (plain transpose);
+// G_M is "the coefficient of M".  Then
+//   * D_bri(x, x+d) = S_d (x) W_d(x) with S_d = a_k + c_k sum d_mu gamma_mu Hermitian, so
+//     G_{W_d}(x) = sum_p w_p sum_t conj((S_d u_p(x))_t) v_p(x+d)_t^T      (colour outer product)
+//     for every displacement d != 0 (App. C.1 stencil);
+//   * W_d(x) = (1/k) sum_mu T_mu(x) W_r(x + s_mu e_mu), r = d - s_mu e_mu (the k-hop recursion of
+//     the path average): a product M = A X B gives G_X = A^T G_M B^T, so
+//       G_T  += (1/k) G_W W_r^T,      G_{W_r} += (1/k) T^T G_W,
+//     and a daggered matrix M = Y^dag gives G_Y = G_M^dag;
+//   * T = U_mu(x) for a + step, U_mu(x - e_mu)^dag for a - step (times -1 across the t boundary
+//     when the fermions are antiperiodic);
+//   * F^a = Re tr(G_U^T (i lambda_a / 2) U) = -Im tr(lambda_a U G_U^T) / 2.
+// The pull-back through the recursion runs level by level from 4 hops down to 1 in gather form:
+// each level-(k-1) entry G_r(y) collects from its parents d = r + s e_mu (mu not in supp r,
+// s = +-1) at x = y - s e_mu, so no two threads write the same entry.
+//
+// Overlap: with X = D_bri(-rho), A = X^dag X, a_i = (A + sigma_i)^{-1} psi,
+// b_i = (A + sigma_i)^{-1} X^dag chi and y = c0 psi + sum omega_i a_i,
+//   dS = rho Re[chi^dag dX y] - rho sum_i omega_i Re[(X a_i)^dag dX b_i + (X b_i)^dag dX a_i],
+// i.e. 1 + 2n pairs of the form above (differentiating the partial fractions of eq.
+// (KLnn_parfrac) inside eq. (def_over)), and the spinor gradient is
+//   dS/d psi = D_ov^dag chi = rho (chi + c0 X^dag chi + sum_i omega_i b_i).
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "stencil.hpp"
+#include "stencil_core.hpp"
+
+namespace bri {
+
+// FP64 multi-shift solve of (A + sigma_i) x = b over the Kenney-Laub shifts, every x kept
+// ([shift][ncol][12 V] in the workspace); with work == NULL only *need is set.
+int ov_solve_shifts(const Geom &g, const void *W64, const ov_params *prm, const void *b, int ncol, void *work,
+                    size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ColState *last);
+
+__device__ __forceinline__ int dj(int j, int mu) { return disp_comp(j, mu); }
+
+__device__ __forceinline__ unsigned site_of(const Geom &g, const int c[4]) {
+    return (unsigned)(c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3])));
+}
+
+__device__ __forceinline__ int wrapc(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// W_d(y) for any displacement index j (stored, daggered partner, or the identity)
+__device__ void link_any(const Geom &g, const double2 *__restrict__ W, int j, const int cy[4], double2 M[3][3]) {
+    const size_t V = (size_t)g.V;
+    if (j == 40) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+        return;
+    }
+    if (j < 40) {
+        const unsigned ys = site_of(g, cy);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a][b] = W[((size_t)j * 9 + a * 3 + b) * V + ys];
+        return;
+    }
+    int cz[4];
+    for (int mu = 0; mu < 4; ++mu) cz[mu] = wrapc(cy[mu] + dj(j, mu), g.L[mu]);
+    const unsigned zs = site_of(g, cz);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double2 w = W[((size_t)(80 - j) * 9 + b * 3 + a) * V + zs];
+            M[a][b] = make_double2(w.x, -w.y);
+        }
+}
+
+// T_mu^{s}(x) (with the antiperiodic sign) for the first step of a path from x
+__device__ void first_step(const Geom &g, const double2 *__restrict__ U, int mu, int s, const int cx[4],
+                           double2 T[3][3]) {
+    const size_t V = (size_t)g.V;
+    if (s > 0) {
+        const unsigned xs = site_of(g, cx);
+        const double sg = (g.tbc && mu == 3 && cx[3] == g.L[3] - 1) ? -1.0 : 1.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double2 u = U[((size_t)(mu * 3 + a) * 3 + b) * V + xs];
+                T[a][b] = make_double2(sg * u.x, sg * u.y);
+            }
+    } else {
+        int cm[4] = {cx[0], cx[1], cx[2], cx[3]};
+        cm[mu] = wrapc(cm[mu] - 1, g.L[mu]);
+        const unsigned ms = site_of(g, cm);
+        const double sg = (g.tbc && mu == 3 && cx[3] == 0) ? -1.0 : 1.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double2 u = U[((size_t)(mu * 3 + b) * 3 + a) * V + ms];
+                T[a][b] = make_double2(sg * u.x, -sg * u.y);
+            }
+    }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ------------------------------------------------------------ outer products
+
+struct PairTable {
+    const double2 *u[BRI_MAX_PAIRS];
+    const double2 *v[BRI_MAX_PAIRS];
+    double w[BRI_MAX_PAIRS];
+    int n;
+};
+
+// G[j][a][b](x) = sum_p w_p sum_t conj((S_d u_p(x))_{t,a}) v_p(x+d)_{t,b}, all d != 0
+__global__ __launch_bounds__(128) void grad_outer_kernel(Geom g, PairTable pt, double2 *__restrict__ G) {
+    const unsigned x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (unsigned)g.V) return;
+    const size_t V = (size_t)g.V;
+    int cx[4];
+    {
+        int s = (int)x;
+        for (int mu = 0; mu < 4; ++mu) {
+            cx[mu] = s % g.L[mu];
+            s /= g.L[mu];
+        }
+    }
+    for (int j = 0; j < 81; ++j) {
+        if (j == 40) continue;
+        int cy[4];
+        for (int mu = 0; mu < 4; ++mu) cy[mu] = wrapc(cx[mu] + dj(j, mu), g.L[mu]);
+        const unsigned ys = site_of(g, cy);
+        const DirW<double, false> dw(j);  // S_d = a_k + c_k sum d_mu gamma_mu for d = disp(j)
+        const double a = dw.a, c0 = dw.c0, c1 = dw.c1, c2 = dw.c2, c3 = dw.c3;
+        double2 acc[3][3];
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) acc[p][q] = make_double2(0.0, 0.0);
+        for (int p = 0; p < pt.n; ++p) {
+            double2 u[4][3], e[4][3];
+            for (int s = 0; s < 4; ++s)
+                for (int c = 0; c < 3; ++c) {
+                    u[s][c] = pt.u[p][(size_t)(s * 3 + c) * V + x];
+                    e[s][c] = make_double2(0.0, 0.0);
+                }
+            spin_accumulate(e, u, a, c0, c1, c2, c3);  // e = S_d u
+            const double wp = pt.w[p];
+            for (int t = 0; t < 4; ++t)
+                for (int bb = 0; bb < 3; ++bb) {
+                    const double2 v = pt.v[p][(size_t)(t * 3 + bb) * V + ys];
+                    for (int aa = 0; aa < 3; ++aa) {
+                        const double2 ce = make_double2(wp * e[t][aa].x, -wp * e[t][aa].y);
+                        const double2 m = cmul(ce, v);
+                        acc[aa][bb].x += m.x;
+                        acc[aa][bb].y += m.y;
+                    }
+                }
+        }
+        for (int aa = 0; aa < 3; ++aa)
+            for (int bb = 0; bb < 3; ++bb) G[((size_t)j * 9 + aa * 3 + bb) * V + x] = acc[aa][bb];
+    }
+}
+
+// Level k -> k-1 in gather form: G_r(y) += (1/k) T^T G_d(x), d = r + s e_mu, x = y - s e_mu.
+__global__ __launch_bounds__(128) void grad_level_kernel(Geom g, const double2 *__restrict__ U, double2 *__restrict__ G, int k) {
+    const unsigned y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= (unsigned)g.V) return;
+    const size_t V = (size_t)g.V;
+    int cy[4];
+    {
+        int s = (int)y;
+        for (int mu = 0; mu < 4; ++mu) {
+            cy[mu] = s % g.L[mu];
+            s /= g.L[mu];
+        }
+    }
+    const double invk = 1.0 / (double)k;
+    for (int jr = 0; jr < 81; ++jr) {
+        int r[4], nh = 0;
+        for (int mu = 0; mu < 4; ++mu) {
+            r[mu] = dj(jr, mu);
+            nh += r[mu] != 0;
+        }
+        if (nh != k - 1 || nh == 0) continue;
+        double2 acc[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc[a][b] = G[((size_t)jr * 9 + a * 3 + b) * V + y];
+        for (int mu = 0; mu < 4; ++mu) {
+            if (r[mu] != 0) continue;
+            for (int s = -1; s <= 1; s += 2) {
+                int cx[4] = {cy[0], cy[1], cy[2], cy[3]};
+                cx[mu] = wrapc(cx[mu] - s, g.L[mu]);
+                const int jd = jr + s * (mu == 0 ? 1 : mu == 1 ? 3 : mu == 2 ? 9 : 27);
+                double2 T[3][3];
+                first_step(g, U, mu, s, cx, T);
+                const unsigned xs = site_of(g, cx);
+                double2 Gd[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Gd[a][b] = G[((size_t)jd * 9 + a * 3 + b) * V + xs];
+                // acc += (1/k) T^T Gd
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double2 t = make_double2(0.0, 0.0);
+                        for (int c = 0; c < 3; ++c) {
+                            const double2 m = cmul(T[c][a], Gd[c][b]);
+                            t.x += m.x;
+                            t.y += m.y;
+                        }
+                        acc[a][b].x += invk * t.x;
+                        acc[a][b].y += invk * t.y;
+                    }
+            }
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) G[((size_t)jr * 9 + a * 3 + b) * V + y] = acc[a][b];
+    }
+}
+
+// G_U_mu(z) from every level's first step, then F^a_mu(z) = -Im tr(lambda_a U G_U^T) / 2
+__global__ __launch_bounds__(128) void grad_force_kernel(Geom g, const double2 *__restrict__ U, const double2 *__restrict__ W,
+                                  const double2 *__restrict__ G, double *__restrict__ F, double2 *__restrict__ GUo) {
+    const unsigned z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= (unsigned)g.V) return;
+    const size_t V = (size_t)g.V;
+    int cz[4];
+    {
+        int s = (int)z;
+        for (int mu = 0; mu < 4; ++mu) {
+            cz[mu] = s % g.L[mu];
+            s /= g.L[mu];
+        }
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        double2 GU[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) GU[a][b] = make_double2(0.0, 0.0);
+        const int emu = mu == 0 ? 1 : mu == 1 ? 3 : mu == 2 ? 9 : 27;
+        int cp[4] = {cz[0], cz[1], cz[2], cz[3]};
+        cp[mu] = wrapc(cp[mu] + 1, g.L[mu]);
+        const unsigned ps = site_of(g, cp);
+        // + step at z: T = sg U_mu(z); G_T = (1/k) G_d(z) W_{d - e_mu}(z + e_mu)^T, G_U += sg G_T
+        const double sgp = (g.tbc && mu == 3 && cz[3] == g.L[3] - 1) ? -1.0 : 1.0;
+        // - step at z + e_mu: T = sg U_mu(z)^dag; G_T = (1/k) G_d(z+e) W_{d + e_mu}(z)^T, G_U += sg G_T^dag
+        const double sgm = (g.tbc && mu == 3 && cp[3] == 0) ? -1.0 : 1.0;
+        for (int jd = 0; jd < 81; ++jd) {
+            const int dmu = dj(jd, mu);
+            if (dmu == 0) continue;
+            int k = 0;
+            for (int nu = 0; nu < 4; ++nu) k += dj(jd, nu) != 0;
+            const double invk = 1.0 / (double)k;
+            double2 Gd[3][3], Wr[3][3];
+            if (dmu > 0) {
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Gd[a][b] = G[((size_t)jd * 9 + a * 3 + b) * V + z];
+                link_any(g, W, jd - emu, cp, Wr);
+            } else {
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Gd[a][b] = G[((size_t)jd * 9 + a * 3 + b) * V + ps];
+                link_any(g, W, jd + emu, cz, Wr);
+            }
+            // GT = Gd Wr^T
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double2 t = make_double2(0.0, 0.0);
+                    for (int c = 0; c < 3; ++c) {
+                        const double2 m = cmul(Gd[a][c], Wr[b][c]);
+                        t.x += m.x;
+                        t.y += m.y;
+                    }
+                    if (dmu > 0) {
+                        GU[a][b].x += sgp * invk * t.x;
+                        GU[a][b].y += sgp * invk * t.y;
+                    } else {  // dagger: G_U[b][a] += conj(t)
+                        GU[b][a].x += sgm * invk * t.x;
+                        GU[b][a].y -= sgm * invk * t.y;
+                    }
+                }
+        }
+        // P = U G_U^T ; F^a = -Im tr(lambda_a P) / 2
+        double2 Um[3][3], P[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Um[a][b] = U[((size_t)(mu * 3 + a) * 3 + b) * V + z];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double2 t = make_double2(0.0, 0.0);
+                for (int c = 0; c < 3; ++c) {
+                    const double2 m = cmul(Um[a][c], GU[b][c]);
+                    t.x += m.x;
+                    t.y += m.y;
+                }
+                P[a][b] = t;
+            }
+        // tr(lambda_a P) = sum_{ij} (lambda_a)_{ij} P_{ji}; F^a = -Im tr(lambda_a P) / 2
+        const double s3 = 0.57735026918962576451;  // 1/sqrt(3)
+        // only the imaginary parts are needed: lambda_{1,4,6} are real symmetric, lambda_{2,5,7}
+        // carry -i above and +i below the diagonal, so tr(lambda P) = i (P_ij - P_ji) for them
+        double im[8];
+        im[0] = P[1][0].y + P[0][1].y;
+        im[1] = P[0][1].x - P[1][0].x;
+        im[2] = P[0][0].y - P[1][1].y;
+        im[3] = P[2][0].y + P[0][2].y;
+        im[4] = P[0][2].x - P[2][0].x;
+        im[5] = P[2][1].y + P[1][2].y;
+        im[6] = P[1][2].x - P[2][1].x;
+        im[7] = s3 * (P[0][0].y + P[1][1].y - 2.0 * P[2][2].y);
+        if (F)
+            for (int a = 0; a < 8; ++a) F[((size_t)mu * 8 + a) * V + z] = -0.5 * im[a];
+        if (GUo)  // torch's complex gradient dS/dRe U + i dS/dIm U = conj(G_U)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    GUo[((size_t)(mu * 3 + a) * 3 + b) * V + z] = make_double2(GU[a][b].x, -GU[a][b].y);
+    }
+}
+
+// ---------------------------------------------------------------- helpers
+
+// out = alpha x + beta y + gam sum_k omega_k z_k  (one FP64 column; z_k at stride zstride)
+__global__ void grad_combine_kernel(size_t n, double alpha, const double2 *__restrict__ x, double beta,
+                                    const double2 *__restrict__ y, double gam, int nz,
+                                    const double *__restrict__ omega, const double2 *__restrict__ z, size_t zstride,
+                                    double2 *__restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double2 v = make_double2(alpha * x[i].x, alpha * x[i].y);
+        if (y) {
+            v.x += beta * y[i].x;
+            v.y += beta * y[i].y;
+        }
+        double2 t = make_double2(0.0, 0.0);
+        for (int k = 0; k < nz; ++k) {
+            const double2 zv = z[(size_t)k * zstride + i];
+            t.x += omega[k] * zv.x;
+            t.y += omega[k] * zv.y;
+        }
+        v.x += gam * t.x;
+        v.y += gam * t.y;
+        out[i] = v;
+    }
+}
+
+static inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// G buffer [81][9][V] complex double
+static size_t grad_g_bytes(const Geom &g) { return al256((size_t)81 * 9 * g.V * sizeof(double2)); }
+
+static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, const PairTable &pt, double2 *G,
+                            double *F, double2 *GU, hipStream_t s) {
+    const int threads = 128;
+    const int blocks = (g.V + threads - 1) / threads;
+    hipLaunchKernelGGL(grad_outer_kernel, dim3(blocks), dim3(threads), 0, s, g, pt, G);
+    for (int k = 4; k >= 2; --k) hipLaunchKernelGGL(grad_level_kernel, dim3(blocks), dim3(threads), 0, s, g, U, G, k);
+    hipLaunchKernelGGL(grad_force_kernel, dim3(blocks), dim3(threads), 0, s, g, U, W, G, F, GU);
+    return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+}
+
+// workspace of ov_apply_grad, carved in this order
+struct GradPlan {
+    size_t g_off, xab_off, bin_off, y_off, om_off, solver_off, bytes, solver_bytes;
+};
+
+static int plan_grad(const Geom &g, const ov_params *prm, GradPlan &pl) {
+    const size_t nel = (size_t)12 * g.V;
+    const size_t vb = al256(nel * sizeof(double2));
+    const int n = prm->kl_n;
+    size_t solver_need = 0;
+    void *xdummy = nullptr;
+    const int rc = ov_solve_shifts(g, nullptr, prm, nullptr, 2, nullptr, 0, &solver_need, nullptr, &xdummy, nullptr);
+    if (rc != BRI_OK) return rc;
+    size_t off = 0;
+    pl.g_off = off;
+    off += grad_g_bytes(g);
+    pl.xab_off = off;  // X applied to the 2n shift solutions
+    off += vb * 2 * n;
+    pl.bin_off = off;  // [psi | X^dag chi]
+    off += vb * 2;
+    pl.y_off = off;
+    off += vb;
+    pl.om_off = off;
+    off += al256(sizeof(double) * MAXS);
+    pl.solver_off = off;
+    pl.solver_bytes = solver_need;
+    off += solver_need;
+    pl.bytes = off;
+    return BRI_OK;
+}
+
+}  // namespace bri
+
+extern "C" {
+
+int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
+                  const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream) {
+    using namespace bri;
+    Geom g;
+    int rc = geom_check(geom, &g);
+    if (rc != BRI_OK) return rc;
+    if (!work_bytes || npairs < 1 || npairs > BRI_MAX_PAIRS) return BRI_EINVAL;
+    const size_t need = grad_g_bytes(g);
+    if (!work) {
+        *work_bytes = need;
+        return BRI_OK;
+    }
+    if (*work_bytes < need || !U || !W || !weights || !u || !v || (!F && !GU)) return BRI_EINVAL;
+    PairTable pt;
+    std::memset(&pt, 0, sizeof(pt));
+    pt.n = npairs;
+    const size_t nel = (size_t)12 * g.V;
+    for (int p = 0; p < npairs; ++p) {
+        pt.u[p] = (const double2 *)u + p * nel;
+        pt.v[p] = (const double2 *)v + p * nel;
+        pt.w[p] = weights[p];
+    }
+    return force_from_pairs(g, (const double2 *)U, (const double2 *)W, pt, (double2 *)work, (double *)F,
+                            (double2 *)GU, (hipStream_t)stream);
+}
+
+int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov_params *prm, const void *chi,
+                  const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes, ov_stats *stats,
+                  void *stream) {
+    using namespace bri;
+    const auto t0 = std::chrono::steady_clock::now();
+    Geom g;
+    int rc = geom_check(geom, &g);
+    if (rc != BRI_OK) return rc;
+    if (!prm || !work_bytes) return BRI_EINVAL;
+    const int n = prm->kl_n;
+    if (n < 1 || n > MAXS || !(prm->rho > 0.0 && prm->rho < 2.0) || !(prm->tol > 0.0) || prm->max_iter < 1 ||
+        prm->inner != BRI_F64 || g.V % 64)
+        return BRI_EINVAL;
+    GradPlan pl;
+    rc = plan_grad(g, prm, pl);
+    if (rc != BRI_OK) return rc;
+    if (!work) {
+        *work_bytes = pl.bytes;
+        return BRI_OK;
+    }
+    if (*work_bytes < pl.bytes || !U || !W64 || !chi || !psi || (!F && !GU) || !gpsi) return BRI_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nel = (size_t)12 * g.V;
+    char *base = (char *)work;
+    double2 *G = (double2 *)(base + pl.g_off);
+    double2 *XAB = (double2 *)(base + pl.xab_off);
+    double2 *BIN = (double2 *)(base + pl.bin_off);
+    double2 *Y = (double2 *)(base + pl.y_off);
+    double *om_dev = (double *)(base + pl.om_off);
+    void *swork = base + pl.solver_off;
+    const double m0 = -prm->rho;
+
+    // BIN = [psi | X^dag chi]
+    BRI_HIP_CHECK(hipMemcpyAsync(BIN, psi, nel * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    StencilArgs a{};
+    a.g = g;
+    a.W = W64;
+    a.ncol = 1;
+    a.in = chi;
+    a.out = BIN + nel;
+    a.diag = 15.0 / 8.0 + m0;
+    rc = stencil_launch(a, BRI_F64, true, EPI_PLAIN, default_config(g, BRI_F64, 1), s);
+    if (rc != BRI_OK) return rc;
+    // a_i = (A + sigma_i)^{-1} psi and b_i = (A + sigma_i)^{-1} X^dag chi in one two-column multi-shift
+    // solve; X holds them as [i][2][12 V], i.e. a_i = X[2 i], b_i = X[2 i + 1]
+    void *xs = nullptr;
+    ColState fin;
+    int rcs = ov_solve_shifts(g, W64, prm, BIN, 2, swork, pl.solver_bytes, nullptr, s, &xs, &fin);
+    if (rcs != BRI_OK && rcs != BRI_ENOCONV) return rcs;
+    const double2 *X = (const double2 *)xs;
+    double c0, om[MAXS], sg[MAXS];
+    bri_kl_coeffs(n, &c0, om, sg);
+    BRI_HIP_CHECK(hipMemcpyAsync(om_dev, om, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    // y = c0 psi + sum omega_i a_i ; gpsi = rho (chi + c0 X^dag chi + sum omega_i b_i)
+    hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, c0, (const double2 *)psi, 0.0,
+                       (const double2 *)nullptr, 1.0, n, (const double *)om_dev, X, 2 * nel, Y);
+    hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, prm->rho, (const double2 *)chi,
+                       prm->rho * c0, (const double2 *)(BIN + nel), prm->rho, n, (const double *)om_dev, X + nel,
+                       2 * nel, (double2 *)gpsi);
+    BRI_HIP_CHECK(hipGetLastError());
+    // X applied to all 2n shift solutions
+    StencilArgs ax = a;
+    ax.ncol = 2 * n;
+    ax.in = X;
+    ax.out = XAB;
+    rc = stencil_launch(ax, BRI_F64, false, EPI_PLAIN, default_config(g, BRI_F64, 2 * n), s);
+    if (rc != BRI_OK) return rc;
+    PairTable pt;
+    std::memset(&pt, 0, sizeof(pt));
+    pt.n = 1 + 2 * n;
+    pt.u[0] = (const double2 *)chi;
+    pt.v[0] = Y;
+    pt.w[0] = prm->rho;
+    for (int i = 0; i < n; ++i) {
+        // (X a_i, b_i) and (X b_i, a_i), weight -rho omega_i
+        pt.u[1 + 2 * i] = XAB + (size_t)(2 * i) * nel;
+        pt.v[1 + 2 * i] = X + (size_t)(2 * i + 1) * nel;
+        pt.w[1 + 2 * i] = -prm->rho * om[i];
+        pt.u[2 + 2 * i] = XAB + (size_t)(2 * i + 1) * nel;
+        pt.v[2 + 2 * i] = X + (size_t)(2 * i) * nel;
+        pt.w[2 + 2 * i] = -prm->rho * om[i];
+    }
+    rc = force_from_pairs(g, (const double2 *)U, (const double2 *)W64, pt, G, (double *)F, (double2 *)GU, s);
+    if (rc != BRI_OK) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return BRI_EHIP;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iters = fin.iter;
+        for (int i = 0; i < n; ++i) {
+            stats->shift_iters[i] = fin.conv_iter[i] ? fin.conv_iter[i] : fin.iter;
+            stats->rel_resid[i] = fin.conv_iter[i] ? fin.conv_res[i] : -1.0;
+        }
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rcs;
+}
+
+}  // extern "C"

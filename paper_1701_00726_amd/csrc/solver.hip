@@ -732,6 +732,47 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     return result;
 }
 
+// FP64 multi-shift solve of (A + sigma_i) x_i = b over the Kenney-Laub shifts with every
+// x_i kept, [shift][ncol][12 V] inside the workspace (the gradient needs the individual
+// shift solutions).  With work == NULL only *need is set.
+int ov_solve_shifts(const Geom &g, const void *W64, const ov_params *prm, const void *b, int ncol, void *work,
+                    size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ColState *last) {
+    const int n = prm->kl_n;
+    if (n < 1 || n > MAXS || ncol < 1) return BRI_EINVAL;
+    MsSolve m;
+    m.g = g;
+    m.prec = BRI_F64;
+    m.W = W64;
+    m.m0 = -prm->rho;
+    m.ncol = ncol;
+    m.nshift = n;
+    m.store_x = true;
+    double om[MAXS], sg[MAXS];
+    kl_coeffs(n, &m.c0, om, sg);
+    m.omega.assign(om, om + n);
+    m.sigma.resize((size_t)ncol * n);
+    for (int c = 0; c < ncol; ++c)
+        for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];
+    m.tol = prm->tol;
+    m.max_iter = prm->max_iter;
+    Arena ar(work);
+    m.carve(ar);
+    if (!work) {
+        if (need) *need = ar.used;
+        return BRI_OK;
+    }
+    if (work_bytes < ar.used || !W64 || !b || !x_out) return BRI_EINVAL;
+    int *hflag = nullptr;
+    BRI_HIP_CHECK(hipHostMalloc((void **)&hflag, sizeof(int), hipHostMallocDefault));
+    RunStats rs;
+    const int rc = ms_run(m, b, true, s, hflag, rs);
+    (void)hipHostFree(hflag);
+    if (rc != BRI_OK) return rc;
+    *x_out = m.x;
+    if (last && !rs.fin.empty()) *last = rs.fin.back();
+    return rs.status;
+}
+
 }  // namespace bri
 
 extern "C" {

@@ -91,3 +91,35 @@ def test_invalid_stencil_arguments():
     assert lib.bri_build_links(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 5, None) == bri.EINVAL
     g.tbc = 2
     assert lib.bri_build_links(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None) == bri.EINVAL
+
+
+def test_gradient_workspace_and_invalid_arguments():
+    lib = bri.load()
+    L = (8, 8, 8, 8)
+    V = 8**4
+    g = bri._geom(L)
+    nb = ctypes.c_size_t(0)
+    w = (ctypes.c_double * 1)(1.0)
+    assert lib.bri_link_grad(ctypes.byref(g), None, None, 1, w, None, None, None, None, None, ctypes.byref(nb),
+                             None) == bri.OK
+    assert nb.value == 81 * 9 * V * 16  # one 3x3 complex double per site and displacement
+    for npairs in (0, bri.MAX_PAIRS + 1):
+        assert lib.bri_link_grad(ctypes.byref(g), None, None, npairs, w, None, None, None, None, None,
+                                 ctypes.byref(nb), None) == bri.EINVAL
+    # neither F nor GU requested: rejected before any launch
+    nb2 = ctypes.c_size_t(1 << 40)
+    assert lib.bri_link_grad(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, w, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), None, None, ctypes.c_void_p(16), ctypes.byref(nb2),
+                             None) == bri.EINVAL
+    prm = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0)
+    assert lib.ov_apply_grad(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, None, None, None, None,
+                             ctypes.byref(nb), None, None) == bri.OK
+    # G, the 2n applied shift solutions, [psi | X^dag chi], y, and the two-column multi-shift
+    # (r, p, t: 3 x 2 columns; x: 8 x 2; shifted directions: 7 x 2)
+    vec = 12 * V * 16
+    assert 81 * 9 * V * 16 + vec * (16 + 2 + 1 + 6 + 16 + 14) <= nb.value
+    assert nb.value < 81 * 9 * V * 16 + vec * (16 + 2 + 1 + 6 + 16 + 14) + (1 << 20)
+    for bad in (bri._OvParams(8, 1.0, 1e-10, 100, 1, 0), bri._OvParams(0, 1.0, 1e-10, 100, 0, 0),
+                bri._OvParams(8, 2.0, 1e-10, 100, 0, 0)):
+        assert lib.ov_apply_grad(ctypes.byref(g), None, None, ctypes.byref(bad), None, None, None, None, None, None,
+                                 ctypes.byref(nb), None, None) == bri.EINVAL
