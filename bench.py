@@ -357,6 +357,15 @@ def main():
                                       "max_rel_err_vs_fp64": max(errs)}
             del opm, opm12, Wlo
             torch.cuda.empty_cache()
+        # gradient of Re chi^dag D_ov psi (force on the links and D_ov^dag chi), FP64
+        chi = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED + 1), bri.F64, dev)
+        op.grad(U, chi[0], b[0])
+        ms_g = timed(lambda: op.grad(U, chi[0], b[0]), 2)
+        pairs = [(1.0, chi[0], b[0])] * (2 * KL_N + 1)
+        bri.link_grad(L, U, W, pairs)
+        ms_f = timed(lambda: bri.link_grad(L, U, W, pairs), 3)
+        extra["grad_fp64_1src"] = {"ms_per_call": ms_g, "ratio_to_step": ms_g / ms_step,
+                                   "link_force_ms_%d_pairs" % (2 * KL_N + 1): ms_f}
         best_mixed = max(extra[k]["applies_per_s"] for k in extra if k.startswith("mixed"))
         extra["fp64_1src_applies_per_s"] = value
         extra["speedup_batched_fp64_vs_fp64_1src"] = extra["batched_fp64_12src"]["applies_per_s"] / value

@@ -228,20 +228,24 @@ int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs
  *   dS = rho Re[chi^dag dX y] - rho sum_i omega_i Re[(X a_i)^dag dX b_i + (X b_i)^dag dX a_i],
  *   gpsi = D_ov^dag chi = rho (chi + c0 X^dag chi + sum_i omega_i b_i)
  *        (= dS/dRe psi + i dS/dIm psi).
- * The a_i and b_i come from one FP64 two-column multi-shift solve (params->inner
- * must be BRI_F64; max_refine is ignored).
+ * The a_i and b_i come from one two-column multi-shift solve that keeps every
+ * shift solution: in FP64 (params->inner = BRI_F64), or in low precision on Wlo
+ * with every (shift, column) refined against its FP64 residual to params->tol,
+ * as ov_apply does (at most max_refine passes).
  *   U, W64  as bri_link_grad (W64 built from U with geom->tbc)
+ *   Wlo     links in precision params->inner; NULL when inner = BRI_F64
  *   chi, psi, gpsi  [4][3][V] complex double
  *   F, GU   as bri_link_grad (at least one non-NULL)
  *   work, work_bytes  device workspace (query with work == NULL)
- *   stats   may be NULL: iterations and the stopping residual of each shift
+ *   stats   may be NULL: iterations, refinement passes and the final residual of
+ *           each shift (worst of the two columns)
  * Synchronises `stream`.  Returns BRI_ENOCONV when a shift missed tol within
  * max_iter (the outputs then use the last iterates), BRI_ENAN on a non-finite
  * residual, BRI_EINVAL for bad arguments (V must be a multiple of 64).
  */
-int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov_params *params, const void *chi,
-                  const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes, ov_stats *stats,
-                  void *stream);
+int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const void *Wlo, const ov_params *params,
+                  const void *chi, const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes,
+                  ov_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

@@ -124,7 +124,7 @@ def load():
             lib.bri_get_stencil_cfg.argtypes = [G, I, I, SC]
             SZ = ctypes.POINTER(ctypes.c_size_t)
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
-            lib.ov_apply_grad.argtypes = [G, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
+            lib.ov_apply_grad.argtypes = [G, P, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
                                           ctypes.POINTER(_OvStats), P]
             for fn in EXPORTS:
                 getattr(lib, fn).restype = I
@@ -332,16 +332,15 @@ class OverlapOp:
         return self._run("ov_sign_apply", psi, out, stream, allow_noconv)
 
     def grad(self, U, chi, psi, force=True, link_grad=False, stream=None, allow_noconv=False):
-        """Gradient of S = Re chi^dag D_ov psi for one right-hand side (FP64 only).
+        """Gradient of S = Re chi^dag D_ov psi for one right-hand side.
 
         U is the (4, 3, 3, V) complex128 field W64 was built from (with this
-        operator's tbc).  Returns (F or None, GU or None, grad_psi, OvStats) with
+        operator's tbc).  The shift solves run in this operator's inner precision
+        (low-precision inner solves are refined to tol in FP64).  Returns (F or None, GU or None, grad_psi, OvStats) with
         F (4, 8, V) the force, GU (4, 3, 3, V) = dS/dRe U + i dS/dIm U and
         grad_psi = D_ov^dag chi of the shape of psi."""
         torch = _torch()
         V = int(np.prod(self.L))
-        if self.params.inner != F64:
-            raise ValueError("the gradient runs its shift solves in FP64 (inner = F64)")
         for name, t in (("chi", chi), ("psi", psi)):
             if t.dtype != torch.complex128 or t.numel() != 12 * V:
                 raise ValueError(f"{name} must be complex128 with 12 V elements")
@@ -351,9 +350,9 @@ class OverlapOp:
             raise ValueError("ask for the force, the link gradient or both")
         if getattr(self, "_gwork", None) is None:
             nb = ctypes.c_size_t(0)
-            _check("ov_apply_grad", load().ov_apply_grad(ctypes.byref(self.g), None, None, ctypes.byref(self.params),
-                                                         None, None, None, None, None, None, ctypes.byref(nb), None,
-                                                         None))
+            _check("ov_apply_grad", load().ov_apply_grad(ctypes.byref(self.g), None, None, None,
+                                                         ctypes.byref(self.params), None, None, None, None, None, None,
+                                                         ctypes.byref(nb), None, None))
             self._gwork = torch.empty(int(nb.value), dtype=torch.uint8, device=self.W64.device)
         F = torch.empty((4, 8, V), dtype=torch.float64, device=U.device) if force else None
         GU = torch.empty_like(U) if link_grad else None
@@ -361,7 +360,8 @@ class OverlapOp:
         stats = _OvStats()
         wb = ctypes.c_size_t(self._gwork.numel())
         st = load().ov_apply_grad(
-            ctypes.byref(self.g), _dptr(U), _dptr(self.W64), ctypes.byref(self.params), _dptr(chi), _dptr(psi),
+            ctypes.byref(self.g), _dptr(U), _dptr(self.W64), None if self.Wlo is None else _dptr(self.Wlo),
+            ctypes.byref(self.params), _dptr(chi), _dptr(psi),
             None if F is None else _dptr(F), None if GU is None else _dptr(GU), _dptr(gpsi), _dptr(self._gwork),
             ctypes.byref(wb), ctypes.byref(stats), _stream(stream),
         )

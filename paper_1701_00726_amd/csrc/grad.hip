@@ -32,10 +32,10 @@
 
 namespace bri {
 
-// FP64 multi-shift solve of (A + sigma_i) x = b over the Kenney-Laub shifts, every x kept
-// ([shift][ncol][12 V] in the workspace); with work == NULL only *need is set.
-int ov_solve_shifts(const Geom &g, const void *W64, const ov_params *prm, const void *b, int ncol, void *work,
-                    size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ColState *last);
+// Multi-shift solve of (A + sigma_i) x = b over the Kenney-Laub shifts, every x kept in FP64
+// ([shift][ncol][12 V] in the workspace); with work == NULL only *need is set (solver.hip).
+int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_params *prm, const void *b, int ncol,
+                    void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st);
 
 __device__ __forceinline__ int dj(int j, int mu) { return disp_comp(j, mu); }
 
@@ -107,57 +107,112 @@ struct PairTable {
     int n;
 };
 
-// G[j][a][b](x) = sum_p w_p sum_t conj((S_d u_p(x))_{t,a}) v_p(x+d)_{t,b}, all d != 0
-__global__ __launch_bounds__(128) void grad_outer_kernel(Geom g, PairTable pt, double2 *__restrict__ G) {
-    const unsigned x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= (unsigned)g.V) return;
+// G[j][a][b](x) = sum_p w_p sum_t conj((S_d u_p(x))_{t,a}) v_p(x+d)_{t,b}, all d != 0.
+// A workgroup owns 64 consecutive sites and 8 of the 80 displacements (the block index modulo
+// the group count picks which 8, so the ten groups of a tile are dispatched side by side);
+// each wave keeps the 3x3 accumulators of 2 displacements in registers while the pairs stream
+// through, so u_p(x) and the neighbourhood of v_p are read while hot in L2 (a pass per
+// displacement would stream every pair from HBM 80 times).
+constexpr int OUTER_WAVES = 4;
+constexpr int OUTER_PER_WAVE = 2;
+constexpr int OUTER_GROUPS = 80 / (OUTER_WAVES * OUTER_PER_WAVE);
+
+__global__ __launch_bounds__(64 * OUTER_WAVES) void grad_outer_kernel(Geom g, PairTable pt,
+                                                                      double2 *__restrict__ G) {
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned grp = blockIdx.x % OUTER_GROUPS;
+    const unsigned x = (blockIdx.x / OUTER_GROUPS) * 64 + lane;
+    const bool live = x < (unsigned)g.V;
     const size_t V = (size_t)g.V;
+    const int jbase = (grp * OUTER_WAVES + w) * OUTER_PER_WAVE;
     int cx[4];
     {
-        int s = (int)x;
+        int s = live ? (int)x : 0;
         for (int mu = 0; mu < 4; ++mu) {
             cx[mu] = s % g.L[mu];
             s /= g.L[mu];
         }
     }
-    for (int j = 0; j < 81; ++j) {
-        if (j == 40) continue;
+    unsigned ys[OUTER_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < OUTER_PER_WAVE; ++i) {
+        const int jj = jbase + i;
+        const int j = jj < 40 ? jj : jj + 1;
         int cy[4];
+#pragma unroll
         for (int mu = 0; mu < 4; ++mu) cy[mu] = wrapc(cx[mu] + dj(j, mu), g.L[mu]);
-        const unsigned ys = site_of(g, cy);
-        const DirW<double, false> dw(j);  // S_d = a_k + c_k sum d_mu gamma_mu for d = disp(j)
-        const double a = dw.a, c0 = dw.c0, c1 = dw.c1, c2 = dw.c2, c3 = dw.c3;
-        double2 acc[3][3];
-        for (int p = 0; p < 3; ++p)
-            for (int q = 0; q < 3; ++q) acc[p][q] = make_double2(0.0, 0.0);
-        for (int p = 0; p < pt.n; ++p) {
-            double2 u[4][3], e[4][3];
+        ys[i] = site_of(g, cy);
+    }
+    double2 acc[OUTER_PER_WAVE][3][3];
+#pragma unroll
+    for (int i = 0; i < OUTER_PER_WAVE; ++i)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[i][a][b] = make_double2(0.0, 0.0);
+    if (!live) return;
+    for (int p = 0; p < pt.n; ++p) {
+        const double2 *__restrict__ up = pt.u[p];
+        const double2 *__restrict__ vp = pt.v[p];
+        const double wp = pt.w[p];
+        double2 u[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double2 t = up[(size_t)(s * 3 + c) * V + x];
+                u[s][c] = make_double2(wp * t.x, wp * t.y);
+            }
+#pragma unroll
+        for (int i = 0; i < OUTER_PER_WAVE; ++i) {
+            const int jj = jbase + i;
+            const DirW<double, false> dw(jj < 40 ? jj : jj + 1);  // S_d = a_k + c_k sum d_mu gamma_mu
+            double2 e[4][3];
+#pragma unroll
             for (int s = 0; s < 4; ++s)
-                for (int c = 0; c < 3; ++c) {
-                    u[s][c] = pt.u[p][(size_t)(s * 3 + c) * V + x];
-                    e[s][c] = make_double2(0.0, 0.0);
-                }
-            spin_accumulate(e, u, a, c0, c1, c2, c3);  // e = S_d u
-            const double wp = pt.w[p];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) e[s][c] = make_double2(0.0, 0.0);
+            spin_accumulate(e, u, dw.a, dw.c0, dw.c1, dw.c2, dw.c3);  // e = w_p S_d u
+#pragma unroll
             for (int t = 0; t < 4; ++t)
+#pragma unroll
                 for (int bb = 0; bb < 3; ++bb) {
-                    const double2 v = pt.v[p][(size_t)(t * 3 + bb) * V + ys];
+                    const double2 v = vp[(size_t)(t * 3 + bb) * V + ys[i]];
+#pragma unroll
                     for (int aa = 0; aa < 3; ++aa) {
-                        const double2 ce = make_double2(wp * e[t][aa].x, -wp * e[t][aa].y);
-                        const double2 m = cmul(ce, v);
-                        acc[aa][bb].x += m.x;
-                        acc[aa][bb].y += m.y;
+                        // acc += conj(e) v
+                        acc[i][aa][bb].x += e[t][aa].x * v.x + e[t][aa].y * v.y;
+                        acc[i][aa][bb].y += e[t][aa].x * v.y - e[t][aa].y * v.x;
                     }
                 }
+            // keep the scheduler from hoisting the next displacement's loads above this one
+            __builtin_amdgcn_sched_barrier(0);
         }
+    }
+#pragma unroll
+    for (int i = 0; i < OUTER_PER_WAVE; ++i) {
+        const int jj = jbase + i;
+        const int j = jj < 40 ? jj : jj + 1;
+#pragma unroll
         for (int aa = 0; aa < 3; ++aa)
-            for (int bb = 0; bb < 3; ++bb) G[((size_t)j * 9 + aa * 3 + bb) * V + x] = acc[aa][bb];
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) G[((size_t)j * 9 + aa * 3 + bb) * V + x] = acc[i][aa][bb];
     }
 }
 
-// Level k -> k-1 in gather form: G_r(y) += (1/k) T^T G_d(x), d = r + s e_mu, x = y - s e_mu.
-__global__ __launch_bounds__(128) void grad_level_kernel(Geom g, const double2 *__restrict__ U, double2 *__restrict__ G, int k) {
-    const unsigned y = blockIdx.x * blockDim.x + threadIdx.x;
+// Displacement indices with a given number of hops (8, 24, 32 or 16 of them).
+struct HopDirs {
+    int n;
+    int j[32];
+};
+
+// Level k -> k-1 in gather form: G_r(y) += (1/k) T^T G_d(x), d = r + s e_mu, x = y - s e_mu;
+// one thread per (site, (k-1)-hop displacement r).  r is the fastest-varying part of the block
+// index, so the children of one parent entry run together and share its L2 line.
+__global__ __launch_bounds__(128) void grad_level_kernel(Geom g, const double2 *__restrict__ U, double2 *__restrict__ G,
+                                                         int k, HopDirs lower) {
+    const unsigned y = (blockIdx.x / lower.n) * blockDim.x + threadIdx.x;
     if (y >= (unsigned)g.V) return;
     const size_t V = (size_t)g.V;
     int cy[4];
@@ -169,13 +224,10 @@ __global__ __launch_bounds__(128) void grad_level_kernel(Geom g, const double2 *
         }
     }
     const double invk = 1.0 / (double)k;
-    for (int jr = 0; jr < 81; ++jr) {
-        int r[4], nh = 0;
-        for (int mu = 0; mu < 4; ++mu) {
-            r[mu] = dj(jr, mu);
-            nh += r[mu] != 0;
-        }
-        if (nh != k - 1 || nh == 0) continue;
+    {
+        const int jr = lower.j[blockIdx.x % lower.n];
+        int r[4];
+        for (int mu = 0; mu < 4; ++mu) r[mu] = dj(jr, mu);
         double2 acc[3][3];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) acc[a][b] = G[((size_t)jr * 9 + a * 3 + b) * V + y];
@@ -211,9 +263,10 @@ __global__ __launch_bounds__(128) void grad_level_kernel(Geom g, const double2 *
 }
 
 // G_U_mu(z) from every level's first step, then F^a_mu(z) = -Im tr(lambda_a U G_U^T) / 2
-__global__ __launch_bounds__(128) void grad_force_kernel(Geom g, const double2 *__restrict__ U, const double2 *__restrict__ W,
-                                  const double2 *__restrict__ G, double *__restrict__ F, double2 *__restrict__ GUo) {
-    const unsigned z = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(128) void grad_force_kernel(Geom g, const double2 *__restrict__ U,
+                                                         const double2 *__restrict__ W, const double2 *__restrict__ G,
+                                                         double *__restrict__ F, double2 *__restrict__ GUo) {
+    const unsigned z = (blockIdx.x >> 2) * blockDim.x + threadIdx.x;
     if (z >= (unsigned)g.V) return;
     const size_t V = (size_t)g.V;
     int cz[4];
@@ -224,7 +277,8 @@ __global__ __launch_bounds__(128) void grad_force_kernel(Geom g, const double2 *
             s /= g.L[mu];
         }
     }
-    for (int mu = 0; mu < 4; ++mu) {
+    {
+        const int mu = blockIdx.x & 3;  // one thread per (site, link direction); mu varies fastest
         double2 GU[3][3];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) GU[a][b] = make_double2(0.0, 0.0);
@@ -340,9 +394,18 @@ static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, c
                             double *F, double2 *GU, hipStream_t s) {
     const int threads = 128;
     const int blocks = (g.V + threads - 1) / threads;
-    hipLaunchKernelGGL(grad_outer_kernel, dim3(blocks), dim3(threads), 0, s, g, pt, G);
-    for (int k = 4; k >= 2; --k) hipLaunchKernelGGL(grad_level_kernel, dim3(blocks), dim3(threads), 0, s, g, U, G, k);
-    hipLaunchKernelGGL(grad_force_kernel, dim3(blocks), dim3(threads), 0, s, g, U, W, G, F, GU);
+    hipLaunchKernelGGL(grad_outer_kernel, dim3(OUTER_GROUPS * ((g.V + 63) / 64)), dim3(64 * OUTER_WAVES), 0, s, g,
+                       pt, G);
+    for (int k = 4; k >= 2; --k) {
+        HopDirs lower{};
+        for (int j = 0; j < 81; ++j) {
+            int nh = 0;
+            for (int r = j, mu = 0; mu < 4; ++mu, r /= 3) nh += (r % 3) != 1;
+            if (nh == k - 1) lower.j[lower.n++] = j;
+        }
+        hipLaunchKernelGGL(grad_level_kernel, dim3(lower.n * blocks), dim3(threads), 0, s, g, U, G, k, lower);
+    }
+    hipLaunchKernelGGL(grad_force_kernel, dim3(4 * blocks), dim3(threads), 0, s, g, U, W, G, F, GU);
     return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
 }
 
@@ -357,7 +420,8 @@ static int plan_grad(const Geom &g, const ov_params *prm, GradPlan &pl) {
     const int n = prm->kl_n;
     size_t solver_need = 0;
     void *xdummy = nullptr;
-    const int rc = ov_solve_shifts(g, nullptr, prm, nullptr, 2, nullptr, 0, &solver_need, nullptr, &xdummy, nullptr);
+    const int rc =
+        ov_solve_shifts(g, nullptr, nullptr, prm, nullptr, 2, nullptr, 0, &solver_need, nullptr, &xdummy, nullptr);
     if (rc != BRI_OK) return rc;
     size_t off = 0;
     pl.g_off = off;
@@ -407,9 +471,9 @@ int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs
                             (double2 *)GU, (hipStream_t)stream);
 }
 
-int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov_params *prm, const void *chi,
-                  const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes, ov_stats *stats,
-                  void *stream) {
+int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const void *Wlo, const ov_params *prm,
+                  const void *chi, const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes,
+                  ov_stats *stats, void *stream) {
     using namespace bri;
     const auto t0 = std::chrono::steady_clock::now();
     Geom g;
@@ -418,8 +482,10 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov
     if (!prm || !work_bytes) return BRI_EINVAL;
     const int n = prm->kl_n;
     if (n < 1 || n > MAXS || !(prm->rho > 0.0 && prm->rho < 2.0) || !(prm->tol > 0.0) || prm->max_iter < 1 ||
-        prm->inner != BRI_F64 || g.V % 64)
+        g.V % 64)
         return BRI_EINVAL;
+    if (prm->inner != BRI_F64 && prm->inner != BRI_F32 && prm->inner != BRI_F32_BF16W) return BRI_EINVAL;
+    if (prm->max_refine < 0 || prm->max_refine > 100) return BRI_EINVAL;
     GradPlan pl;
     rc = plan_grad(g, prm, pl);
     if (rc != BRI_OK) return rc;
@@ -427,7 +493,9 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov
         *work_bytes = pl.bytes;
         return BRI_OK;
     }
-    if (*work_bytes < pl.bytes || !U || !W64 || !chi || !psi || (!F && !GU) || !gpsi) return BRI_EINVAL;
+    if (*work_bytes < pl.bytes || !U || !W64 || !chi || !psi || (!F && !GU) || !gpsi ||
+        (prm->inner != BRI_F64 && !Wlo))
+        return BRI_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const size_t nel = (size_t)12 * g.V;
     char *base = (char *)work;
@@ -453,8 +521,8 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov
     // a_i = (A + sigma_i)^{-1} psi and b_i = (A + sigma_i)^{-1} X^dag chi in one two-column multi-shift
     // solve; X holds them as [i][2][12 V], i.e. a_i = X[2 i], b_i = X[2 i + 1]
     void *xs = nullptr;
-    ColState fin;
-    int rcs = ov_solve_shifts(g, W64, prm, BIN, 2, swork, pl.solver_bytes, nullptr, s, &xs, &fin);
+    ov_stats sst;
+    int rcs = ov_solve_shifts(g, W64, Wlo, prm, BIN, 2, swork, pl.solver_bytes, nullptr, s, &xs, &sst);
     if (rcs != BRI_OK && rcs != BRI_ENOCONV) return rcs;
     const double2 *X = (const double2 *)xs;
     double c0, om[MAXS], sg[MAXS];
@@ -493,12 +561,7 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const ov
     if (rc != BRI_OK) return rc;
     if (hipStreamSynchronize(s) != hipSuccess) return BRI_EHIP;
     if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->iters = fin.iter;
-        for (int i = 0; i < n; ++i) {
-            stats->shift_iters[i] = fin.conv_iter[i] ? fin.conv_iter[i] : fin.iter;
-            stats->rel_resid[i] = fin.conv_iter[i] ? fin.conv_res[i] : -1.0;
-        }
+        *stats = sst;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return rcs;

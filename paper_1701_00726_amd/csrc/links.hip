@@ -19,10 +19,19 @@ __device__ __forceinline__ int site_index(const Geom &g, const int c[4]) {
     return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }
 
-__global__ void build_level_kernel(Geom g, const double2 *__restrict__ U, double2 *__restrict__ W, int k) {
+// Stored directions j < 40 with k non-zero components, per level k = 1..4 (4, 12, 16, 8 of them).
+struct LevelDirs {
+    int n;
+    int j[16];
+};
+
+// One thread per (site, stored direction of level k): blockIdx.y picks the direction.
+__global__ __launch_bounds__(128) void build_level_kernel(Geom g, const double2 *__restrict__ U,
+                                                          double2 *__restrict__ W, int k, LevelDirs dirs) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= g.V) return;
     const size_t V = (size_t)g.V;
+    const int j = dirs.j[blockIdx.y];
     int cx[4];
     {
         int s = x;
@@ -31,80 +40,73 @@ __global__ void build_level_kernel(Geom g, const double2 *__restrict__ U, double
             s /= g.L[mu];
         }
     }
-    for (int j = 0; j < 40; ++j) {
-        int d[4], nh = 0;
-        for (int mu = 0; mu < 4; ++mu) {
-            d[mu] = disp_comp(j, mu);
-            nh += d[mu] != 0;
-        }
-        if (nh != k) continue;
-        double2 acc[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) acc[a][b] = make_double2(0.0, 0.0);
-        for (int mu = 0; mu < 4; ++mu) {
-            if (d[mu] == 0) continue;
-            const int s = d[mu];
-            // first step T_mu(x)
-            double2 T[3][3];
-            double sgn = 1.0;
-            if (s > 0) {
-                const int xs = x;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) T[a][b] = U[((size_t)(mu * 3 + a) * 3 + b) * V + xs];
-                if (g.tbc && mu == 3 && cx[3] == g.L[3] - 1) sgn = -1.0;
-            } else {
-                int cm[4] = {cx[0], cx[1], cx[2], cx[3]};
-                cm[mu] = wrap(cm[mu] - 1, g.L[mu]);
-                const int xs = site_index(g, cm);
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) {
-                        double2 u = U[((size_t)(mu * 3 + b) * 3 + a) * V + xs];
-                        T[a][b] = make_double2(u.x, -u.y);
-                    }
-                if (g.tbc && mu == 3 && cx[3] == 0) sgn = -1.0;
-            }
-            // remainder W_{d - s e_mu}(x + s e_mu)
-            int cy[4] = {cx[0], cx[1], cx[2], cx[3]};
-            cy[mu] = wrap(cy[mu] + s, g.L[mu]);
-            int dr[4] = {d[0], d[1], d[2], d[3]};
-            dr[mu] = 0;
-            double2 M[3][3];
-            if (k == 1) {
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) M[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
-            } else {
-                const int jr = (dr[0] + 1) + 3 * (dr[1] + 1) + 9 * (dr[2] + 1) + 27 * (dr[3] + 1);
-                if (jr < 40) {
-                    const int ys = site_index(g, cy);
-                    for (int a = 0; a < 3; ++a)
-                        for (int b = 0; b < 3; ++b) M[a][b] = W[((size_t)jr * 9 + a * 3 + b) * V + ys];
-                } else {
-                    // W_{dr}(y) = W_{-dr}(y + dr)^dag, -dr stored at index 80 - jr
-                    int cz[4];
-                    for (int nu = 0; nu < 4; ++nu) cz[nu] = wrap(cy[nu] + dr[nu], g.L[nu]);
-                    const int zs = site_index(g, cz);
-                    for (int a = 0; a < 3; ++a)
-                        for (int b = 0; b < 3; ++b) {
-                            double2 w = W[((size_t)(80 - jr) * 9 + b * 3 + a) * V + zs];
-                            M[a][b] = make_double2(w.x, -w.y);
-                        }
-                }
-            }
+    int d[4];
+    for (int mu = 0; mu < 4; ++mu) d[mu] = disp_comp(j, mu);
+    double2 acc[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int mu = 0; mu < 4; ++mu) {
+        if (d[mu] == 0) continue;
+        const int s = d[mu];
+        // first step T_mu(x)
+        double2 T[3][3];
+        double sgn = 1.0;
+        if (s > 0) {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) T[a][b] = U[((size_t)(mu * 3 + a) * 3 + b) * V + x];
+            if (g.tbc && mu == 3 && cx[3] == g.L[3] - 1) sgn = -1.0;
+        } else {
+            int cm[4] = {cx[0], cx[1], cx[2], cx[3]};
+            cm[mu] = wrap(cm[mu] - 1, g.L[mu]);
+            const int xs = site_index(g, cm);
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
-                    double2 t = make_double2(0.0, 0.0);
-                    for (int c = 0; c < 3; ++c) cmac(t, T[a][c], M[c][b]);
-                    acc[a][b].x = fma(sgn, t.x, acc[a][b].x);
-                    acc[a][b].y = fma(sgn, t.y, acc[a][b].y);
+                    double2 u = U[((size_t)(mu * 3 + b) * 3 + a) * V + xs];
+                    T[a][b] = make_double2(u.x, -u.y);
                 }
+            if (g.tbc && mu == 3 && cx[3] == 0) sgn = -1.0;
         }
-        const double inv_k = 1.0 / (double)k;
+        // remainder W_{d - s e_mu}(x + s e_mu)
+        int cy[4] = {cx[0], cx[1], cx[2], cx[3]};
+        cy[mu] = wrap(cy[mu] + s, g.L[mu]);
+        int dr[4] = {d[0], d[1], d[2], d[3]};
+        dr[mu] = 0;
+        double2 M[3][3];
+        if (k == 1) {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) M[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+        } else {
+            const int jr = (dr[0] + 1) + 3 * (dr[1] + 1) + 9 * (dr[2] + 1) + 27 * (dr[3] + 1);
+            if (jr < 40) {
+                const int ys = site_index(g, cy);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) M[a][b] = W[((size_t)jr * 9 + a * 3 + b) * V + ys];
+            } else {
+                // W_{dr}(y) = W_{-dr}(y + dr)^dag, -dr stored at index 80 - jr
+                int cz[4];
+                for (int nu = 0; nu < 4; ++nu) cz[nu] = wrap(cy[nu] + dr[nu], g.L[nu]);
+                const int zs = site_index(g, cz);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double2 w = W[((size_t)(80 - jr) * 9 + b * 3 + a) * V + zs];
+                        M[a][b] = make_double2(w.x, -w.y);
+                    }
+            }
+        }
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
-                double2 v = acc[a][b];
-                W[((size_t)j * 9 + a * 3 + b) * V + x] = make_double2(v.x * inv_k, v.y * inv_k);
+                double2 t = make_double2(0.0, 0.0);
+                for (int c = 0; c < 3; ++c) cmac(t, T[a][c], M[c][b]);
+                acc[a][b].x = fma(sgn, t.x, acc[a][b].x);
+                acc[a][b].y = fma(sgn, t.y, acc[a][b].y);
             }
     }
+    const double inv_k = 1.0 / (double)k;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double2 v = acc[a][b];
+            W[((size_t)j * 9 + a * 3 + b) * V + x] = make_double2(v.x * inv_k, v.y * inv_k);
+        }
 }
 
 __global__ void convert_f32_kernel(size_t n, const double2 *__restrict__ src, float2 *__restrict__ dst) {
@@ -143,7 +145,13 @@ int build_links_f64(const Geom &g, const double2 *U, double2 *W, hipStream_t st)
     const int threads = 128;
     const int blocks = (g.V + threads - 1) / threads;
     for (int k = 1; k <= 4; ++k) {
-        hipLaunchKernelGGL(build_level_kernel, dim3(blocks), dim3(threads), 0, st, g, U, W, k);
+        LevelDirs dirs{};
+        for (int j = 0; j < 40; ++j) {
+            int nh = 0;
+            for (int r = j, mu = 0; mu < 4; ++mu, r /= 3) nh += (r % 3) != 1;
+            if (nh == k) dirs.j[dirs.n++] = j;
+        }
+        hipLaunchKernelGGL(build_level_kernel, dim3(blocks, dirs.n), dim3(threads), 0, st, g, U, W, k, dirs);
         BRI_HIP_CHECK(hipGetLastError());
     }
     return BRI_OK;

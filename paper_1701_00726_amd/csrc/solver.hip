@@ -217,9 +217,14 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
 // column c = blockIdx.y:
 //   y += sum_sigma omega alpha^sigma p^sigma   (or x^sigma += alpha^sigma p^sigma)
 //   p^sigma = zeta^sigma r + beta^sigma p^sigma,  p = r + beta p
+// The shifted directions are streamed UPD_BATCH at a time: all loads of a batch are issued
+// before any store, so the independent streams overlap in flight.
+constexpr int UPD_BATCH = 8;
+
 template <typename C>
-__global__ void ms_update_kernel(const ColState *__restrict__ states, size_t n, int ncol, const C *__restrict__ r,
-                                 C *__restrict__ p, C *__restrict__ y, C *__restrict__ x, C *__restrict__ ps) {
+__global__ __launch_bounds__(256) void ms_update_kernel(const ColState *__restrict__ states, size_t n, int ncol,
+                                                        const C *__restrict__ r, C *__restrict__ p,
+                                                        C *__restrict__ y, C *__restrict__ x, C *__restrict__ ps) {
     const int col = blockIdx.y;
     const ColState *st = states + col;
     const int done = st->done;
@@ -232,27 +237,36 @@ __global__ void ms_update_kernel(const ColState *__restrict__ states, size_t n, 
         C pi = p[off + i];
         C yi;
         if (y) yi = y[off + i];
-        for (int k = 0; k < ns; ++k) {
-            if (!st->upd_x[k]) continue;
-            C *pk = k == 0 ? nullptr : ps + ((size_t)(k - 1) * ncol + col) * n;
-            C v = k == 0 ? pi : pk[i];
-            const double as = st->alpha_s[k];
-            if (y) {
-                const double w = st->omega[k] * as;
-                yi.x += w * v.x;
-                yi.y += w * v.y;
-            } else {
-                C *xk = x + ((size_t)k * ncol + col) * n;
-                C xv = xk[i];
-                xv.x += as * v.x;
-                xv.y += as * v.y;
-                xk[i] = xv;
+        for (int k0 = 0; k0 < ns; k0 += UPD_BATCH) {
+            C v[UPD_BATCH], xv[UPD_BATCH];
+#pragma unroll
+            for (int b = 0; b < UPD_BATCH; ++b) {
+                const int k = k0 + b;
+                if (k >= ns || !st->upd_x[k]) continue;
+                v[b] = k == 0 ? pi : ps[((size_t)(k - 1) * ncol + col) * n + i];
+                if (!y) xv[b] = x[((size_t)k * ncol + col) * n + i];
             }
-            if (k > 0 && st->active[k]) {
-                const double z = st->zeta[k], bs = st->beta_s[k];
-                v.x = z * ri.x + bs * v.x;
-                v.y = z * ri.y + bs * v.y;
-                pk[i] = v;
+#pragma unroll
+            for (int b = 0; b < UPD_BATCH; ++b) {
+                const int k = k0 + b;
+                if (k >= ns || !st->upd_x[k]) continue;
+                const double as = st->alpha_s[k];
+                if (y) {
+                    const double w = st->omega[k] * as;
+                    yi.x += w * v[b].x;
+                    yi.y += w * v[b].y;
+                } else {
+                    xv[b].x += as * v[b].x;
+                    xv[b].y += as * v[b].y;
+                    x[((size_t)k * ncol + col) * n + i] = xv[b];
+                }
+                if (k > 0 && st->active[k]) {
+                    const double z = st->zeta[k], bs = st->beta_s[k];
+                    C u;
+                    u.x = z * ri.x + bs * v[b].x;
+                    u.y = z * ri.y + bs * v[b].y;
+                    ps[((size_t)(k - 1) * ncol + col) * n + i] = u;
+                }
             }
         }
         if (y) y[off + i] = yi;
@@ -262,6 +276,12 @@ __global__ void ms_update_kernel(const ColState *__restrict__ states, size_t n, 
             p[off + i] = pi;
         }
     }
+}
+
+// blocks per column of the vector-update kernel: about two elements per thread
+static inline int update_blocks(size_t n) {
+    const size_t b = (n + 511) / 512;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 // done 2 -> 1 for every column; *alldone = 1 once every column is done
@@ -412,6 +432,7 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
     }
     BRI_HIP_CHECK(hipMemcpyAsync(s.st, h.data(), sizeof(ColState) * s.ncol, hipMemcpyHostToDevice, strm));
     const dim3 vgrid(INIT_BLOCKS, s.ncol);
+    const dim3 ugrid(update_blocks(n), s.ncol);
     if (s.prec == BRI_F64) {
         hipLaunchKernelGGL((ms_init_kernel<double2, double2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
                            (double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x, (double2 *)s.ps, s.ncol,
@@ -453,11 +474,11 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
             const int e2 = stencil_launch(a2, s.prec, true, EPI_CG_R, cfg, strm);
             hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, s.nblk_st);
             if (s.prec == BRI_F64)
-                hipLaunchKernelGGL(ms_update_kernel<double2>, vgrid, dim3(256), 0, strm, s.st, n, s.ncol,
+                hipLaunchKernelGGL(ms_update_kernel<double2>, ugrid, dim3(256), 0, strm, s.st, n, s.ncol,
                                    (const double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x,
                                    (double2 *)s.ps);
             else
-                hipLaunchKernelGGL(ms_update_kernel<float2>, vgrid, dim3(256), 0, strm, s.st, n, s.ncol,
+                hipLaunchKernelGGL(ms_update_kernel<float2>, ugrid, dim3(256), 0, strm, s.st, n, s.ncol,
                                    (const float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps);
             hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(256), 0, strm, s.st, s.ncol, s.alldone);
             if (e1 != BRI_OK || e2 != BRI_OK) return e1 != BRI_OK ? e1 : e2;
@@ -732,45 +753,87 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     return result;
 }
 
-// FP64 multi-shift solve of (A + sigma_i) x_i = b over the Kenney-Laub shifts with every
-// x_i kept, [shift][ncol][12 V] inside the workspace (the gradient needs the individual
-// shift solutions).  With work == NULL only *need is set.
-int ov_solve_shifts(const Geom &g, const void *W64, const ov_params *prm, const void *b, int ncol, void *work,
-                    size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ColState *last) {
+// Multi-shift solve of (A + sigma_i) x_i = b over the Kenney-Laub shifts with every x_i kept
+// in FP64, [shift][ncol][12 V] inside the workspace (the gradient needs the individual shift
+// solutions).  inner = BRI_F64 runs the FP64 multi-shift; a low-precision inner runs it on
+// Wlo and refines every (shift, column) in FP64 as the overlap apply does.  With
+// work == NULL only *need is set.  st (may be NULL) receives iterations and the final
+// residual of each shift (the worst column).
+int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_params *prm, const void *b, int ncol,
+                    void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st) {
     const int n = prm->kl_n;
     if (n < 1 || n > MAXS || ncol < 1) return BRI_EINVAL;
+    const bool mixed = prm->inner != BRI_F64;
+    OvPlan pl;
     MsSolve m;
-    m.g = g;
-    m.prec = BRI_F64;
-    m.W = W64;
-    m.m0 = -prm->rho;
-    m.ncol = ncol;
-    m.nshift = n;
-    m.store_x = true;
-    double om[MAXS], sg[MAXS];
-    kl_coeffs(n, &m.c0, om, sg);
-    m.omega.assign(om, om + n);
-    m.sigma.resize((size_t)ncol * n);
-    for (int c = 0; c < ncol; ++c)
-        for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];
-    m.tol = prm->tol;
-    m.max_iter = prm->max_iter;
-    Arena ar(work);
-    m.carve(ar);
-    if (!work) {
-        if (need) *need = ar.used;
-        return BRI_OK;
+    if (mixed) {
+        plan_overlap(pl, g, prm, ncol, W64, Wlo, nullptr);
+        if (!work) {
+            if (need) *need = pl.bytes;
+            return BRI_OK;
+        }
+        if (work_bytes < pl.bytes || !W64 || !Wlo || !b || !x_out) return BRI_EINVAL;
+        plan_overlap(pl, g, prm, ncol, W64, Wlo, work);
+    } else {
+        m.g = g;
+        m.prec = BRI_F64;
+        m.W = W64;
+        m.m0 = -prm->rho;
+        m.ncol = ncol;
+        m.nshift = n;
+        m.store_x = true;
+        double om[MAXS], sg[MAXS];
+        kl_coeffs(n, &m.c0, om, sg);
+        m.omega.assign(om, om + n);
+        m.sigma.resize((size_t)ncol * n);
+        for (int c = 0; c < ncol; ++c)
+            for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];
+        m.tol = prm->tol;
+        m.max_iter = prm->max_iter;
+        Arena ar(work);
+        m.carve(ar);
+        if (!work) {
+            if (need) *need = ar.used;
+            return BRI_OK;
+        }
+        if (work_bytes < ar.used || !W64 || !b || !x_out) return BRI_EINVAL;
     }
-    if (work_bytes < ar.used || !W64 || !b || !x_out) return BRI_EINVAL;
     int *hflag = nullptr;
     BRI_HIP_CHECK(hipHostMalloc((void **)&hflag, sizeof(int), hipHostMallocDefault));
     RunStats rs;
-    const int rc = ms_run(m, b, true, s, hflag, rs);
+    int passes = 0;
+    std::vector<double> shift_res((size_t)n, 0.0);
+    int rc = ms_run(mixed ? pl.main : m, b, true, s, hflag, rs);
+    int result = rc != BRI_OK ? rc : rs.status;
+    if (mixed && (result == BRI_OK || result == BRI_ENOCONV)) {
+        const size_t nel = (size_t)12 * g.V;
+        hipLaunchKernelGGL(widen_kernel<float2>, dim3(4096), dim3(256), 0, s, nel * ncol * n,
+                           (const float2 *)pl.main.x, pl.x64, 0);
+        rc = refine(pl, g, prm, W64, b, s, hflag, passes, shift_res);
+        result = rc;
+    }
     (void)hipHostFree(hflag);
-    if (rc != BRI_OK) return rc;
-    *x_out = m.x;
-    if (last && !rs.fin.empty()) *last = rs.fin.back();
-    return rs.status;
+    if (result != BRI_OK && result != BRI_ENOCONV) return result;
+    *x_out = mixed ? (void *)pl.x64 : m.x;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->iters = rs.iters;
+        st->refine = passes;
+        for (int i = 0; i < n; ++i) {
+            int it = 0;
+            double res = 0.0;
+            for (const ColState &c : rs.fin) {
+                const int ci = c.conv_iter[i] ? c.conv_iter[i] : c.iter;
+                const double cr = c.conv_iter[i] ? c.conv_res[i]
+                                                 : fabs(c.zeta[i]) * sqrt(c.rr / (c.bnorm2 > 0 ? c.bnorm2 : 1));
+                if (ci > it) it = ci;
+                if (cr > res) res = cr;
+            }
+            st->shift_iters[i] = it;
+            st->rel_resid[i] = mixed ? shift_res[i] : res;
+        }
+    }
+    return result;
 }
 
 }  // namespace bri
