@@ -26,7 +26,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extr
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -56,11 +55,15 @@ def stencil_bytes_per_site(spinor_bytes_per_real: int, link_bytes_per_real: int,
     return (24 + 24) * nrhs * spinor_bytes_per_real + 720 * link_bytes_per_real
 
 
+STENCIL_SOURCES = ("common.hpp", "stencil.hpp", "stencil_core.hpp", "stencil.hip", "tune.hip")
+
+
 def kernel_source_digest() -> str:
+    """Hash of the sources that define the FP64 stencil kernel and its launch configuration."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1701_00726_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode() + f.read())
+    for name in STENCIL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1701_00726_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 
@@ -357,6 +360,24 @@ def main():
                                       "max_rel_err_vs_fp64": max(errs)}
             del opm, opm12, Wlo
             torch.cuda.empty_cache()
+        # HIP-graph replay of the CG loop against plain launches, here and on a small lattice
+        graphs = {}
+        for Lg in (L, (8, 8, 8, 8)):
+            if Lg == L:
+                opg, bg = op, b
+            else:
+                Ug = bri.links_to_device(synth.smeared_links(Lg, LINK_EPS, LINK_SEED, APE_ALPHA, APE_STEPS), dev)
+                Wg = bri.build_links(Lg, Ug, bri.F64)
+                opg = bri.OverlapOp(Lg, Wg, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+                bg = bri.spinor_to_device(synth.gaussian_source(Lg, SRC_SEED), bri.F64, dev)
+            og = torch.empty_like(bg)
+            row = {}
+            for on in (False, True):
+                bri.set_solver_graphs(on)
+                opg.apply(bg, out=og)
+                row["ms_graphs_on" if on else "ms_graphs_off"] = timed(lambda: opg.apply(bg, out=og), 10)
+            graphs["x".join(str(v) for v in Lg)] = row
+        extra["cg_graph_replay"] = graphs
         # gradient of Re chi^dag D_ov psi (force on the links and D_ov^dag chi), FP64
         chi = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED + 1), bri.F64, dev)
         op.grad(U, chi[0], b[0])

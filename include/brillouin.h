@@ -183,6 +183,16 @@ int bri_autotune(const bri_geom *geom, const void *W, int prec, const void *in, 
 int bri_set_stencil_cfg(const bri_geom *geom, int prec, int nrhs, const bri_stencil_cfg *cfg);
 int bri_get_stencil_cfg(const bri_geom *geom, int prec, int nrhs, bri_stencil_cfg *cfg);
 
+/* bri_set_solver_graphs -- enable (1, the default) or disable (0) HIP-graph replay of
+ * the multi-shift CG loop.  When enabled, each block of 8 iterations (six launches per
+ * iteration) is captured once per solve layout (device, lattice, precision, column count,
+ * workspace and link addresses, launch configuration) on a library-owned stream and
+ * replayed on the caller's stream; up to 16 instantiated graphs are cached per process and
+ * disabling clears them.  Results are identical either way (same kernels, same order).
+ * Not thread-safe against solves running concurrently in other threads.  BRI_EINVAL for
+ * other values. */
+int bri_set_solver_graphs(int enable);
+
 /* Kenney-Laub coefficients c0, omega[n], sigma[n] of f_{n,n} (eq. (KLnn_parfrac)),
  * computed in double precision on the host; sigma ascending. */
 int bri_kl_coeffs(int n, double *c0, double *omega, double *sigma);

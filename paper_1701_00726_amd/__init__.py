@@ -122,6 +122,7 @@ def load():
             lib.bri_autotune.argtypes = [G, P, I, P, P, I, I, SC, ctypes.POINTER(D), P]
             lib.bri_set_stencil_cfg.argtypes = [G, I, I, SC]
             lib.bri_get_stencil_cfg.argtypes = [G, I, I, SC]
+            lib.bri_set_solver_graphs.argtypes = [I]
             SZ = ctypes.POINTER(ctypes.c_size_t)
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
             lib.ov_apply_grad.argtypes = [G, P, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
@@ -145,6 +146,7 @@ EXPORTS = (
     "bri_get_stencil_cfg",
     "bri_link_grad",
     "ov_apply_grad",
+    "bri_set_solver_graphs",
 )
 MAX_PAIRS = 2 * MAX_SHIFTS + 1
 
@@ -370,6 +372,11 @@ class OverlapOp:
         s = OvStats(stats.iters, stats.refine, list(stats.shift_iters[:n]), list(stats.rel_resid[:n]), stats.seconds)
         s.status = st
         return F, GU, gpsi, s
+
+
+def set_solver_graphs(enable):
+    """Turn HIP-graph replay of the multi-shift CG loop on (default) or off."""
+    _check("bri_set_solver_graphs", load().bri_set_solver_graphs(1 if enable else 0))
 
 
 def kl_coeffs(n):

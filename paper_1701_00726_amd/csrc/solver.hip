@@ -30,11 +30,17 @@
 //
 // All solver scalars live on the device (ColState) and are updated by small
 // kernels; the host only polls a done flag every few iterations, and every
-// loop kernel returns at once for columns that are done.
+// loop kernel returns at once for columns that are done.  Because no launch
+// argument changes between iterations, a block of iterations is captured once
+// into a HIP graph and replayed (one launch per block instead of six per
+// iteration); the instantiated graphs are cached per solve layout.
 #include <math.h>
 
 #include <chrono>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "stencil.hpp"
@@ -413,6 +419,71 @@ struct RunStats {
     std::vector<ColState> fin;
 };
 
+// ------------------------------------------------------------ graph cache
+
+// Instantiated graphs of CHECK_EVERY solver iterations, keyed by everything their launches
+// depend on (device, geometry, precision, buffers, launch configuration).  Bounded; the
+// oldest entry is destroyed first.  Capture runs on a library stream per device (capture
+// is not possible on the null stream); the graph is then launched on the caller's stream.
+namespace {
+constexpr size_t GRAPH_CACHE_MAX = 16;
+std::mutex g_graph_mu;
+bool g_graphs_on = true;
+std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
+std::deque<std::vector<uint64_t>> g_graph_order;
+std::map<int, hipStream_t> g_capture_streams;
+
+void graph_cache_clear_locked() {
+    for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+    g_graph_order.clear();
+}
+}  // namespace
+
+template <typename F>
+static int graph_for(const std::vector<uint64_t> &key, F enqueue, hipGraphExec_t *out) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        *out = it->second;
+        return BRI_OK;
+    }
+    int dev = 0;
+    BRI_HIP_CHECK(hipGetDevice(&dev));
+    hipStream_t cs = g_capture_streams[dev];
+    if (!cs) {
+        BRI_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        g_capture_streams[dev] = cs;
+    }
+    BRI_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != BRI_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != BRI_OK ? rc : BRI_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return BRI_EHIP;
+    if (g_graphs.size() >= GRAPH_CACHE_MAX) {
+        auto old = g_graph_order.front();
+        g_graph_order.pop_front();
+        (void)hipGraphExecDestroy(g_graphs[old]);
+        g_graphs.erase(old);
+    }
+    g_graphs[key] = ex;
+    g_graph_order.push_back(key);
+    *out = ex;
+    return BRI_OK;
+}
+
+static bool graphs_enabled() {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    return g_graphs_on;
+}
+
 // Runs one batched multi-shift solve; b is [ncol][12 V] complex double (or
 // complex float when b_is_f64 is false).  Returns a HIP / argument status;
 // convergence and NaN status land in rs.
@@ -466,23 +537,61 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
     a2.p = s.p;
     a2.r = s.r;
 
+    // one CG iteration for every column: t = X p, alpha, r update, beta, vector updates, done flags
+    auto iteration = [&](hipStream_t q) -> int {
+        const int e1 = stencil_launch(a1, s.prec, false, EPI_NORMS, cfg, q);
+        hipLaunchKernelGGL(ms_alpha_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
+        const int e2 = stencil_launch(a2, s.prec, true, EPI_CG_R, cfg, q);
+        hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
+        if (s.prec == BRI_F64)
+            hipLaunchKernelGGL(ms_update_kernel<double2>, ugrid, dim3(256), 0, q, s.st, n, s.ncol,
+                               (const double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x,
+                               (double2 *)s.ps);
+        else
+            hipLaunchKernelGGL(ms_update_kernel<float2>, ugrid, dim3(256), 0, q, s.st, n, s.ncol,
+                               (const float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps);
+        hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(256), 0, q, s.st, s.ncol, s.alldone);
+        if (e1 != BRI_OK || e2 != BRI_OK) return e1 != BRI_OK ? e1 : e2;
+        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+    };
+    const bool use_graph = graphs_enabled();
+    std::vector<uint64_t> key;
+    if (use_graph) {
+        int dev = 0;
+        BRI_HIP_CHECK(hipGetDevice(&dev));
+        uint64_t m0bits;
+        std::memcpy(&m0bits, &s.m0, sizeof(m0bits));
+        key = {(uint64_t)dev, (uint64_t)s.g.L[0], (uint64_t)s.g.L[1], (uint64_t)s.g.L[2], (uint64_t)s.g.L[3],
+               (uint64_t)s.g.tbc, (uint64_t)s.prec, (uint64_t)s.ncol, m0bits, (uint64_t)(uintptr_t)s.W,
+               (uint64_t)(uintptr_t)s.st, (uint64_t)(uintptr_t)s.partial, (uint64_t)(uintptr_t)s.alldone,
+               (uint64_t)(uintptr_t)s.r, (uint64_t)(uintptr_t)s.p, (uint64_t)(uintptr_t)s.t,
+               (uint64_t)(uintptr_t)s.y, (uint64_t)(uintptr_t)s.x, (uint64_t)(uintptr_t)s.ps,
+               (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1], (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3],
+               (uint64_t)cfg.colz, (uint64_t)cfg.nsplit, (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap};
+    }
+
     int it = 0;
     for (;;) {
-        for (int k = 0; k < CHECK_EVERY && it < s.max_iter; ++k, ++it) {
-            const int e1 = stencil_launch(a1, s.prec, false, EPI_NORMS, cfg, strm);
-            hipLaunchKernelGGL(ms_alpha_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, s.nblk_st);
-            const int e2 = stencil_launch(a2, s.prec, true, EPI_CG_R, cfg, strm);
-            hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, s.nblk_st);
-            if (s.prec == BRI_F64)
-                hipLaunchKernelGGL(ms_update_kernel<double2>, ugrid, dim3(256), 0, strm, s.st, n, s.ncol,
-                                   (const double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x,
-                                   (double2 *)s.ps);
-            else
-                hipLaunchKernelGGL(ms_update_kernel<float2>, ugrid, dim3(256), 0, strm, s.st, n, s.ncol,
-                                   (const float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps);
-            hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(256), 0, strm, s.st, s.ncol, s.alldone);
-            if (e1 != BRI_OK || e2 != BRI_OK) return e1 != BRI_OK ? e1 : e2;
-            BRI_HIP_CHECK(hipGetLastError());
+        if (use_graph && it + CHECK_EVERY <= s.max_iter) {
+            hipGraphExec_t ex = nullptr;
+            const int rc = graph_for(
+                key,
+                [&](hipStream_t q) -> int {
+                    for (int k = 0; k < CHECK_EVERY; ++k) {
+                        const int e = iteration(q);
+                        if (e != BRI_OK) return e;
+                    }
+                    return BRI_OK;
+                },
+                &ex);
+            if (rc != BRI_OK) return rc;
+            BRI_HIP_CHECK(hipGraphLaunch(ex, strm));
+            it += CHECK_EVERY;
+        } else {
+            for (int k = 0; k < CHECK_EVERY && it < s.max_iter; ++k, ++it) {
+                const int e = iteration(strm);
+                if (e != BRI_OK) return e;
+            }
         }
         BRI_HIP_CHECK(hipMemcpyAsync(hflag, s.alldone, sizeof(int), hipMemcpyDeviceToHost, strm));
         BRI_HIP_CHECK(hipStreamSynchronize(strm));
@@ -839,6 +948,14 @@ int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_pa
 }  // namespace bri
 
 extern "C" {
+
+int bri_set_solver_graphs(int enable) {
+    if (enable != 0 && enable != 1) return BRI_EINVAL;
+    std::lock_guard<std::mutex> lk(bri::g_graph_mu);
+    bri::g_graphs_on = enable == 1;
+    if (!bri::g_graphs_on) bri::graph_cache_clear_locked();
+    return BRI_OK;
+}
 
 int bri_kl_coeffs(int n, double *c0, double *omega, double *sigma) {
     if (n < 1 || n > BRI_MAX_SHIFTS || !c0 || !omega || !sigma) return BRI_EINVAL;

@@ -129,3 +129,9 @@ def test_gradient_workspace_and_invalid_arguments():
     assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(lo), None, None, None, None, None, None,
                              ctypes.byref(nb_lo), None, None) == bri.OK
     assert nb_lo.value > nb.value
+
+
+def test_solver_graph_switch_rejects_other_values():
+    lib = bri.load()
+    assert lib.bri_set_solver_graphs(2) == bri.EINVAL
+    assert lib.bri_set_solver_graphs(-1) == bri.EINVAL
