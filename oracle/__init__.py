@@ -13,6 +13,7 @@ Functions and the passages they follow:
   links            off-axis links as averages over all shortest paths (App. C.1)
   dirac, dirac_adj Brillouin operator eq. (def_bril), c_SW = 0, and its adjoint
   dense_matrix     the same operator as a dense matrix (small lattices)
+  dirac_at, dirac_adj_at  the same sums at listed sites only, links built on the fly from U
   cg               textbook CG on (D^dag D + sigma) x = b
   rational_apply   c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, eq. (KLnn_parfrac)
   sign_apply       gamma5 g_{2n+1}(H) b with H = gamma5 D(-rho), Sec. 3.3 / eq. (def_over)
@@ -75,6 +76,8 @@ def _load():
             lib.orc_rational.restype = I
             lib.orc_num_threads.restype = I
             lib.orc_lambda.argtypes = [I, P]
+            lib.orc_dirac_at.argtypes = [P, I, P, D, P, I, P, P]
+            lib.orc_dirac_adj_at.argtypes = [P, I, P, D, P, I, P, P]
             lib.orc_link_force.argtypes = [P, I, P, I, P, P, P, P]
             _lib = lib
     return _lib
@@ -166,6 +169,28 @@ def dense_matrix(L, W, m0: float) -> np.ndarray:
     M = np.zeros((n, n), dtype=np.complex128)
     _load().orc_dirac_dense(_ptr(_geom(L)), _ptr(_c128(W)), float(m0), _ptr(M))
     return M
+
+
+def _apply_at(fn, L, U, tbc, m0, psi, sites):
+    V = volume(L)
+    U = _c128(U)
+    assert U.shape == (4, V, 3, 3)
+    psi = _c128(psi)
+    assert psi.shape == (V, 4, 3)
+    st = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros((len(st), 4, 3), dtype=np.complex128)
+    fn(_ptr(_geom(L)), int(tbc), _ptr(U), float(m0), _ptr(psi), len(st), _ptr(st), _ptr(out))
+    return out
+
+
+def dirac_at(L, U, tbc, m0: float, psi: np.ndarray, sites) -> np.ndarray:
+    """(D_bri(m0) psi)(x) for x in sites, shape (len(sites), 4, 3); links from U on the fly."""
+    return _apply_at(_load().orc_dirac_at, L, U, tbc, m0, psi, sites)
+
+
+def dirac_adj_at(L, U, tbc, m0: float, psi: np.ndarray, sites) -> np.ndarray:
+    """(D_bri(m0)^dag psi)(x) for x in sites (transposed sum, links on the fly)."""
+    return _apply_at(_load().orc_dirac_adj_at, L, U, tbc, m0, psi, sites)
 
 
 # -------------------------------------------------------------------- solvers

@@ -33,6 +33,9 @@
  *                  (transposed sum; gamma5-hermiticity is NOT used here, so a
  *                  test can check it).
  *   orc_dirac_dense  the same operator as a dense matrix (small lattices).
+ *   orc_dirac_at, orc_dirac_adj_at  D psi and D^dag psi at listed sites only, with
+ *                  the links of those sites (and their neighbours) built on the
+ *                  fly, for lattices too large for the full link array.
  *   orc_cg         textbook conjugate gradient on (D^dag D + sigma) x = b.
  *   orc_rational   y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, every
  *                  shift solved separately (eq. (KLnn_parfrac) with
@@ -232,51 +235,55 @@ static void init_perms(void) {
     perm_ready = 1;
 }
 
+/* the 81 path-averaged links W_d(x) of one site x, out[81][9] */
+static void links_site(const int *L, int tbc, const cplx *U, long x, cplx *out81) {
+    const long V = vol(L);
+    int cx[4];
+    coords(L, x, cx);
+    for (int j = 0; j < 81; ++j) {
+        int d[4];
+        disp_of(j, d);
+        int axes[4], k = 0;
+        for (int mu = 0; mu < 4; ++mu)
+            if (d[mu] != 0) axes[k++] = mu;
+        cplx *out = out81 + (size_t)j * 9;
+        cplx acc[9] = {0};
+        /* enumerate the k! orderings of the non-zero axes */
+        const int np_local = NPERM[k];
+        const int (*pl)[4] = PERM[k];
+        for (int p = 0; p < np_local; ++p) {
+            cplx M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            int cy[4] = {cx[0], cx[1], cx[2], cx[3]};
+            double sign = 1.0;
+            for (int st = 0; st < k; ++st) {
+                int mu = axes[pl[p][st]];
+                cplx T[9];
+                if (d[mu] > 0) {
+                    /* step +mu: multiply by U_mu(y), then y -> y + mu */
+                    long sy = site_of(L, cy);
+                    mat_mul(M, U + ((size_t)mu * V + sy) * 9, T);
+                    if (tbc && mu == 3 && cy[3] == L[3] - 1) sign = -sign;
+                    cy[mu] += 1;
+                } else {
+                    /* step -mu: y -> y - mu, multiply by U_mu(y)^dag */
+                    if (tbc && mu == 3 && cy[3] == 0) sign = -sign;
+                    cy[mu] -= 1;
+                    long sy = site_of(L, cy);
+                    mat_mul_dag(M, U + ((size_t)mu * V + sy) * 9, T);
+                }
+                memcpy(M, T, sizeof(T));
+            }
+            for (int e = 0; e < 9; ++e) acc[e] += sign * M[e];
+        }
+        for (int e = 0; e < 9; ++e) out[e] = acc[e] / (double)np_local;
+    }
+}
+
 void orc_links(const int *L, int tbc, const cplx *U, cplx *W) {
     const long V = vol(L);
     init_perms();
 #pragma omp parallel for schedule(static)
-    for (long x = 0; x < V; ++x) {
-        int cx[4];
-        coords(L, x, cx);
-        for (int j = 0; j < 81; ++j) {
-            int d[4];
-            disp_of(j, d);
-            int axes[4], k = 0;
-            for (int mu = 0; mu < 4; ++mu)
-                if (d[mu] != 0) axes[k++] = mu;
-            cplx *out = W + ((size_t)x * 81 + j) * 9;
-            cplx acc[9] = {0};
-            /* enumerate the k! orderings of the non-zero axes */
-            const int np_local = NPERM[k];
-            const int (*pl)[4] = PERM[k];
-            for (int p = 0; p < np_local; ++p) {
-                cplx M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-                int cy[4] = {cx[0], cx[1], cx[2], cx[3]};
-                double sign = 1.0;
-                for (int st = 0; st < k; ++st) {
-                    int mu = axes[pl[p][st]];
-                    cplx T[9];
-                    if (d[mu] > 0) {
-                        /* step +mu: multiply by U_mu(y), then y -> y + mu */
-                        long sy = site_of(L, cy);
-                        mat_mul(M, U + ((size_t)mu * V + sy) * 9, T);
-                        if (tbc && mu == 3 && cy[3] == L[3] - 1) sign = -sign;
-                        cy[mu] += 1;
-                    } else {
-                        /* step -mu: y -> y - mu, multiply by U_mu(y)^dag */
-                        if (tbc && mu == 3 && cy[3] == 0) sign = -sign;
-                        cy[mu] -= 1;
-                        long sy = site_of(L, cy);
-                        mat_mul_dag(M, U + ((size_t)mu * V + sy) * 9, T);
-                    }
-                    memcpy(M, T, sizeof(T));
-                }
-                for (int e = 0; e < 9; ++e) acc[e] += sign * M[e];
-            }
-            for (int e = 0; e < 9; ++e) out[e] = acc[e] / (double)np_local;
-        }
-    }
+    for (long x = 0; x < V; ++x) links_site(L, tbc, U, x, W + (size_t)x * 81 * 9);
 }
 
 /* ------------------------------------------------------------ the operator */
@@ -384,6 +391,70 @@ void orc_dirac_dense(const int *L, const cplx *W, double m0, cplx *M) {
                             M[(size_t)(12 * x + 3 * s + a) * n + 12 * nb[j] + 3 * t + b] +=
                                 S[j][s][t] * Wd[3 * a + b];
         }
+    }
+}
+
+/* (D psi)(x) and (D^dag psi)(x) at the listed sites only, with the links built
+ * on the fly from U (for lattices too large for the full link array).  Same sums
+ * as orc_dirac / orc_dirac_adj.  out[nsites][4][3]. */
+void orc_dirac_at(const int *L, int tbc, const cplx *U, double m0, const cplx *in, int nsites, const long *sites,
+                  cplx *out) {
+    init_perms();
+    cplx S[81][4][4];
+    for (int j = 0; j < 81; ++j) spin_matrix(j, m0, S[j]);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < nsites; ++i) {
+        const long x = sites[i];
+        cplx Wx[81 * 9];
+        links_site(L, tbc, U, x, Wx);
+        long nb[81];
+        neighbour_table(L, x, nb);
+        cplx acc[4][3] = {{0}};
+        for (int j = 0; j < 81; ++j) {
+            const cplx *Wd = Wx + (size_t)j * 9;
+            const cplx *p = in + (size_t)nb[j] * 12;
+            for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a) {
+                    cplx v = 0;
+                    for (int t = 0; t < 4; ++t)
+                        for (int b = 0; b < 3; ++b) v += S[j][s][t] * Wd[3 * a + b] * p[3 * t + b];
+                    acc[s][a] += v;
+                }
+        }
+        for (int s = 0; s < 4; ++s)
+            for (int a = 0; a < 3; ++a) out[(size_t)i * 12 + 3 * s + a] = acc[s][a];
+    }
+}
+
+void orc_dirac_adj_at(const int *L, int tbc, const cplx *U, double m0, const cplx *in, int nsites, const long *sites,
+                      cplx *out) {
+    init_perms();
+    cplx S[81][4][4];
+    for (int j = 0; j < 81; ++j) spin_matrix(j, m0, S[j]);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < nsites; ++i) {
+        const long x = sites[i];
+        long nb[81];
+        neighbour_table(L, x, nb);
+        cplx acc[4][3] = {{0}};
+        cplx Wy[81 * 9];
+        for (int j = 0; j < 81; ++j) {
+            /* D^dag(x, x+d) = D(x+d, x)^dag = S_{-d}^dag W_{-d}(x+d)^dag */
+            const int jm = 80 - j;
+            const long y = nb[j];
+            links_site(L, tbc, U, y, Wy);
+            const cplx *Wd = Wy + (size_t)jm * 9;
+            const cplx *p = in + (size_t)y * 12;
+            for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a) {
+                    cplx v = 0;
+                    for (int t = 0; t < 4; ++t)
+                        for (int b = 0; b < 3; ++b) v += conj(S[jm][t][s]) * conj(Wd[3 * b + a]) * p[3 * t + b];
+                    acc[s][a] += v;
+                }
+        }
+        for (int s = 0; s < 4; ++s)
+            for (int a = 0; a < 3; ++a) out[(size_t)i * 12 + 3 * s + a] = acc[s][a];
     }
 }
 
