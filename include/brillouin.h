@@ -153,7 +153,8 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  * z-planes, so that stencil neighbours run together on one XCD; col_z = 0:
  * lexicographic tiles), the work split (rpt = 0: one right-hand side per
  * block row with nsplit = 1, 2 or 4 waves sharing the 80 displacements;
- * rpt = 1..4: rpt right-hand sides per thread) and xcd = 1 to give each XCD a
+ * rpt = 1..4: rpt right-hand sides per thread, four waves sharing the
+ * displacements, nsplit ignored) and xcd = 1 to give each XCD a
  * contiguous range of tiles.
  */
 typedef struct {

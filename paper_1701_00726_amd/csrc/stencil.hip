@@ -18,13 +18,16 @@
 // in LDS; wave q finishes 12/NSPLIT of the spin-colour components.
 //
 // stencil_mrhs_kernel (many right-hand sides): a block owns a tile of 64 sites
-// and 4 waves; each wave takes R right-hand sides and all 80 displacements, so
-// each link entry is loaded once per R right-hand sides (and the 4 waves of a
-// block read the same link lines at the same time).
+// and R right-hand sides; its MRHS_SPLIT waves split the slabs as above and
+// every thread carries all R right-hand sides, so each link entry is loaded
+// once per R right-hand sides while the tile still spreads over MRHS_SPLIT
+// waves.  The partial sums meet in LDS one column at a time.
 #include "stencil.hpp"
 #include "stencil_core.hpp"
 
 namespace bri {
+
+constexpr int MRHS_SPLIT = 4;  // waves per tile of the multi-RHS kernel
 
 template <typename C> __device__ __forceinline__ double norm2(const C &v) {
     return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
@@ -187,14 +190,16 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
 // ------------------------------------------------------ many right-hand sides
 
 template <class LS, int R, bool DAG, int MODE>
-__global__ __launch_bounds__(256) void stencil_mrhs_kernel(StencilArgs a) {
+__global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilArgs a) {
     using RT = typename LS::R;
     using C = typename Cx<RT>::T;
+    constexpr int NSPLIT = MRHS_SPLIT;
+    constexpr int NCOMP = 12 / NSPLIT;
     const unsigned V = (unsigned)a.g.V;
     const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int col0 = (blockIdx.y * 4 + w) * R;
-    if (col0 >= a.ncol) return;  // whole wave; no block barriers in this kernel
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col0 = blockIdx.y * R;
+    // block-uniform: every wave of the block carries the same R columns
     bool live[R];
     bool any = false;
 #pragma unroll
@@ -219,11 +224,14 @@ __global__ __launch_bounds__(256) void stencil_mrhs_kernel(StencilArgs a) {
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 C v = cmake<C>((RT)0, (RT)0);
-                if (live[r]) v = in[((size_t)r * 12 + s * 3 + b) * V + x];
-                acc[r][s][b] = cmake<C>(diag * v.x, diag * v.y);
+                if (q == 0 && live[r]) {
+                    const C u = in[((size_t)r * 12 + s * 3 + b) * V + x];
+                    v = cmake<C>(diag * u.x, diag * u.y);
+                }
+                acc[r][s][b] = v;
             }
 
-    for (int j = 0; j < 40; ++j) {
+    for (int j = q; j < 40; j += NSPLIT) {
         const DirW<RT, DAG> dw(j);
         const typename LS::store_t *__restrict__ Wj = W + (size_t)j * 9 * V;
         C wl[3][3];
@@ -250,24 +258,52 @@ __global__ __launch_bounds__(256) void stencil_mrhs_kernel(StencilArgs a) {
         }
     }
 
+    // per column: the NSPLIT partial sums meet in LDS, wave q finishes NCOMP components
+    __shared__ C red[NSPLIT][12][64];
+    __shared__ double wsum[NSPLIT][2];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!live[r]) continue;
         const int col = col0 + r;
-        double n0 = 0.0, n1 = 0.0;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) epilogue<MODE, C, RT>(a, col, s * 3 + b, x, V, acc[r][s][b], n0, n1);
+            for (int b = 0; b < 3; ++b) red[q][s * 3 + b][lane] = acc[r][s][b];
+        __syncthreads();
+        double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) {
+            const int comp = q * NCOMP + i;
+            C v = red[0][comp][lane];
+#pragma unroll
+            for (int w = 1; w < NSPLIT; ++w) {
+                const C u = red[w][comp][lane];
+                v.x += u.x;
+                v.y += u.y;
+            }
+            epilogue<MODE, C, RT>(a, col, comp, x, V, v, n0, n1);
+        }
         if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
+            // deterministic: wave sums, then the NSPLIT wave totals in order
             n0 = wave_sum(n0);
             n1 = wave_sum(n1);
             if (lane == 0) {
+                wsum[q][0] = n0;
+                wsum[q][1] = n1;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s0 = 0.0, s1 = 0.0;
+                for (int w = 0; w < NSPLIT; ++w) {
+                    s0 += wsum[w][0];
+                    s1 += wsum[w][1];
+                }
                 const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
-                a.partial[2 * pb] = n0;
-                a.partial[2 * pb + 1] = n1;
+                a.partial[2 * pb] = s0;
+                a.partial[2 * pb + 1] = s1;
             }
         }
+        __syncthreads();  // red and wsum are reused by the next column
     }
 }
 
@@ -291,7 +327,7 @@ static hipError_t launch_1rhs(const StencilArgs &a, int mode, hipStream_t st) {
 template <class LS, int R, bool DAG>
 static hipError_t launch_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
     const int groups = (a.ncol + R - 1) / R;
-    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)((groups + 3) / 4)), block(256);
+    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(64 * MRHS_SPLIT);
     switch (mode) {
     case EPI_PLAIN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
     case EPI_NORMS: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
@@ -370,12 +406,11 @@ int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
 }
 
 int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilConfig &cfg, hipStream_t st) {
-    if (a.ncol < 1 || a.ncol > 65535 * 4) return BRI_EINVAL;
+    if (a.ncol < 1 || a.ncol > 65535) return BRI_EINVAL;
     int rc = plan_tile(a.g, cfg, a.tile, a.nb);
     if (rc != BRI_OK) return rc;
     a.colz = cfg.colz;
     a.xcd_remap = cfg.xcd_remap;
-    if (cfg.rpt == 0 && a.ncol > 65535) return BRI_EINVAL;
     hipError_t e;
     if (prec == BRI_F64)
         e = dag ? launch_prec<LinkF64, true>(a, mode, cfg, st) : launch_prec<LinkF64, false>(a, mode, cfg, st);
@@ -411,11 +446,11 @@ StencilConfig default_config(const Geom &g, int prec, int ncol) {
     if (tuned_config(g, prec, ncol, &c)) return c;
     default_traversal(g, c);
     c.xcd_remap = 1;
-    if (ncol >= 4) {
-        // link loads amortised over R right-hand sides per thread
-        c.nsplit = 1;
-        c.rpt = prec == BRI_F64 ? 2 : 4;
-        if (ncol % c.rpt) c.rpt = (ncol % 3 == 0) ? 3 : (prec == BRI_F64 ? 1 : 2);
+    if (ncol >= 2) {
+        // link loads amortised over R right-hand sides per thread (a last, partial group of
+        // columns is allowed); four waves still split each tile's displacements
+        c.nsplit = MRHS_SPLIT;
+        c.rpt = ncol < 4 ? ncol : ((ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3);
     } else {
         // few sites -> split each site's directions over more waves to fill the 1024 SIMDs
         c.rpt = 0;

@@ -95,12 +95,12 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
             if (g.L[0] % t[0] == 0 && g.L[1] % t[1] == 0 && g.L[2] % cz == 0) trav.push_back({t[0], t[1], 1, 1, cz});
     trav.push_back({0, 0, 0, 0, 0});  // automatic lexicographic tile
     std::vector<std::pair<int, int>> work;  // (nsplit, rpt)
-    if (ncol < 4) {
+    if (ncol == 1) {
         work = {{2, 0}, {4, 0}};
-    } else if (prec == BRI_F64) {
-        work = {{1, 1}, {1, 2}};
+    } else if (ncol < 4) {
+        work = {{4, 0}, {4, ncol}};
     } else {
-        work = {{1, 2}, {1, 3}, {1, 4}};
+        work = {{4, 2}, {4, 3}, {4, 4}};
     }
     for (const auto &t : trav)
         for (const auto &w : work)

@@ -21,7 +21,7 @@ L = (16, 8, 8, 6)
 def _configs(nrhs):
     trav = [(0, 0, 0, 0, 0), (16, 4, 1, 1, 0), (4, 4, 4, 1, 0)]
     trav += [(tx, ty, 1, 1, cz) for (tx, ty), cz in itertools.product([(8, 8), (16, 4)], [2, 4, 8])]
-    work = [(2, 0), (4, 0), (1, 0)] if nrhs < 4 else [(1, 1), (1, 2), (1, 3), (1, 4)]
+    work = [(2, 0), (4, 0), (1, 0)] if nrhs == 1 else [(4, 0), (4, 1), (4, 2), (4, 3), (4, 4)]
     for t, w, xcd in itertools.product(trav, work, (0, 1)):
         yield bri.StencilCfg(t[0], t[1], t[2], t[3], t[4], w[0], w[1], xcd)
 
@@ -34,7 +34,7 @@ def setup():
     return Wo, W
 
 
-@pytest.mark.parametrize("nrhs", [1, 5])
+@pytest.mark.parametrize("nrhs", [1, 2, 5])
 def test_every_config_matches_oracle(setup, nrhs):
     need_gpu()
     Wo, W = setup
