@@ -21,6 +21,7 @@ extra        the same apply batched over the 12 spin-colour point sources and
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
        python bench.py --stencil-only     (copy calibration + stencil launches, for counters)
+       python bench.py --stencil-only --lattice 32,32,32,64   (the same on a larger workload lattice)
 """
 
 from __future__ import annotations
@@ -99,6 +100,9 @@ def parse():
     ap.add_argument("--survey", action="store_true",
                     help="stencil (tuned, FP64/FP32/BF16-link, 1 and 12 RHS) and overlap timings at 16^4, 24^3x48, 32^3x64")
     ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
+    ap.add_argument("--lattice", default=None,
+                    help="with --stencil-only: another lattice, e.g. 32,32,32,64 (links exp(0.7iA) + 3 APE "
+                         "built on the device)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
     return ap.parse_args()
 
@@ -189,6 +193,28 @@ def survey(torch, bri, synth):
         torch.cuda.empty_cache()
 
 
+def stencil_only_large(torch, bri, synth, L, reps):
+    """Counter runs on a workload lattice other than the bench's: a 1 GiB calibration copy, the
+    links of that lattice's recipe (exp(0.7 i A) + 3 APE(0.6)) built on the device, and `reps`
+    FP64 stencil launches in the default configuration."""
+    V = int(np.prod(L))
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    del a, c
+    U = synth.smeared_links_torch(L, 0.7, LINK_SEED, APE_ALPHA, APE_STEPS, device="cuda", chunk=1 << 18)
+    W = bri.build_links(L, U.permute(0, 2, 3, 1).contiguous(), bri.F64)
+    del U
+    x = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED), bri.F64)
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        bri.apply(L, W, bri.F64, -RHO, x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"stencil_only": True, "lattice": list(L), "launches": reps,
+                      "alg_bytes_per_launch": stencil_bytes_per_site(8, 8) * V,
+                      "config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -209,6 +235,9 @@ def main():
         sys.exit(1)
     if args.survey:
         survey(torch, bri, synth)
+        return
+    if args.stencil_only and args.lattice:
+        stencil_only_large(torch, bri, synth, tuple(int(v) for v in args.lattice.split(",")), args.stencil_reps)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
