@@ -219,8 +219,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(
-            "bench.py measures one GPU only: this build has no multi-GPU path "
-            "(the lattice would shard by sources or by domain decomposition; see the design notes).",
+            "bench.py measures one GPU only: the library has no multi-GPU path "
+            "(the work would shard by sources, or by domain decomposition of the lattice in t).",
             file=sys.stderr,
         )
         sys.exit(2)
