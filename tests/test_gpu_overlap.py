@@ -61,7 +61,7 @@ def test_overlap_against_dense_eigendecomposition():
     assert np.linalg.norm(bri.spinor_to_host(s_out)[0] - exact) <= dov.sign_bound(8) * 1.01 + 1e-11
 
 
-@pytest.mark.parametrize("L,tbc", [((4, 8, 4, 6), 0), ((4, 4, 4, 8), 1)])
+@pytest.mark.parametrize("L,tbc", [((4, 8, 4, 6), 0), ((4, 4, 4, 8), 1), ((16, 4, 1, 1), 1), ((2, 2, 2, 8), 0)])
 def test_overlap_non_cubic(L, tbc):
     need_gpu()
     U = synth.random_links(L, 0.4, 77)

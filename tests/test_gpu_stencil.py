@@ -22,6 +22,11 @@ CASES = [
     ((4, 8, 4, 6), "rough", 0),
     ((4, 4, 4, 8), "rough", 1),
     ((8, 8, 8, 8), "cfg2", 0),
+    # degenerate extents: +1 and -1 neighbours coincide (2), or are the site itself (1), so the
+    # stored and the daggered links of several displacements meet on the same sites
+    ((2, 2, 2, 8), "rough", 1),
+    ((16, 4, 1, 1), "rough", 1),
+    ((4, 4, 2, 2), "rough", 0),
 ]
 
 
