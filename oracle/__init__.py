@@ -21,6 +21,8 @@ Functions and the passages they follow:
   link_force       dS/d omega for S = Re sum_p w_p u_p^dag D v_p, U -> exp(i omega^a
                    lambda_a / 2) U (Sec. 9: derivative with respect to the Gell-Mann
                    components of log U), product rule along every path of App. C.1
+  massive.ov_solve (D_ov + mt) x = bt of the complete massive form (Sec. 4), by textbook BiCGstab
+                   (Sec. 7) around ov_apply
   ov_force         the same derivative for S = Re chi^dag D_ov psi with the fixed-order
                    rational of eq. (KLnn_parfrac) inside eq. (def_over) (Sec. 9), and
                    the spinor gradient D_ov^dag chi
