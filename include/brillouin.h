@@ -146,6 +146,44 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
              void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream);
 
 /*
+ * Outer solve of the massive overlap equation (Sec. 4; BiCGstab outer solver of Sec. 7):
+ *   (D_ov + mt) x = bt,  mt = m / (1 - m/(2 rho)),
+ *   complete form (eq. (upshot_complete)):   bt = [1 + (m/(2 rho)) (1 - D_ov/(2 rho))] b / (1 - m/(2 rho))
+ *   traditional (eq. (upshot_traditional)):  bt = b / (1 - m/(2 rho))
+ * with lattice spacing 1.  Every application of D_ov is one ov_apply with `params` (the inner
+ * multi-shift); its tolerance should be well below the outer one.
+ */
+typedef struct {
+    double mass;  /* bare quark mass m, 0 <= m < 2 rho                               */
+    int complete; /* 1: complete massive form, 0: traditional                        */
+    double tol;   /* outer stop: recursive |bt - (D_ov + mt) x| <= tol |bt|          */
+    int max_iter; /* outer BiCGstab iterations                                       */
+} ov_mass_params;
+
+typedef struct {
+    int iters;        /* outer BiCGstab iterations                                    */
+    int inner_iters;  /* multi-shift CG iterations summed over all D_ov applies       */
+    int applies;      /* D_ov applies (two per outer iteration, plus bt and the check) */
+    double rel_resid; /* true |bt - (D_ov + mt) x| / |bt| at exit                      */
+    double seconds;   /* host wall time of the call                                   */
+} ov_solve_stats;
+
+/*
+ * ov_solve -- x = (D_ov + mt)^{-1} bt for one right-hand side.
+ *   W64, Wlo, params : as ov_apply (params->inner may be low precision with refinement)
+ *   mp    : mass, form, outer tolerance and iteration cap
+ *   in    : b, [4][3][V] complex double;  out : x, same layout, must not overlap in
+ *   work, work_bytes : device workspace (query with work == NULL)
+ *   stats : may be NULL
+ * Synchronises `stream`.  Returns BRI_ENOCONV when max_iter outer iterations did not reach tol
+ * (out holds the last iterate), BRI_ENAN on a non-finite or breaking-down recurrence, the
+ * status of a failing inner ov_apply, BRI_EINVAL for bad arguments (m outside [0, 2 rho)).
+ */
+int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params,
+             const ov_mass_params *mp, const void *in, void *out, void *work, size_t *work_bytes,
+             ov_solve_stats *stats, void *stream);
+
+/*
  * Stencil launch configuration and autotuner.  A configuration picks the
  * 64-site tile (tile_x * tile_y * tile_z * tile_t = 64, each dividing its
  * lattice extent; all zero = automatic), the traversal (col_z > 0: tiles of

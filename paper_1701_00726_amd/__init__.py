@@ -65,6 +65,25 @@ class _OvStats(ctypes.Structure):
     ]
 
 
+class _MassParams(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double),
+        ("complete", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+    ]
+
+
+class _SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("inner_iters", ctypes.c_int),
+        ("applies", ctypes.c_int),
+        ("rel_resid", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
 class StencilCfg(ctypes.Structure):
     """Launch configuration of the stencil kernels (see include/brillouin.h)."""
 
@@ -89,6 +108,15 @@ class OvStats:
     refine: int
     shift_iters: list = field(default_factory=list)
     rel_resid: list = field(default_factory=list)
+    seconds: float = 0.0
+
+
+@dataclass
+class SolveStats:
+    iters: int
+    inner_iters: int
+    applies: int
+    rel_resid: float
     seconds: float = 0.0
 
 
@@ -125,6 +153,8 @@ def load():
             lib.bri_set_solver_graphs.argtypes = [I]
             SZ = ctypes.POINTER(ctypes.c_size_t)
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
+            lib.ov_solve.argtypes = [G, P, P, ctypes.POINTER(_OvParams), ctypes.POINTER(_MassParams), P, P, P, SZ,
+                                     ctypes.POINTER(_SolveStats), P]
             lib.ov_apply_grad.argtypes = [G, P, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
                                           ctypes.POINTER(_OvStats), P]
             for fn in EXPORTS:
@@ -146,6 +176,7 @@ EXPORTS = (
     "bri_get_stencil_cfg",
     "bri_link_grad",
     "ov_apply_grad",
+    "ov_solve",
     "bri_set_solver_graphs",
 )
 MAX_PAIRS = 2 * MAX_SHIFTS + 1
@@ -372,6 +403,34 @@ class OverlapOp:
         s = OvStats(stats.iters, stats.refine, list(stats.shift_iters[:n]), list(stats.rel_resid[:n]), stats.seconds)
         s.status = st
         return F, GU, gpsi, s
+
+
+    def solve(self, b, mass, complete=True, tol=1e-10, max_iter=1000, stream=None, allow_noconv=False):
+        """x = (D_ov + mt)^{-1} bt for one right-hand side b: the massive overlap
+        equation of Sec. 4 (complete or traditional form), BiCGstab outer solver with
+        every D_ov apply run by this operator.  Returns (x, SolveStats)."""
+        torch = _torch()
+        V = int(np.prod(self.L))
+        if b.dtype != torch.complex128 or b.numel() != 12 * V:
+            raise ValueError("b must be complex128 with 12 V elements")
+        mp = _MassParams(float(mass), 1 if complete else 0, float(tol), int(max_iter))
+        if getattr(self, "_swork", None) is None:
+            nb = ctypes.c_size_t(0)
+            _check("ov_solve", load().ov_solve(ctypes.byref(self.g), None, None, ctypes.byref(self.params),
+                                               ctypes.byref(mp), None, None, None, ctypes.byref(nb), None, None))
+            self._swork = torch.empty(int(nb.value), dtype=torch.uint8, device=self.W64.device)
+        x = torch.empty_like(b)
+        st = _SolveStats()
+        wb = ctypes.c_size_t(self._swork.numel())
+        rc = load().ov_solve(
+            ctypes.byref(self.g), _dptr(self.W64), None if self.Wlo is None else _dptr(self.Wlo),
+            ctypes.byref(self.params), ctypes.byref(mp), _dptr(b), _dptr(x), _dptr(self._swork), ctypes.byref(wb),
+            ctypes.byref(st), _stream(stream),
+        )
+        _check("ov_solve", rc, allow=(ENOCONV,) if allow_noconv else ())
+        s = SolveStats(st.iters, st.inner_iters, st.applies, st.rel_resid, st.seconds)
+        s.status = rc
+        return x, s
 
 
 def set_solver_graphs(enable):

@@ -135,3 +135,37 @@ def test_solver_graph_switch_rejects_other_values():
     lib = bri.load()
     assert lib.bri_set_solver_graphs(2) == bri.EINVAL
     assert lib.bri_set_solver_graphs(-1) == bri.EINVAL
+
+
+def test_massive_solve_workspace_and_invalid_args():
+    lib = bri.load()
+    L = (8, 8, 8, 8)
+    V = 8**4
+    g = bri._geom(L)
+    prm = bri._OvParams(8, 1.0, 1e-12, 200, 0, 0)
+    st, ov_bytes = _ov_query(L, kl_n=8, tol=1e-12, max_iter=200)
+    assert st == bri.OK
+    nb = ctypes.c_size_t(0)
+    mp_ = bri._MassParams(0.1, 1, 1e-10, 100)
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), None, None, None,
+                        ctypes.byref(nb), None, None) == bri.OK
+    # the ov_apply workspace plus seven BiCGstab vectors (bt, r, r0, p, v, s, t) and dot partials
+    vec = 12 * V * 16
+    assert ov_bytes + 7 * vec <= nb.value < ov_bytes + 7 * vec + (1 << 16)
+    for bad in (bri._MassParams(-0.1, 1, 1e-10, 100), bri._MassParams(2.0, 1, 1e-10, 100),
+                bri._MassParams(0.1, 2, 1e-10, 100), bri._MassParams(0.1, 1, 0.0, 100),
+                bri._MassParams(0.1, 0, 1e-10, 0)):
+        assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(bad), None, None, None,
+                            ctypes.byref(nb), None, None) == bri.EINVAL
+    # bad inner parameters are rejected through the ov_apply query
+    badp = bri._OvParams(0, 1.0, 1e-12, 200, 0, 0)
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(badp), ctypes.byref(mp_), None, None, None,
+                        ctypes.byref(nb), None, None) == bri.EINVAL
+    # a workspace that is too small, or in == out, is rejected before any launch
+    small = ctypes.c_size_t(nb.value - 1)
+    p = ctypes.c_void_p(256)
+    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), p, ctypes.c_void_p(512), p,
+                        ctypes.byref(small), None, None) == bri.EINVAL
+    full = ctypes.c_size_t(nb.value)
+    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), p, p, p,
+                        ctypes.byref(full), None, None) == bri.EINVAL
