@@ -217,6 +217,55 @@ def stencil_only_large(torch, bri, synth, L, reps):
                       "config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict()}), flush=True)
 
 
+# the cascaded-preconditioning measurement: the 16^3x32 volume of the paper's timing table,
+# links exp(0.5 iA) + 7 APE(0.6) steps, am = 0.03, rho = 1, exit |r|/|b| <= 1e-9
+CASCADE_L = (16, 16, 16, 32)
+CASCADE_MASS, CASCADE_TOL, CASCADE_APE = 0.03, 1e-9, 7
+# rows: (Kenney-Laub order, name, preconditioner levels as (kl_n, tol, max_iter, ms_tol))
+CASCADE_ROWS = (
+    (1, "none", ()),
+    (1, "1-level", ((0, 0.03, 50, 0.0),)),
+    (4, "none", ()),
+    (4, "2-level", ((1, 0.03, 30, 1e-4), (0, 0.1, 30, 0.0))),
+)
+
+
+def cascade_table(dev):
+    """Outer BiCGstab iterations and seconds per right-hand side for f_{1,1} and f_{4,4}, without
+    and with cascaded preconditioning (complete massive form), one Gaussian source."""
+    import torch
+
+    import paper_1701_00726_amd as bri
+    import synth
+
+    L = CASCADE_L
+    U = synth.smeared_links_torch(L, LINK_EPS, LINK_SEED + 30, APE_ALPHA, CASCADE_APE, device=dev, chunk=1 << 18)
+    U = U.permute(0, 2, 3, 1).contiguous()
+    W = bri.build_links(L, U, bri.F64)
+    del U
+    b = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED + 30), bri.F64, dev)
+    rows, ref = [], {}
+    for n, name, levels in CASCADE_ROWS:
+        prec = [bri.Level(k, tol=t, max_iter=mi, ms_tol=ms) for k, t, mi, ms in levels]
+        op = bri.OverlapOp(L, W, kl_n=n, rho=RHO, tol=CG_TOL, max_iter=5000)
+        op.solve(b, CASCADE_MASS, tol=1e-3, prec=prec)  # warm caches and workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = op.solve(b, CASCADE_MASS, complete=True, tol=CASCADE_TOL, max_iter=2000, prec=prec)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        row = {"f": f"{n},{n}", "precond": name, "n_iter": st.iters, "s_per_rhs": sec,
+               "level_iters": st.level_iters, "true_rel_resid": st.rel_resid}
+        if n in ref:
+            row["rel_diff_vs_unpreconditioned"] = float(torch.linalg.vector_norm(x - ref[n]) /
+                                                        torch.linalg.vector_norm(ref[n]))
+        else:
+            ref[n] = x
+        rows.append(row)
+        del op
+    return {"lattice": list(L), "mass": CASCADE_MASS, "tol": CASCADE_TOL, "ape_steps": CASCADE_APE, "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -426,6 +475,7 @@ def main():
             "inner_cg_iters": sts.inner_iters, "ms_per_solve": ms_s, "ms_per_ov_apply": ms_s / sts.applies,
             "true_rel_resid": sts.rel_resid}
         del xs
+        extra["cascaded_16x16x16x32"] = cascade_table(dev)
         best_mixed = max(extra[k]["applies_per_s"] for k in extra if k.startswith("mixed"))
         extra["fp64_1src_applies_per_s"] = value
         extra["speedup_batched_fp64_vs_fp64_1src"] = extra["batched_fp64_12src"]["applies_per_s"] / value

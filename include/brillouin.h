@@ -152,7 +152,18 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  *   traditional (eq. (upshot_traditional)):  bt = b / (1 - m/(2 rho))
  * with lattice spacing 1.  Every application of D_ov is one ov_apply with `params` (the inner
  * multi-shift); its tolerance should be well below the outer one.
+ *
+ * Cascaded preconditioning (Sec. 8, eqs. (cascaded_one), (cascaded_two)): the outer BiCGstab can
+ * be preconditioned from the right by a chain of cheaper operators of the same massive form,
+ *   A_k = rho [D^(k) + 1 + mt/rho],  D^(k) = X r_{n_k}(X^dag X)  (the overlap approximant of
+ *   Kenney-Laub order n_k, so A_k = D_ov^(n_k) + mt),  D^(0) = X = D_bri(-rho),
+ * each inverted approximately by its own BiCGstab (stopped at a loose tolerance or an iteration
+ * cap) that is preconditioned by the next operator of the chain.  The paper's one-level scheme
+ * for f_{1,1} is params->kl_n = 1 with prec = {Brillouin}; its two-level scheme for f_{4,4} is
+ * kl_n = 4 with prec = {n = 1, Brillouin}.  The same bare mass is used at every level.
  */
+#define BRI_MAX_LEVELS 4
+
 typedef struct {
     double mass;  /* bare quark mass m, 0 <= m < 2 rho                               */
     int complete; /* 1: complete massive form, 0: traditional                        */
@@ -160,28 +171,46 @@ typedef struct {
     int max_iter; /* outer BiCGstab iterations                                       */
 } ov_mass_params;
 
+/* One preconditioner level. */
 typedef struct {
-    int iters;        /* outer BiCGstab iterations                                    */
-    int inner_iters;  /* multi-shift CG iterations summed over all D_ov applies       */
-    int applies;      /* D_ov applies (two per outer iteration, plus bt and the check) */
-    double rel_resid; /* true |bt - (D_ov + mt) x| / |bt| at exit                      */
-    double seconds;   /* host wall time of the call                                   */
+    int kl_n;      /* 0: the Brillouin operator (must be the last level), else 1..BRI_MAX_SHIFTS */
+    double tol;    /* stop of this level's BiCGstab, relative to the vector it is applied to   */
+    int max_iter;  /* iteration cap of this level's BiCGstab, per application                  */
+    double ms_tol; /* multi-shift CG tolerance of this level's overlap applies (kl_n > 0)       */
+    int inner;     /* bri_prec of this level's multi-shift (kl_n > 0); low precision needs Wlo  */
+} ov_level;
+
+typedef struct {
+    int iters;                          /* outer BiCGstab iterations                          */
+    int inner_iters;                    /* multi-shift CG iterations summed over every level  */
+    int applies;                        /* D_ov applies of the outer level (bt, two per
+                                           iteration, the final check)                        */
+    double rel_resid;                   /* true |bt - (D_ov + mt) x| / |bt| at exit            */
+    int level_iters[BRI_MAX_LEVELS];    /* BiCGstab iterations summed per preconditioner level */
+    int level_calls[BRI_MAX_LEVELS];    /* applications of each preconditioner level          */
+    int level_applies[BRI_MAX_LEVELS];  /* operator applies of each preconditioner level      */
+    double seconds;                     /* host wall time of the call                         */
 } ov_solve_stats;
 
 /*
  * ov_solve -- x = (D_ov + mt)^{-1} bt for one right-hand side.
- *   W64, Wlo, params : as ov_apply (params->inner may be low precision with refinement)
+ *   W64, Wlo, params : as ov_apply (params->kl_n is the order of the operator solved for; Wlo is
+ *          needed when params->inner or any level's inner is low precision)
  *   mp    : mass, form, outer tolerance and iteration cap
+ *   nprec, prec : preconditioner chain, 0..BRI_MAX_LEVELS levels (prec may be NULL for 0);
+ *          prec[0] preconditions the outer operator, prec[k+1] preconditions prec[k]
  *   in    : b, [4][3][V] complex double;  out : x, same layout, must not overlap in
  *   work, work_bytes : device workspace (query with work == NULL)
  *   stats : may be NULL
  * Synchronises `stream`.  Returns BRI_ENOCONV when max_iter outer iterations did not reach tol
- * (out holds the last iterate), BRI_ENAN on a non-finite or breaking-down recurrence, the
- * status of a failing inner ov_apply, BRI_EINVAL for bad arguments (m outside [0, 2 rho)).
+ * (out holds the last iterate), BRI_ENAN on a non-finite or breaking-down outer recurrence, the
+ * status of a failing outer ov_apply, BRI_EINVAL for bad arguments (m outside [0, 2 rho), a
+ * Brillouin level that is not the last one).  Preconditioner levels that stop at their cap are
+ * not errors.
  */
 int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params,
-             const ov_mass_params *mp, const void *in, void *out, void *work, size_t *work_bytes,
-             ov_solve_stats *stats, void *stream);
+             const ov_mass_params *mp, int nprec, const ov_level *prec, const void *in, void *out, void *work,
+             size_t *work_bytes, ov_solve_stats *stats, void *stream);
 
 /*
  * Stencil launch configuration and autotuner.  A configuration picks the

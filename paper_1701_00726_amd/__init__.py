@@ -74,12 +74,28 @@ class _MassParams(ctypes.Structure):
     ]
 
 
+MAX_LEVELS = 4
+
+
+class _Level(ctypes.Structure):
+    _fields_ = [
+        ("kl_n", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("ms_tol", ctypes.c_double),
+        ("inner", ctypes.c_int),
+    ]
+
+
 class _SolveStats(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int),
         ("inner_iters", ctypes.c_int),
         ("applies", ctypes.c_int),
         ("rel_resid", ctypes.c_double),
+        ("level_iters", ctypes.c_int * MAX_LEVELS),
+        ("level_calls", ctypes.c_int * MAX_LEVELS),
+        ("level_applies", ctypes.c_int * MAX_LEVELS),
         ("seconds", ctypes.c_double),
     ]
 
@@ -118,6 +134,22 @@ class SolveStats:
     applies: int
     rel_resid: float
     seconds: float = 0.0
+    level_iters: list = field(default_factory=list)
+    level_calls: list = field(default_factory=list)
+    level_applies: list = field(default_factory=list)
+
+
+@dataclass
+class Level:
+    """One preconditioner level of the cascaded solve (Sec. 8): kl_n = 0 is the Brillouin
+    operator rho D_bri(-rho) + rho + mt (last level only), kl_n > 0 the overlap approximant of
+    that Kenney-Laub order plus mt.  It is inverted by BiCGstab to `tol` (relative) or
+    `max_iter` iterations; its multi-shift runs at `ms_tol` in precision `inner`."""
+    kl_n: int
+    tol: float = 0.1
+    max_iter: int = 50
+    ms_tol: float = 1e-4
+    inner: int = 0
 
 
 _lock = threading.Lock()
@@ -153,8 +185,8 @@ def load():
             lib.bri_set_solver_graphs.argtypes = [I]
             SZ = ctypes.POINTER(ctypes.c_size_t)
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
-            lib.ov_solve.argtypes = [G, P, P, ctypes.POINTER(_OvParams), ctypes.POINTER(_MassParams), P, P, P, SZ,
-                                     ctypes.POINTER(_SolveStats), P]
+            lib.ov_solve.argtypes = [G, P, P, ctypes.POINTER(_OvParams), ctypes.POINTER(_MassParams), I,
+                                     ctypes.POINTER(_Level), P, P, P, SZ, ctypes.POINTER(_SolveStats), P]
             lib.ov_apply_grad.argtypes = [G, P, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
                                           ctypes.POINTER(_OvStats), P]
             for fn in EXPORTS:
@@ -405,30 +437,37 @@ class OverlapOp:
         return F, GU, gpsi, s
 
 
-    def solve(self, b, mass, complete=True, tol=1e-10, max_iter=1000, stream=None, allow_noconv=False):
+    def solve(self, b, mass, complete=True, tol=1e-10, max_iter=1000, prec=(), stream=None, allow_noconv=False):
         """x = (D_ov + mt)^{-1} bt for one right-hand side b: the massive overlap
         equation of Sec. 4 (complete or traditional form), BiCGstab outer solver with
-        every D_ov apply run by this operator.  Returns (x, SolveStats)."""
+        every D_ov apply run by this operator, optionally right-preconditioned by the
+        cascade `prec` (a sequence of Level, Sec. 8).  Returns (x, SolveStats)."""
         torch = _torch()
         V = int(np.prod(self.L))
         if b.dtype != torch.complex128 or b.numel() != 12 * V:
             raise ValueError("b must be complex128 with 12 V elements")
         mp = _MassParams(float(mass), 1 if complete else 0, float(tol), int(max_iter))
-        if getattr(self, "_swork", None) is None:
-            nb = ctypes.c_size_t(0)
-            _check("ov_solve", load().ov_solve(ctypes.byref(self.g), None, None, ctypes.byref(self.params),
-                                               ctypes.byref(mp), None, None, None, ctypes.byref(nb), None, None))
+        nprec = len(prec)
+        lv = (_Level * max(nprec, 1))(*[_Level(int(l.kl_n), float(l.tol), int(l.max_iter), float(l.ms_tol),
+                                                int(l.inner)) for l in prec])
+        nb = ctypes.c_size_t(0)
+        _check("ov_solve", load().ov_solve(ctypes.byref(self.g), None, None, ctypes.byref(self.params),
+                                           ctypes.byref(mp), nprec, lv, None, None, None, ctypes.byref(nb), None,
+                                           None))
+        if getattr(self, "_swork", None) is None or self._swork.numel() < nb.value:
+            self._swork = None
             self._swork = torch.empty(int(nb.value), dtype=torch.uint8, device=self.W64.device)
         x = torch.empty_like(b)
         st = _SolveStats()
         wb = ctypes.c_size_t(self._swork.numel())
         rc = load().ov_solve(
             ctypes.byref(self.g), _dptr(self.W64), None if self.Wlo is None else _dptr(self.Wlo),
-            ctypes.byref(self.params), ctypes.byref(mp), _dptr(b), _dptr(x), _dptr(self._swork), ctypes.byref(wb),
-            ctypes.byref(st), _stream(stream),
+            ctypes.byref(self.params), ctypes.byref(mp), nprec, lv, _dptr(b), _dptr(x), _dptr(self._swork),
+            ctypes.byref(wb), ctypes.byref(st), _stream(stream),
         )
         _check("ov_solve", rc, allow=(ENOCONV,) if allow_noconv else ())
-        s = SolveStats(st.iters, st.inner_iters, st.applies, st.rel_resid, st.seconds)
+        s = SolveStats(st.iters, st.inner_iters, st.applies, st.rel_resid, st.seconds,
+                       list(st.level_iters[:nprec]), list(st.level_calls[:nprec]), list(st.level_applies[:nprec]))
         s.status = rc
         return x, s
 

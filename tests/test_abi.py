@@ -147,25 +147,70 @@ def test_massive_solve_workspace_and_invalid_args():
     assert st == bri.OK
     nb = ctypes.c_size_t(0)
     mp_ = bri._MassParams(0.1, 1, 1e-10, 100)
-    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), None, None, None,
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, None, None, None,
                         ctypes.byref(nb), None, None) == bri.OK
-    # the ov_apply workspace plus seven BiCGstab vectors (bt, r, r0, p, v, s, t) and dot partials
+    # the ov_apply workspace plus bt and eight BiCGstab vectors (r, r0, p, v, s, t, K p, K s) and
+    # dot partials
     vec = 12 * V * 16
-    assert ov_bytes + 7 * vec <= nb.value < ov_bytes + 7 * vec + (1 << 16)
+    assert ov_bytes + 9 * vec <= nb.value < ov_bytes + 9 * vec + (1 << 16)
     for bad in (bri._MassParams(-0.1, 1, 1e-10, 100), bri._MassParams(2.0, 1, 1e-10, 100),
                 bri._MassParams(0.1, 2, 1e-10, 100), bri._MassParams(0.1, 1, 0.0, 100),
                 bri._MassParams(0.1, 0, 1e-10, 0)):
-        assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(bad), None, None, None,
-                            ctypes.byref(nb), None, None) == bri.EINVAL
+        assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(bad), 0, None, None, None,
+                            None, ctypes.byref(nb), None, None) == bri.EINVAL
     # bad inner parameters are rejected through the ov_apply query
     badp = bri._OvParams(0, 1.0, 1e-12, 200, 0, 0)
-    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(badp), ctypes.byref(mp_), None, None, None,
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(badp), ctypes.byref(mp_), 0, None, None, None, None,
                         ctypes.byref(nb), None, None) == bri.EINVAL
     # a workspace that is too small, or in == out, is rejected before any launch
     small = ctypes.c_size_t(nb.value - 1)
     p = ctypes.c_void_p(256)
-    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), p, ctypes.c_void_p(512), p,
-                        ctypes.byref(small), None, None) == bri.EINVAL
+    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, p, ctypes.c_void_p(512),
+                        p, ctypes.byref(small), None, None) == bri.EINVAL
     full = ctypes.c_size_t(nb.value)
-    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), p, p, p,
+    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, p, p, p,
                         ctypes.byref(full), None, None) == bri.EINVAL
+
+
+def test_cascade_levels_validated():
+    lib = bri.load()
+    L = (8, 8, 8, 8)
+    V = 8**4
+    vec = 12 * V * 16
+    g = bri._geom(L)
+    prm = bri._OvParams(4, 1.0, 1e-12, 200, 0, 0)
+    mp_ = bri._MassParams(0.03, 1, 1e-9, 100)
+
+    def query(levels, n=None):
+        arr = (bri._Level * max(len(levels), 1))(*levels)
+        nb = ctypes.c_size_t(0)
+        st = lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_),
+                          len(levels) if n is None else n, arr, None, None, None, ctypes.byref(nb), None, None)
+        return st, nb.value
+
+    st0, nb0 = query([])
+    assert st0 == bri.OK
+    # the paper's two-level cascade for f_{4,4}: n = 1, then the Brillouin operator
+    st2, nb2 = query([bri._Level(1, 0.1, 20, 1e-6, 0), bri._Level(0, 0.1, 20, 0.0, 0)])
+    assert st2 == bri.OK and nb2 == nb0 + 2 * 8 * vec
+    bads = [
+        [bri._Level(0, 0.1, 20, 0.0, 0), bri._Level(1, 0.1, 20, 1e-6, 0)],  # Brillouin not last
+        [bri._Level(1, 0.0, 20, 1e-6, 0)],                                 # tol <= 0
+        [bri._Level(1, 0.1, 0, 1e-6, 0)],                                  # no iterations
+        [bri._Level(1, 0.1, 20, 0.0, 0)],                                  # multi-shift tol <= 0
+        [bri._Level(bri.MAX_SHIFTS + 1, 0.1, 20, 1e-6, 0)],                # order too large
+        [bri._Level(-1, 0.1, 20, 1e-6, 0)],
+        [bri._Level(1, 0.1, 20, 1e-6, 9)],                                 # unknown precision
+    ]
+    for lv in bads:
+        assert query(lv)[0] == bri.EINVAL, lv
+    assert query([bri._Level(1, 0.1, 20, 1e-6, 0)] * 5)[0] == bri.EINVAL  # more than BRI_MAX_LEVELS
+    assert query([], n=1)[0] == bri.EINVAL  # a level count without levels
+    # a low-precision level needs Wlo: rejected at the call, before any launch
+    arr = (bri._Level * 1)(bri._Level(1, 0.1, 20, 1e-5, 1))
+    nb = ctypes.c_size_t(0)
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 1, arr, None, None, None,
+                        ctypes.byref(nb), None, None) == bri.OK
+    p = ctypes.c_void_p(256)
+    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 1, arr, p,
+                        ctypes.c_void_p(512), p, ctypes.byref(nb), None, None) == bri.EINVAL

@@ -37,16 +37,24 @@ def _op(L, U, n, tol=1e-13, tbc=0, inner=bri.F64):
     return bri.OverlapOp(L, W, kl_n=n, rho=RHO, tol=tol, max_iter=3000, tbc=tbc, Wlo=Wlo, inner=inner)
 
 
+def _dense_dov(dov, n):
+    G = dov.fn_of_H(lambda lam: lam * kl.r_diag_f64(lam * lam, n))
+    return RHO * (np.eye(G.shape[0]) + dov.G5[:, None] * G)
+
+
 @pytest.fixture(scope="module")
-def dense4():
+def dense_dov4():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     U, Wo = field(L4, "cfg1")
-    dov = odense.DenseOverlap(oracle.dense_matrix(L4, Wo, -RHO), 256, RHO)
-    G = dov.fn_of_H(lambda lam: lam * kl.r_diag_f64(lam * lam, N))
-    D = RHO * (np.eye(3072) + dov.G5[:, None] * G)
+    return U, Wo, odense.DenseOverlap(oracle.dense_matrix(L4, Wo, -RHO), 256, RHO)
+
+
+@pytest.fixture(scope="module")
+def dense4(dense_dov4):
+    U, _, dov = dense_dov4
     b = synth.gaussian_source(L4, synth.SOURCE_SEED_BASE + 4)[0]
-    return U, D, b
+    return U, _dense_dov(dov, N), b
 
 
 def _dense_x(D, b, m, complete):
@@ -132,3 +140,70 @@ def test_solve_bench_lattice_residual():
     bt = ((1 + m / (2 * RHO)) * b - (m / (4 * RHO**2)) * Db) / den
     r = bt - (Dx + massive.mass_tilde(m, RHO) * x.reshape(b.shape))
     assert (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(bt)).item() < 1e-9
+
+
+# ------------------------------------------------------------- cascaded preconditioning (Sec. 8)
+
+TWO_LEVEL = [bri.Level(1, tol=0.1, max_iter=30, ms_tol=1e-8), bri.Level(0, tol=0.1, max_iter=30)]
+
+
+@pytest.mark.parametrize("n,levels", [
+    (1, [bri.Level(0, tol=0.1, max_iter=30)]),
+    (4, TWO_LEVEL),
+    (13, [bri.Level(4, tol=0.1, max_iter=20, ms_tol=1e-8)] + TWO_LEVEL),
+], ids=["f11_1level", "f44_2level", "f1313_3level"])
+def test_cascade_4_4_against_dense(dense_dov4, n, levels):
+    """The preconditioned solve reaches the solution of (D_ov^(n) + mt) x = bt (dense, same [n/n])."""
+    U, _, dov = dense_dov4
+    b = synth.gaussian_source(L4, synth.SOURCE_SEED_BASE + 4)[0]
+    op = _op(L4, U, n)
+    x, st = op.solve(bri.spinor_to_device(b[None]), M, complete=True, tol=1e-11, prec=levels)
+    want = _dense_x(_dense_dov(dov, n), b, M, True)
+    assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-9, (st.iters, st.level_iters)
+    assert st.status == bri.OK and st.rel_resid < 1e-10
+    assert all(c > 0 for c in st.level_calls) and all(i >= c for i, c in zip(st.level_iters, st.level_calls))
+    # two preconditioner applications per outer iteration (one when it stops half way)
+    assert 2 * st.iters - 1 <= st.level_calls[0] <= 2 * st.iters
+
+
+def test_cascade_iterations_match_oracle(dense4):
+    """Same algorithm on both sides: f_{4,4} with two levels at 4^4 takes the oracle's number of
+    outer iterations, and about its number of preconditioner iterations per level."""
+    U, _, b = dense4
+    _, Wo = field(L4, "cfg1")
+    levels = [(1, 0.1, 30, 1e-8), (0, 0.1, 30, 0.0)]
+    xo, ito, reso, counts = massive.ov_solve_cascade(L4, Wo, RHO, 4, M, b, levels, complete=True, tol=1e-11)
+    op = _op(L4, U, 4)
+    x, st = op.solve(bri.spinor_to_device(b[None]), M, complete=True, tol=1e-11, prec=TWO_LEVEL)
+    assert abs(st.iters - ito) <= 1, (st.iters, ito)
+    for got, want in zip(st.level_iters, counts):
+        assert abs(got - want) <= max(2, 0.1 * want), (st.level_iters, counts)
+    assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], xo) < 1e-9
+
+
+def test_cascade_low_precision_level(dense_dov4):
+    """A preconditioner level may run its multi-shift in FP32 links: the outer solution is unchanged."""
+    U, _, dov = dense_dov4
+    b = synth.gaussian_source(L4, synth.SOURCE_SEED_BASE + 4)[0]
+    op = _op(L4, U, 4, inner=bri.F32)
+    op.params.inner = bri.F64  # the outer level in FP64, the preconditioner in FP32
+    levels = [bri.Level(1, tol=0.1, max_iter=30, ms_tol=1e-5, inner=bri.F32), bri.Level(0, tol=0.1, max_iter=30)]
+    x, st = op.solve(bri.spinor_to_device(b[None]), M, complete=True, tol=1e-11, prec=levels)
+    want = _dense_x(_dense_dov(dov, 4), b, M, True)
+    assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-9
+    assert st.status == bri.OK
+
+
+def test_cascade_bench_lattice():
+    """16^4 smeared field, am = 0.05: f_{4,4} with and without the two-level cascade reach the
+    same x, the cascade with far fewer outer iterations."""
+    need_gpu()
+    L = (16, 16, 16, 16)
+    U, _ = field(L, "cfg2")
+    op = _op(L, U, 4, tol=1e-12)
+    b = bri.spinor_to_device(synth.gaussian_source(L, synth.SOURCE_SEED_BASE + 16))
+    x0, st0 = op.solve(b, 0.05, complete=True, tol=1e-10)
+    x1, st1 = op.solve(b, 0.05, complete=True, tol=1e-10, prec=TWO_LEVEL)
+    assert st0.rel_resid < 1e-9 and st1.rel_resid < 1e-9
+    assert (torch.linalg.vector_norm(x1 - x0) / torch.linalg.vector_norm(x0)).item() < 1e-8
+    assert 3 * st1.iters < st0.iters, (st0.iters, st1.iters, st1.level_iters)
