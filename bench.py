@@ -467,6 +467,15 @@ def main():
         ms_f = timed(lambda: bri.link_grad(L, U, W, pairs), 3)
         extra["grad_fp64_1src"] = {"ms_per_call": ms_g, "ratio_to_step": ms_g / ms_step,
                                    "link_force_ms_%d_pairs" % (2 * KL_N + 1): ms_f}
+        # relaxed per-shift stopping (tol * omega_max / omega_i) against the strict apply
+        opr = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, relax=True)
+        orl = torch.empty_like(b)
+        _, str_ = opr.apply(b, out=orl)
+        ms_r = timed(lambda: opr.apply(b, out=orl), 10)
+        extra["relaxed_fp64_1src"] = {
+            "applies_per_s": 1 / (ms_r / 1e3), "ms_per_call": ms_r, "cg_iterations": str_.iters,
+            "rel_diff_vs_strict": float(torch.linalg.vector_norm(orl - ref64) / torch.linalg.vector_norm(ref64))}
+        del opr, orl
         # massive overlap solve, complete form of Sec. 4 with the BiCGstab outer solver, am = 0.05
         xs, sts = op.solve(b, MASS, complete=True, tol=OUTER_TOL)
         ms_s = timed(lambda: op.solve(b, MASS, complete=True, tol=OUTER_TOL), 1)

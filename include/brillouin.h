@@ -101,6 +101,13 @@ int bri_apply(const bri_geom *geom, const void *W, int prec, double m0, const vo
 int bri_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
                   void *stream);
 
+/* Kenney-Laub family member used for sign(H) (ov_params.kind). */
+enum bri_kl_kind {
+    BRI_KL_DIAG = 0, /* diagonal f_{n,n} = g_{2n+1}, eq. (KLnn_parfrac): c0 + n poles           */
+    BRI_KL_UPPER = 1 /* first upper diagonal f_{n-1,n} = g_{2n} (Sec. 3.3, Tab. 6): n poles, no
+                        constant term                                                         */
+};
+
 /* Parameters of the overlap applies. */
 typedef struct {
     int kl_n;       /* Kenney-Laub order n: f_{n,n} = g_{2n+1}, 1..BRI_MAX_SHIFTS */
@@ -110,6 +117,10 @@ typedef struct {
     int inner;      /* bri_prec of the multi-shift: BRI_F64, or BRI_F32 /
                        BRI_F32_BF16W with FP64 defect correction of every shift */
     int max_refine; /* mixed precision: FP64 residual + correction passes, 0..100 */
+    int kind;       /* bri_kl_kind; BRI_KL_DIAG unless stated                   */
+    int relax;      /* 1: shift i stops at tol * omega_max / omega_i (App. B: the
+                       weights grow with the shift, so small shifts may stop at a
+                       larger residual); 0: every shift at tol                  */
 } ov_params;
 
 /* Statistics of one overlap apply (the last right-hand side for nrhs > 1). */
@@ -264,6 +275,11 @@ int bri_set_solver_graphs(int enable);
 /* Kenney-Laub coefficients c0, omega[n], sigma[n] of f_{n,n} (eq. (KLnn_parfrac)),
  * computed in double precision on the host; sigma ascending. */
 int bri_kl_coeffs(int n, double *c0, double *omega, double *sigma);
+
+/* Coefficients omega[n], sigma[n] of the first upper diagonal f_{n-1,n} = g_{2n}
+ * = x sum_i omega_i / (x^2 + sigma_i) (Sec. 3.3; Tab. 6 for n <= 3), host double precision,
+ * sigma ascending.  BRI_EINVAL for n outside 1..BRI_MAX_SHIFTS or NULL pointers. */
+int bri_kl_upper_coeffs(int n, double *omega, double *sigma);
 
 /*
  * Differentiation (Sec. 9: the molecular-dynamics force is the derivative with

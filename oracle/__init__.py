@@ -210,11 +210,41 @@ def cg(L, W, m0: float, sigma: float, b: np.ndarray, tol: float = 1e-13, maxit: 
     return x, it, rel.value
 
 
-def rational_apply(L, W, m0: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
+def kl_coeffs(n: int, kind: str = "diag"):
+    """(c0, omega, sigma) in double precision: g_{2n+1} (kind "diag") or g_{2n} (kind "upper",
+    c0 = 0)."""
+    if kind == "diag":
+        return kl.kl_diag_coeffs_f64(n)
+    if kind == "upper":
+        om, sg = kl.kl_upper_coeffs(n)
+        return 0.0, [float(v) for v in om], [float(v) for v in sg]
+    raise ValueError(kind)
+
+
+def rational_apply(L, W, m0: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000,
+                   kind: str = "diag", relax: bool = False):
     """y = r_n(D^dag D) b = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, shifts solved one by one.
 
-    Returns (y, iters per shift, true relative residual per shift)."""
-    c0, om, sg = kl.kl_diag_coeffs_f64(n)
+    kind "diag": the coefficients of g_{2n+1} (eq. (KLnn_parfrac)); "upper": those of g_{2n}
+    (Sec. 3.3), c0 = 0.  relax: shift i is solved to tol * max(omega) / omega_i instead of tol
+    (App. B).  Returns (y, iters per shift, true relative residual per shift)."""
+    c0, om, sg = kl_coeffs(n, kind)
+    if relax:
+        wmax = max(om)
+        y = c0 * _c128(b)
+        iters = np.zeros(n, dtype=np.int32)
+        rel = np.zeros(n, dtype=np.float64)
+        for i in range(n):
+            yi, it_i, rel_i = rational_apply_coeffs(L, W, m0, 0.0, [om[i]], [sg[i]], b, tol * wmax / om[i], maxit)
+            y = y + yi
+            iters[i], rel[i] = it_i[0], rel_i[0]
+        return y, iters, rel
+    return rational_apply_coeffs(L, W, m0, c0, om, sg, b, tol, maxit)
+
+
+def rational_apply_coeffs(L, W, m0: float, c0: float, om, sg, b: np.ndarray, tol: float, maxit: int):
+    """y = c0 b + sum_i om_i (D^dag D + sg_i)^{-1} b for given coefficients, each shift by its own CG."""
+    n = len(om)
     b = _c128(b)
     y = np.zeros_like(b)
     om = np.ascontiguousarray(om, dtype=np.float64)
@@ -228,16 +258,19 @@ def rational_apply(L, W, m0: float, n: int, b: np.ndarray, tol: float = 1e-13, m
     return y, iters, rel
 
 
-def sign_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
-    """g_{2n+1}(H) b with H = gamma5 D(-rho):  g(H) = H r_n(H^2), H^2 = D^dag D, so
-    g(H) b = gamma5 D r_n(D^dag D) b."""
-    y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit)
+def sign_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000,
+               kind: str = "diag", relax: bool = False):
+    """g_{2n+1}(H) b (or g_{2n}(H) b for kind "upper") with H = gamma5 D(-rho):
+    g(H) = H r_n(H^2), H^2 = D^dag D, so g(H) b = gamma5 D r_n(D^dag D) b."""
+    y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit, kind, relax)
     return gamma5_apply(dirac(L, W, -rho, y)), iters, rel
 
 
-def ov_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000):
-    """D_ov b = rho (1 + gamma5 g_{2n+1}(H)) b = rho (b + D(-rho) r_n(D^dag D) b), eq. (def_over)."""
-    y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit)
+def ov_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000,
+             kind: str = "diag", relax: bool = False):
+    """D_ov b = rho (1 + gamma5 g(H)) b = rho (b + D(-rho) r_n(D^dag D) b), eq. (def_over), with
+    g = g_{2n+1} (kind "diag") or g_{2n} (kind "upper")."""
+    y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit, kind, relax)
     return rho * (b + dirac(L, W, -rho, y)), iters, rel
 
 
@@ -266,15 +299,16 @@ def link_force(L, U: np.ndarray, tbc: int, pairs) -> np.ndarray:
 
 
 def ov_force(L, U: np.ndarray, tbc: int, rho: float, n: int, chi: np.ndarray, psi: np.ndarray,
-             tol: float = 1e-13, maxit: int = 10000):
+             tol: float = 1e-13, maxit: int = 10000, kind: str = "diag"):
     """Gradient of S = Re chi^dag D_ov psi, D_ov = rho (1 + X r_n(X^dag X)), X = D_bri(-rho).
 
     With a_i = (A + sigma_i)^{-1} psi, b_i = (A + sigma_i)^{-1} X^dag chi, A = X^dag X and
     y = c0 psi + sum_i omega_i a_i, the derivative of the partial fractions gives
       dS = rho Re[chi^dag dX y] - rho sum_i omega_i Re[(X a_i)^dag dX b_i + (X b_i)^dag dX a_i],
     and grad_psi S = D_ov^dag chi = rho (chi + c0 X^dag chi + sum_i omega_i b_i).
+    kind selects g_{2n+1} or g_{2n} as in rational_apply.
     Returns (F (4, V, 8), grad_psi (V, 4, 3))."""
-    c0, om, sg = kl.kl_diag_coeffs_f64(n)
+    c0, om, sg = kl_coeffs(n, kind)
     W = links(L, U, tbc)
     m0 = -rho
     xdc = dirac_adj(L, W, m0, chi)

@@ -29,6 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbrillouin.so")
 
 F64, F32, F32_BF16W = 0, 1, 2
+KL_DIAG, KL_UPPER = 0, 1
 OK, EINVAL, ENOCONV, ENAN, EHIP = 0, -1, -2, -3, -4
 MAX_SHIFTS = 32
 STATUS_NAMES = {OK: "BRI_OK", EINVAL: "BRI_EINVAL", ENOCONV: "BRI_ENOCONV", ENAN: "BRI_ENAN", EHIP: "BRI_EHIP"}
@@ -52,6 +53,8 @@ class _OvParams(ctypes.Structure):
         ("max_iter", ctypes.c_int),
         ("inner", ctypes.c_int),
         ("max_refine", ctypes.c_int),
+        ("kind", ctypes.c_int),
+        ("relax", ctypes.c_int),
     ]
 
 
@@ -185,6 +188,7 @@ def load():
             lib.bri_set_solver_graphs.argtypes = [I]
             SZ = ctypes.POINTER(ctypes.c_size_t)
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
+            lib.bri_kl_upper_coeffs.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D)]
             lib.ov_solve.argtypes = [G, P, P, ctypes.POINTER(_OvParams), ctypes.POINTER(_MassParams), I,
                                      ctypes.POINTER(_Level), P, P, P, SZ, ctypes.POINTER(_SolveStats), P]
             lib.ov_apply_grad.argtypes = [G, P, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
@@ -209,6 +213,7 @@ EXPORTS = (
     "bri_link_grad",
     "ov_apply_grad",
     "ov_solve",
+    "bri_kl_upper_coeffs",
     "bri_set_solver_graphs",
 )
 MAX_PAIRS = 2 * MAX_SHIFTS + 1
@@ -342,10 +347,12 @@ class OverlapOp:
     """Holds the workspace of ov_apply / ov_sign_apply for one lattice and parameter set."""
 
     def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0,
-                 max_refine=None, nrhs=1):
+                 max_refine=None, nrhs=1, kind=KL_DIAG, relax=False):
         """Workspace for up to `nrhs` right-hand sides per call.  inner = F32 or
         F32_BF16W runs the multi-shift with the low-precision links `Wlo` and refines
-        every shift in FP64 (at most max_refine passes, default 10)."""
+        every shift in FP64 (at most max_refine passes, default 10).  kind = KL_UPPER
+        uses the first upper diagonal g_{2n} instead of g_{2n+1}; relax stops shift i
+        at tol * omega_max / omega_i."""
         self.L = tuple(int(v) for v in L)
         self.g = _geom(self.L, tbc)
         self.W64 = W64
@@ -354,7 +361,8 @@ class OverlapOp:
             raise ValueError("a low-precision inner solve needs Wlo")
         if max_refine is None:
             max_refine = 0 if inner == F64 else 10
-        self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine))
+        self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine),
+                                int(kind), 1 if relax else 0)
         self.nrhs = int(nrhs)
         nbytes = ctypes.c_size_t(0)
         _check(
@@ -475,6 +483,14 @@ class OverlapOp:
 def set_solver_graphs(enable):
     """Turn HIP-graph replay of the multi-shift CG loop on (default) or off."""
     _check("bri_set_solver_graphs", load().bri_set_solver_graphs(1 if enable else 0))
+
+
+def kl_upper_coeffs(n):
+    """(omega[n], sigma[n]) of g_{2n} as computed by the library's host code."""
+    om = (ctypes.c_double * n)()
+    sg = (ctypes.c_double * n)()
+    _check("bri_kl_upper_coeffs", load().bri_kl_upper_coeffs(int(n), om, sg))
+    return list(om), list(sg)
 
 
 def kl_coeffs(n):

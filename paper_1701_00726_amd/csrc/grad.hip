@@ -36,6 +36,10 @@ namespace bri {
 // ([shift][ncol][12 V] in the workspace); with work == NULL only *need is set (solver.hip).
 int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_params *prm, const void *b, int ncol,
                     void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st);
+// the rational of `prm` (diagonal or upper-diagonal coefficients, per-shift tolerance factors) and
+// the validity check of its fields (solver.hip)
+void shift_coeffs(const ov_params *prm, double *c0, double *omega, double *sigma, double *tolf);
+bool params_ok(const ov_params *prm);
 
 __device__ __forceinline__ int dj(int j, int mu) { return disp_comp(j, mu); }
 
@@ -481,11 +485,7 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     if (rc != BRI_OK) return rc;
     if (!prm || !work_bytes) return BRI_EINVAL;
     const int n = prm->kl_n;
-    if (n < 1 || n > MAXS || !(prm->rho > 0.0 && prm->rho < 2.0) || !(prm->tol > 0.0) || prm->max_iter < 1 ||
-        g.V % 64)
-        return BRI_EINVAL;
-    if (prm->inner != BRI_F64 && prm->inner != BRI_F32 && prm->inner != BRI_F32_BF16W) return BRI_EINVAL;
-    if (prm->max_refine < 0 || prm->max_refine > 100) return BRI_EINVAL;
+    if (!params_ok(prm) || g.V % 64) return BRI_EINVAL;
     GradPlan pl;
     rc = plan_grad(g, prm, pl);
     if (rc != BRI_OK) return rc;
@@ -525,8 +525,8 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     int rcs = ov_solve_shifts(g, W64, Wlo, prm, BIN, 2, swork, pl.solver_bytes, nullptr, s, &xs, &sst);
     if (rcs != BRI_OK && rcs != BRI_ENOCONV) return rcs;
     const double2 *X = (const double2 *)xs;
-    double c0, om[MAXS], sg[MAXS];
-    bri_kl_coeffs(n, &c0, om, sg);
+    double c0, om[MAXS], sg[MAXS], tf[MAXS];
+    shift_coeffs(prm, &c0, om, sg, tf);
     BRI_HIP_CHECK(hipMemcpyAsync(om_dev, om, sizeof(double) * n, hipMemcpyHostToDevice, s));
     // y = c0 psi + sum omega_i a_i ; gpsi = rho (chi + c0 X^dag chi + sum omega_i b_i)
     hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, c0, (const double2 *)psi, 0.0,

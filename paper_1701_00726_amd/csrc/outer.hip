@@ -253,6 +253,8 @@ static ov_params level_params(const ov_params *top, const ov_level &l) {
     p.kl_n = l.kl_n;
     p.tol = l.ms_tol;
     p.inner = l.inner;
+    p.kind = BRI_KL_DIAG;  // the cascade nests f_{1,1}: diagonal approximants only
+    p.relax = 0;
     if (p.inner != BRI_F64 && p.max_refine == 0) p.max_refine = 10;
     return p;
 }

@@ -204,7 +204,7 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
             st->zeta_old[i] = st->zeta[i];
             st->zeta[i] = st->zeta_new[i];
             const double res2 = st->zeta[i] * st->zeta[i] * rr_new;
-            if (res2 <= st->tol2) {
+            if (res2 <= st->tol2 * st->tolf2[i]) {
                 st->active[i] = 0;
                 st->conv_iter[i] = it;
                 st->conv_res[i] = sqrt(res2 / st->bnorm2);
@@ -359,6 +359,53 @@ void kl_coeffs(int n, double *c0, double *omega, double *sigma) {
     }
 }
 
+// First upper diagonal f_{n-1,n} = g_{2n} (Sec. 3.3, App. B): g_2n(x) = (x/n) sum_{i<n}
+// 1 / (sin^2 theta_i + cos^2 theta_i x^2), theta_i = (2i+1) pi / (4n), i.e. no constant term,
+// omega_i = 1 / (n cos^2 theta_i), sigma_i = tan^2 theta_i (complementary angle past pi/4).
+void kl_upper_coeffs(int n, double *omega, double *sigma) {
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        if (2 * i + 1 <= n) {  // theta <= pi/4
+            const double th = (2.0 * i + 1.0) * pi / (4.0 * n);
+            const double cs = cos(th), tn = tan(th);
+            omega[i] = 1.0 / (n * cs * cs);
+            sigma[i] = tn * tn;
+        } else {
+            const double ph = (2.0 * (n - i) - 1.0) * pi / (4.0 * n);
+            const double sn = sin(ph), tn = tan(ph);
+            omega[i] = 1.0 / (n * sn * sn);
+            sigma[i] = 1.0 / (tn * tn);
+        }
+    }
+}
+
+// The rational of an overlap apply: c0, omega, sigma of the diagonal or first upper diagonal
+// Kenney-Laub function, and the per-shift factor on the stopping tolerance: 1, or with
+// relaxation omega_max / omega_i (App. B: the weights grow with the shift, so the small shifts,
+// whose terms carry small weights, may stop at a larger residual).
+void shift_coeffs(const ov_params *prm, double *c0, double *omega, double *sigma, double *tolf) {
+    const int n = prm->kl_n;
+    if (prm->kind == BRI_KL_UPPER) {
+        *c0 = 0.0;
+        kl_upper_coeffs(n, omega, sigma);
+    } else {
+        kl_coeffs(n, c0, omega, sigma);
+    }
+    double wmax = 0.0;
+    for (int i = 0; i < n; ++i) wmax = omega[i] > wmax ? omega[i] : wmax;
+    for (int i = 0; i < n; ++i) tolf[i] = prm->relax ? wmax / omega[i] : 1.0;
+}
+
+bool params_ok(const ov_params *prm) {
+    const int n = prm->kl_n;
+    if (n < 1 || n > MAXS || !(prm->rho > 0.0 && prm->rho < 2.0) || !(prm->tol > 0.0) || prm->max_iter < 1)
+        return false;
+    if (prm->inner != BRI_F64 && prm->inner != BRI_F32 && prm->inner != BRI_F32_BF16W) return false;
+    if (prm->max_refine < 0 || prm->max_refine > 100) return false;
+    if (prm->kind != BRI_KL_DIAG && prm->kind != BRI_KL_UPPER) return false;
+    return prm->relax == 0 || prm->relax == 1;
+}
+
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // bump allocator over the caller's workspace (only counts bytes when base is NULL)
@@ -384,6 +431,7 @@ struct MsSolve {
     double c0 = 0.0;
     std::vector<double> omega;  // [nshift]
     std::vector<double> sigma;  // [ncol][nshift], ascending per column
+    std::vector<double> tolf;   // [nshift] factor on tol per shift (empty: 1)
     double tol = 1e-12;
     int max_iter = 1000;
     // workspace pieces
@@ -499,6 +547,8 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
         for (int i = 0; i < s.nshift; ++i) {
             cs.omega[i] = s.omega[i];
             cs.delta[i] = s.sigma[(size_t)c * s.nshift + i] - cs.sigma0;
+            const double f = s.tolf.empty() ? 1.0 : s.tolf[i];
+            cs.tolf2[i] = f * f;
         }
     }
     BRI_HIP_CHECK(hipMemcpyAsync(s.st, h.data(), sizeof(ColState) * s.ncol, hipMemcpyHostToDevice, strm));
@@ -619,7 +669,7 @@ constexpr int REFINE_CHUNK = 32;  // (shift, source) columns per refinement batc
 struct OvPlan {
     int n = 0, nrhs = 0, chunk = 0;
     bool mixed = false;
-    double c0 = 0.0, om[MAXS], sg[MAXS];
+    double c0 = 0.0, om[MAXS], sg[MAXS], tolf[MAXS];
     MsSolve main;                 // FP64: y accumulated; mixed: every x^sigma kept
     MsSolve corr;                 // mixed: batched single-shift corrections
     double2 *x64 = nullptr;       // mixed: [n][nrhs][12V] FP64 shift solutions
@@ -637,7 +687,7 @@ static void plan_overlap(OvPlan &pl, const Geom &g, const ov_params *prm, int nr
     pl.n = prm->kl_n;
     pl.nrhs = nrhs;
     pl.mixed = prm->inner != BRI_F64;
-    kl_coeffs(pl.n, &pl.c0, pl.om, pl.sg);
+    shift_coeffs(prm, &pl.c0, pl.om, pl.sg, pl.tolf);
     Arena ar(work);
     MsSolve &m = pl.main;
     m.g = g;
@@ -649,6 +699,7 @@ static void plan_overlap(OvPlan &pl, const Geom &g, const ov_params *prm, int nr
     m.store_x = pl.mixed;
     m.c0 = pl.c0;
     m.omega.assign(pl.om, pl.om + pl.n);
+    m.tolf.assign(pl.tolf, pl.tolf + pl.n);
     m.sigma.resize((size_t)nrhs * pl.n);
     for (int c = 0; c < nrhs; ++c)
         for (int i = 0; i < pl.n; ++i) m.sigma[(size_t)c * pl.n + i] = pl.sg[i];
@@ -746,7 +797,7 @@ static int refine(OvPlan &pl, const Geom &g, const ov_params *prm, const void *W
                 if (!isfinite(rel)) return BRI_ENAN;
                 const int sh = col / nrhs;
                 if (rel > shift_res[sh]) shift_res[sh] = rel;
-                if (rel > prm->tol) chunk_ok = false;
+                if (rel > prm->tol * pl.tolf[sh]) chunk_ok = false;
             }
             if (chunk_ok || pass >= prm->max_refine) {
                 all_ok = all_ok && chunk_ok;
@@ -781,10 +832,7 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     if (rc != BRI_OK) return rc;
     if (!prm || !work_bytes) return BRI_EINVAL;
     const int n = prm->kl_n;
-    if (n < 1 || n > MAXS || !(prm->rho > 0.0 && prm->rho < 2.0) || !(prm->tol > 0.0) || prm->max_iter < 1)
-        return BRI_EINVAL;
-    if (prm->inner != BRI_F64 && prm->inner != BRI_F32 && prm->inner != BRI_F32_BF16W) return BRI_EINVAL;
-    if (prm->max_refine < 0 || prm->max_refine > 100) return BRI_EINVAL;
+    if (!params_ok(prm)) return BRI_EINVAL;
     if (g.V % 64 || nrhs < 1 || nrhs > 4096) return BRI_EINVAL;
     OvPlan pl;
     plan_overlap(pl, g, prm, nrhs, W64, Wlo, nullptr);
@@ -891,9 +939,10 @@ int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_pa
         m.ncol = ncol;
         m.nshift = n;
         m.store_x = true;
-        double om[MAXS], sg[MAXS];
-        kl_coeffs(n, &m.c0, om, sg);
+        double om[MAXS], sg[MAXS], tf[MAXS];
+        shift_coeffs(prm, &m.c0, om, sg, tf);
         m.omega.assign(om, om + n);
+        m.tolf.assign(tf, tf + n);
         m.sigma.resize((size_t)ncol * n);
         for (int c = 0; c < ncol; ++c)
             for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];
@@ -954,6 +1003,12 @@ int bri_set_solver_graphs(int enable) {
     std::lock_guard<std::mutex> lk(bri::g_graph_mu);
     bri::g_graphs_on = enable == 1;
     if (!bri::g_graphs_on) bri::graph_cache_clear_locked();
+    return BRI_OK;
+}
+
+int bri_kl_upper_coeffs(int n, double *omega, double *sigma) {
+    if (n < 1 || n > BRI_MAX_SHIFTS || !omega || !sigma) return BRI_EINVAL;
+    bri::kl_upper_coeffs(n, omega, sigma);
     return BRI_OK;
 }
 

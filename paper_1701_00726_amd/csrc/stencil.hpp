@@ -16,6 +16,7 @@ struct ColState {
     int iter, done, status, nshift;
     double c0;
     double delta[MAXS], omega[MAXS];
+    double tolf2[MAXS];     // squared per-shift factor on the stopping tolerance
     double zeta[MAXS], zeta_old[MAXS], zeta_new[MAXS];
     double alpha_s[MAXS], beta_s[MAXS];
     int active[MAXS];       // shift still iterating

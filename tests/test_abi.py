@@ -214,3 +214,31 @@ def test_cascade_levels_validated():
     p = ctypes.c_void_p(256)
     assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 1, arr, p,
                         ctypes.c_void_p(512), p, ctypes.byref(nb), None, None) == bri.EINVAL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 16, 32])
+def test_host_upper_diagonal_coefficients_match_oracle(n):
+    om, sg = bri.kl_upper_coeffs(n)
+    rom, rsg = kl.kl_upper_coeffs(n)
+    assert sg == sorted(sg)
+    for a, b in zip(om, rom):
+        assert abs(mp.mpf(a) - b) <= 6e-16 * abs(b)
+    for a, b in zip(sg, rsg):
+        assert abs(mp.mpf(a) - b) <= 6e-16 * abs(b)
+
+
+def test_kind_and_relax_validated():
+    assert _ov_query((8, 8, 8, 8))[0] == bri.OK
+    lib = bri.load()
+    g = bri._geom((8, 8, 8, 8))
+    nb = ctypes.c_size_t(0)
+    for kind, relax, want in ((1, 0, bri.OK), (0, 1, bri.OK), (1, 1, bri.OK), (2, 0, bri.EINVAL),
+                              (-1, 0, bri.EINVAL), (0, 2, bri.EINVAL)):
+        prm = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0, kind, relax)
+        assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb),
+                            None, None) == want, (kind, relax)
+        assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None,
+                                 None, ctypes.byref(nb), None, None) == want, (kind, relax)
+    om = (ctypes.c_double * 1)()
+    assert lib.bri_kl_upper_coeffs(0, om, om) == bri.EINVAL
+    assert lib.bri_kl_upper_coeffs(bri.MAX_SHIFTS + 1, om, om) == bri.EINVAL
