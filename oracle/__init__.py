@@ -72,9 +72,12 @@ def _load():
             lib.orc_dirac_dense.argtypes = [P, P, D, P]
             lib.orc_gamma.argtypes = [I, P]
             lib.orc_spin_matrix.argtypes = [I, D, P]
-            lib.orc_cg.argtypes = [P, P, D, D, P, P, D, I, P]
+            lib.orc_wilson.argtypes = [P, I, P, D, P, P, I]
+            lib.orc_wilson_adj.argtypes = [P, I, P, D, P, P, I]
+            lib.orc_wilson_dense.argtypes = [P, I, P, D, P]
+            lib.orc_cg.argtypes = [P, I, I, P, D, D, P, P, D, I, P]
             lib.orc_cg.restype = I
-            lib.orc_rational.argtypes = [P, P, D, I, D, P, P, P, P, D, I, P, P]
+            lib.orc_rational.argtypes = [P, I, I, P, D, I, D, P, P, P, P, D, I, P, P]
             lib.orc_rational.restype = I
             lib.orc_num_threads.restype = I
             lib.orc_lambda.argtypes = [I, P]
@@ -141,35 +144,59 @@ def links(L, U: np.ndarray, tbc: int = 0) -> np.ndarray:
     return W
 
 
-def _apply(fn, L, W, m0, psi):
+class WilsonKernel:
+    """The Wilson operator of eq. (def_wils) (c_SW = 0) as the kernel: the gauge field U
+    (4, V, 3, 3) and the t boundary condition.  Wherever the functions below take the Brillouin
+    link array W, an instance of this class selects the Wilson operator instead."""
+
+    def __init__(self, U: np.ndarray, tbc: int = 0):
+        self.U = _c128(U)
+        self.tbc = int(tbc)
+
+
+def _kernel_args(W):
+    """(kern, tbc, array) for the C solvers: 0 = Brillouin link array, 1 = Wilson gauge field."""
+    if isinstance(W, WilsonKernel):
+        return 1, W.tbc, W.U
+    return 0, 0, _c128(W)
+
+
+def _apply(fn, L, W, m0, psi, wfn=None):
     V = volume(L)
     psi = _c128(psi)
     squeeze = psi.ndim == 3
     if squeeze:
         psi = psi[None]
     assert psi.shape[1:] == (V, 4, 3)
-    W = _c128(W)
     out = np.zeros_like(psi)
-    fn(_ptr(_geom(L)), _ptr(W), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
+    if isinstance(W, WilsonKernel):
+        assert W.U.shape == (4, V, 3, 3)
+        wfn(_ptr(_geom(L)), W.tbc, _ptr(W.U), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
+    else:
+        W = _c128(W)
+        fn(_ptr(_geom(L)), _ptr(W), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
     return out[0] if squeeze else out
 
 
 def dirac(L, W, m0: float, psi: np.ndarray) -> np.ndarray:
-    """D_bri(m0) psi, direct 81-term sum."""
-    return _apply(_load().orc_dirac, L, W, m0, psi)
+    """D_bri(m0) psi, direct 81-term sum (D_wil(m0) psi for a WilsonKernel)."""
+    return _apply(_load().orc_dirac, L, W, m0, psi, _load().orc_wilson)
 
 
 def dirac_adj(L, W, m0: float, psi: np.ndarray) -> np.ndarray:
-    """D_bri(m0)^dag psi by the transposed sum (no gamma5 trick)."""
-    return _apply(_load().orc_dirac_adj, L, W, m0, psi)
+    """D(m0)^dag psi by the transposed sum (no gamma5 trick); Brillouin or Wilson."""
+    return _apply(_load().orc_dirac_adj, L, W, m0, psi, _load().orc_wilson_adj)
 
 
 def dense_matrix(L, W, m0: float) -> np.ndarray:
-    """Dense D_bri(m0), index 12*site + 3*spin + colour."""
+    """Dense D_bri(m0) (or D_wil(m0) for a WilsonKernel), index 12*site + 3*spin + colour."""
     V = volume(L)
     n = 12 * V
     M = np.zeros((n, n), dtype=np.complex128)
-    _load().orc_dirac_dense(_ptr(_geom(L)), _ptr(_c128(W)), float(m0), _ptr(M))
+    if isinstance(W, WilsonKernel):
+        _load().orc_wilson_dense(_ptr(_geom(L)), W.tbc, _ptr(W.U), float(m0), _ptr(M))
+    else:
+        _load().orc_dirac_dense(_ptr(_geom(L)), _ptr(_c128(W)), float(m0), _ptr(M))
     return M
 
 
@@ -203,8 +230,9 @@ def cg(L, W, m0: float, sigma: float, b: np.ndarray, tol: float = 1e-13, maxit: 
     b = _c128(b)
     x = np.zeros_like(b)
     rel = ctypes.c_double(0)
+    kern, tbc, arr = _kernel_args(W)
     it = _load().orc_cg(
-        _ptr(_geom(L)), _ptr(_c128(W)), float(m0), float(sigma), _ptr(b), _ptr(x), float(tol), int(maxit),
+        _ptr(_geom(L)), kern, tbc, _ptr(arr), float(m0), float(sigma), _ptr(b), _ptr(x), float(tol), int(maxit),
         ctypes.byref(rel),
     )
     return x, it, rel.value
@@ -251,8 +279,9 @@ def rational_apply_coeffs(L, W, m0: float, c0: float, om, sg, b: np.ndarray, tol
     sg = np.ascontiguousarray(sg, dtype=np.float64)
     iters = np.zeros(n, dtype=np.int32)
     rel = np.zeros(n, dtype=np.float64)
+    kern, tbc, arr = _kernel_args(W)
     _load().orc_rational(
-        _ptr(_geom(L)), _ptr(_c128(W)), float(m0), int(n), float(c0), _ptr(om), _ptr(sg), _ptr(b), _ptr(y),
+        _ptr(_geom(L)), kern, tbc, _ptr(arr), float(m0), int(n), float(c0), _ptr(om), _ptr(sg), _ptr(b), _ptr(y),
         float(tol), int(maxit), _ptr(iters), _ptr(rel),
     )
     return y, iters, rel

@@ -36,7 +36,11 @@
  *   orc_dirac_at, orc_dirac_adj_at  D psi and D^dag psi at listed sites only, with
  *                  the links of those sites (and their neighbours) built on the
  *                  fly, for lattices too large for the full link array.
- *   orc_cg         textbook conjugate gradient on (D^dag D + sigma) x = b.
+ *   orc_wilson, orc_wilson_adj, orc_wilson_dense  the Wilson operator of eq. (def_wils)
+ *                  (c_SW = 0) from its covariant derivative and 9-point Laplacian, applied
+ *                  block by block straight from U; the adjoint as the transposed sum.
+ *   orc_cg         textbook conjugate gradient on (D^dag D + sigma) x = b, for either kernel
+ *                  (kern 0: Brillouin with its link array W; kern 1: Wilson with U and tbc).
  *   orc_rational   y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, every
  *                  shift solved separately (eq. (KLnn_parfrac) with
  *                  X^dag X = D^dag D).
@@ -458,6 +462,117 @@ void orc_dirac_adj_at(const int *L, int tbc, const cplx *U, double m0, const cpl
     }
 }
 
+/* ------------------------------------------------------------ Wilson kernel */
+
+/*
+ * The Wilson operator, eq. (def_wils) with c_SW = 0:
+ *   D_wil = sum_mu gamma_mu nabla_mu - (1/2) lap + m0,
+ *   nabla_mu psi(x) = (1/2) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)],
+ *   lap psi(x) = sum_mu [U_mu(x) psi(x+mu) + U_mu(x-mu)^dag psi(x-mu) - 2 psi(x)].
+ * Collecting the terms per neighbour gives the blocks
+ *   D(x, x+mu) = (+gamma_mu/2 - 1/2) U_mu(x),   D(x, x-mu) = (-gamma_mu/2 - 1/2) U_mu(x-mu)^dag,
+ *   D(x, x) = 4 + m0,
+ * with a factor -1 on a hop across the t boundary when tbc = 1.  The operator is applied from
+ * these blocks; the adjoint by D^dag(x, y) = D(y, x)^dag, without the gamma5 trick.
+ */
+
+/* block D(x, x + s mu) (s = +1 or -1): spin matrix S and colour matrix M; returns the neighbour */
+static long wilson_block(const int *L, int tbc, const cplx *U, long x, int mu, int s, cplx S[4][4], cplx M[9]) {
+    const long V = vol(L);
+    init_gammas();
+    int c[4];
+    coords(L, x, c);
+    double sign = 1.0;
+    if (s > 0) {
+        memcpy(M, U + ((size_t)mu * V + x) * 9, sizeof(cplx) * 9);
+        if (tbc && mu == 3 && c[3] == L[3] - 1) sign = -1.0;
+        c[mu] += 1;
+    } else {
+        if (tbc && mu == 3 && c[3] == 0) sign = -1.0;
+        c[mu] -= 1;
+        const cplx *u = U + ((size_t)mu * V + site_of(L, c)) * 9;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[3 * a + b] = conj(u[3 * b + a]);
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) S[a][b] = sign * (0.5 * s * GAM[mu][a][b] - (a == b ? 0.5 : 0.0));
+    return site_of(L, c);
+}
+
+static void wilson_site(const int *L, int tbc, const cplx *U, double m0, const cplx *src, long x, int adj,
+                        cplx *dst) {
+    cplx acc[4][3];
+    for (int s = 0; s < 4; ++s)
+        for (int a = 0; a < 3; ++a) acc[s][a] = (4.0 + m0) * src[(size_t)x * 12 + 3 * s + a];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int sg = -1; sg <= 1; sg += 2) {
+            cplx S[4][4], M[9];
+            long y;
+            if (!adj) {
+                y = wilson_block(L, tbc, U, x, mu, sg, S, M);
+            } else {
+                /* D^dag(x, y) = D(y, x)^dag with y = x + sg mu, i.e. the block of y towards -sg */
+                int c[4];
+                coords(L, x, c);
+                c[mu] += sg;
+                y = site_of(L, c);
+                cplx S2[4][4], M2[9];
+                wilson_block(L, tbc, U, y, mu, -sg, S2, M2);
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) S[a][b] = conj(S2[b][a]);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) M[3 * a + b] = conj(M2[3 * b + a]);
+            }
+            const cplx *p = src + (size_t)y * 12;
+            for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a) {
+                    cplx v = 0;
+                    for (int t = 0; t < 4; ++t)
+                        for (int b = 0; b < 3; ++b) v += S[s][t] * M[3 * a + b] * p[3 * t + b];
+                    acc[s][a] += v;
+                }
+        }
+    for (int s = 0; s < 4; ++s)
+        for (int a = 0; a < 3; ++a) dst[(size_t)x * 12 + 3 * s + a] = acc[s][a];
+}
+
+void orc_wilson(const int *L, int tbc, const cplx *U, double m0, const cplx *in, cplx *out, int nrhs) {
+    const long V = vol(L);
+    init_gammas();
+    for (int r = 0; r < nrhs; ++r) {
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < V; ++x) wilson_site(L, tbc, U, m0, in + (size_t)r * V * 12, x, 0, out + (size_t)r * V * 12);
+    }
+}
+
+void orc_wilson_adj(const int *L, int tbc, const cplx *U, double m0, const cplx *in, cplx *out, int nrhs) {
+    const long V = vol(L);
+    init_gammas();
+    for (int r = 0; r < nrhs; ++r) {
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < V; ++x) wilson_site(L, tbc, U, m0, in + (size_t)r * V * 12, x, 1, out + (size_t)r * V * 12);
+    }
+}
+
+void orc_wilson_dense(const int *L, int tbc, const cplx *U, double m0, cplx *M) {
+    const long V = vol(L);
+    const long n = 12 * V;
+    memset(M, 0, sizeof(cplx) * (size_t)n * n);
+    for (long x = 0; x < V; ++x) {
+        for (int i = 0; i < 12; ++i) M[(size_t)(12 * x + i) * n + 12 * x + i] += 4.0 + m0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                cplx S[4][4], C[9];
+                const long y = wilson_block(L, tbc, U, x, mu, sg, S, C);
+                for (int s = 0; s < 4; ++s)
+                    for (int a = 0; a < 3; ++a)
+                        for (int t = 0; t < 4; ++t)
+                            for (int b = 0; b < 3; ++b)
+                                M[(size_t)(12 * x + 3 * s + a) * n + 12 * y + 3 * t + b] += S[s][t] * C[3 * a + b];
+            }
+    }
+}
+
 /* ------------------------------------------------------------------ solvers */
 
 static cplx dotc(const cplx *a, const cplx *b, long n) {
@@ -473,11 +588,32 @@ static cplx dotc(const cplx *a, const cplx *b, long n) {
 
 static double norm2(const cplx *a, long n) { return creal(dotc(a, a, n)); }
 
+/* The kernel operator of the solvers: kern 0 = Brillouin (W = the 81 links per site), kern 1 =
+ * Wilson (W = the gauge field U, tbc applied on the fly). */
+typedef struct {
+    int kern, tbc;
+    const cplx *W;
+} kernel_t;
+
+static void kernel_apply(const int *L, const kernel_t *K, double m0, const cplx *x, cplx *y, int adj) {
+    if (K->kern == 1) {
+        if (adj)
+            orc_wilson_adj(L, K->tbc, K->W, m0, x, y, 1);
+        else
+            orc_wilson(L, K->tbc, K->W, m0, x, y, 1);
+    } else {
+        if (adj)
+            orc_dirac_adj(L, K->W, m0, x, y, 1);
+        else
+            orc_dirac(L, K->W, m0, x, y, 1);
+    }
+}
+
 /* y = (D^dag D + sigma) x */
-static void normal_op(const int *L, const cplx *W, double m0, double sigma, const cplx *x, cplx *y, cplx *tmp) {
+static void normal_op(const int *L, const kernel_t *K, double m0, double sigma, const cplx *x, cplx *y, cplx *tmp) {
     const long n = 12 * vol(L);
-    orc_dirac(L, W, m0, x, tmp, 1);
-    orc_dirac_adj(L, W, m0, tmp, y, 1);
+    kernel_apply(L, K, m0, x, tmp, 0);
+    kernel_apply(L, K, m0, tmp, y, 1);
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) y[i] += sigma * x[i];
 }
@@ -486,9 +622,11 @@ static void normal_op(const int *L, const cplx *W, double m0, double sigma, cons
  * recursive residual is below tol*|b|, then recomputes the true residual and
  * restarts from the current x if that is still above tol*|b|.
  * Returns the iteration count; *true_rel receives |b - (A+sigma)x|/|b|. */
-int orc_cg(const int *L, const cplx *W, double m0, double sigma, const cplx *b, cplx *x, double tol,
-           int maxit, double *true_rel) {
+int orc_cg(const int *L, int kern, int tbc, const cplx *W, double m0, double sigma, const cplx *b, cplx *x,
+           double tol, int maxit, double *true_rel) {
     const long n = 12 * vol(L);
+    const kernel_t Kv = {kern, tbc, W};
+    const kernel_t *K = &Kv;
     cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
     cplx *Ap = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
     const double bn = sqrt(norm2(b, n));
@@ -502,14 +640,14 @@ int orc_cg(const int *L, const cplx *W, double m0, double sigma, const cplx *b, 
     }
     while (it < maxit) {
         /* (re)start: r = b - A x */
-        normal_op(L, W, m0, sigma, x, Ap, tmp);
+        normal_op(L, K, m0, sigma, x, Ap, tmp);
         for (long i = 0; i < n; ++i) r[i] = b[i] - Ap[i];
         double rr = norm2(r, n);
         rel = sqrt(rr) / bn;
         if (rel <= tol) break;
         memcpy(p, r, sizeof(cplx) * n);
         while (it < maxit) {
-            normal_op(L, W, m0, sigma, p, Ap, tmp);
+            normal_op(L, K, m0, sigma, p, Ap, tmp);
             double pAp = creal(dotc(p, Ap, n));
             double alpha = rr / pAp;
             for (long i = 0; i < n; ++i) {
@@ -524,7 +662,7 @@ int orc_cg(const int *L, const cplx *W, double m0, double sigma, const cplx *b, 
             for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
         }
     }
-    normal_op(L, W, m0, sigma, x, Ap, tmp);
+    normal_op(L, K, m0, sigma, x, Ap, tmp);
     double rr = 0;
     for (long i = 0; i < n; ++i) {
         cplx e = b[i] - Ap[i];
@@ -537,14 +675,15 @@ int orc_cg(const int *L, const cplx *W, double m0, double sigma, const cplx *b, 
 
 /* y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, each shift separately.
  * iters[i], rel[i] receive the per-shift CG iteration count and true residual. */
-int orc_rational(const int *L, const cplx *W, double m0, int nshift, double c0, const double *omega,
-                 const double *sigma, const cplx *b, cplx *y, double tol, int maxit, int *iters, double *rel) {
+int orc_rational(const int *L, int kern, int tbc, const cplx *W, double m0, int nshift, double c0,
+                 const double *omega, const double *sigma, const cplx *b, cplx *y, double tol, int maxit, int *iters,
+                 double *rel) {
     const long n = 12 * vol(L);
     cplx *xs = malloc(sizeof(cplx) * n);
     for (long i = 0; i < n; ++i) y[i] = c0 * b[i];
     int worst = 0;
     for (int s = 0; s < nshift; ++s) {
-        iters[s] = orc_cg(L, W, m0, sigma[s], b, xs, tol, maxit, &rel[s]);
+        iters[s] = orc_cg(L, kern, tbc, W, m0, sigma[s], b, xs, tol, maxit, &rel[s]);
         if (rel[s] > tol) worst = 1;
         for (long i = 0; i < n; ++i) y[i] += omega[s] * xs[i];
     }
