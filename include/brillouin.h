@@ -101,12 +101,33 @@ int bri_apply(const bri_geom *geom, const void *W, int prec, double m0, const vo
 int bri_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
                   void *stream);
 
+/* Kernel operator X of the overlap (ov_params.kernel). */
+enum bri_kernel {
+    BRI_KERNEL_BRILLOUIN = 0, /* D_bri, eq. (def_bril), c_SW = 0: the 81-point stencil         */
+    BRI_KERNEL_WILSON = 1     /* D_wil, eq. (def_wils), c_SW = 0: the 9-point stencil, reading
+                                 the four one-hop slabs of the same link array               */
+};
+
 /* Kenney-Laub family member used for sign(H) (ov_params.kind). */
 enum bri_kl_kind {
     BRI_KL_DIAG = 0, /* diagonal f_{n,n} = g_{2n+1}, eq. (KLnn_parfrac): c0 + n poles           */
     BRI_KL_UPPER = 1 /* first upper diagonal f_{n-1,n} = g_{2n} (Sec. 3.3, Tab. 6): n poles, no
                         constant term                                                         */
 };
+
+/*
+ * wil_apply     -- out = D_wil(m0) in,  eq. (def_wils) with c_SW = 0:
+ *   (D psi)(x) = (4 + m0) psi(x) - (1/2) sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+ * wil_apply_dag -- out = D_wil(m0)^dag in = gamma5 D_wil(m0) gamma5 in.
+ * W is the link array of bri_build_links (its four one-hop slabs are U_mu(x - mu)^dag with the
+ * boundary signs folded in; the other slabs are not read), so both kernels share one set-up.
+ * Arguments, layouts and errors as bri_apply.
+ */
+int wil_apply(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
+              void *stream);
+int wil_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
+                  void *stream);
 
 /* Parameters of the overlap applies. */
 typedef struct {
@@ -121,6 +142,8 @@ typedef struct {
     int relax;      /* 1: shift i stops at tol * omega_max / omega_i (App. B: the
                        weights grow with the shift, so small shifts may stop at a
                        larger residual); 0: every shift at tol                  */
+    int kernel;     /* bri_kernel: X = D_kernel(-rho); BRI_KERNEL_BRILLOUIN unless
+                       stated                                                  */
 } ov_params;
 
 /* Statistics of one overlap apply (the last right-hand side for nrhs > 1). */

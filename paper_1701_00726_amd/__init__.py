@@ -30,6 +30,7 @@ LIB_PATH = os.path.join(_HERE, "libbrillouin.so")
 
 F64, F32, F32_BF16W = 0, 1, 2
 KL_DIAG, KL_UPPER = 0, 1
+KERNEL_BRILLOUIN, KERNEL_WILSON = 0, 1
 OK, EINVAL, ENOCONV, ENAN, EHIP = 0, -1, -2, -3, -4
 MAX_SHIFTS = 32
 STATUS_NAMES = {OK: "BRI_OK", EINVAL: "BRI_EINVAL", ENOCONV: "BRI_ENOCONV", ENAN: "BRI_ENAN", EHIP: "BRI_EHIP"}
@@ -55,6 +56,7 @@ class _OvParams(ctypes.Structure):
         ("max_refine", ctypes.c_int),
         ("kind", ctypes.c_int),
         ("relax", ctypes.c_int),
+        ("kernel", ctypes.c_int),
     ]
 
 
@@ -175,6 +177,8 @@ def load():
             lib.bri_build_links.argtypes = [G, P, P, I, P]
             lib.bri_apply.argtypes = [G, P, I, D, P, P, I, P]
             lib.bri_apply_dag.argtypes = [G, P, I, D, P, P, I, P]
+            lib.wil_apply.argtypes = [G, P, I, D, P, P, I, P]
+            lib.wil_apply_dag.argtypes = [G, P, I, D, P, P, I, P]
             ovargs = [G, P, P, ctypes.POINTER(_OvParams), P, P, I, P, ctypes.POINTER(ctypes.c_size_t),
                       ctypes.POINTER(_OvStats), P]
             lib.ov_sign_apply.argtypes = ovargs
@@ -203,6 +207,8 @@ EXPORTS = (
     "bri_build_links",
     "bri_apply",
     "bri_apply_dag",
+    "wil_apply",
+    "wil_apply_dag",
     "ov_sign_apply",
     "ov_apply",
     "bri_kl_coeffs",
@@ -343,16 +349,27 @@ def apply_dag(L, W, prec, m0, psi, out=None, stream=None):
     return _apply("bri_apply_dag", L, W, prec, m0, psi, out, stream)
 
 
+def wilson_apply(L, W, prec, m0, psi, out=None, stream=None):
+    """out = D_wil(m0) psi, reading the one-hop slabs of the link array W."""
+    return _apply("wil_apply", L, W, prec, m0, psi, out, stream)
+
+
+def wilson_apply_dag(L, W, prec, m0, psi, out=None, stream=None):
+    """out = D_wil(m0)^dag psi."""
+    return _apply("wil_apply_dag", L, W, prec, m0, psi, out, stream)
+
+
 class OverlapOp:
     """Holds the workspace of ov_apply / ov_sign_apply for one lattice and parameter set."""
 
     def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0,
-                 max_refine=None, nrhs=1, kind=KL_DIAG, relax=False):
+                 max_refine=None, nrhs=1, kind=KL_DIAG, relax=False, kernel=KERNEL_BRILLOUIN):
         """Workspace for up to `nrhs` right-hand sides per call.  inner = F32 or
         F32_BF16W runs the multi-shift with the low-precision links `Wlo` and refines
         every shift in FP64 (at most max_refine passes, default 10).  kind = KL_UPPER
         uses the first upper diagonal g_{2n} instead of g_{2n+1}; relax stops shift i
-        at tol * omega_max / omega_i."""
+        at tol * omega_max / omega_i; kernel = KERNEL_WILSON builds the overlap on the
+        Wilson operator (the one-hop slabs of W64) instead of the Brillouin one."""
         self.L = tuple(int(v) for v in L)
         self.g = _geom(self.L, tbc)
         self.W64 = W64
@@ -362,7 +379,7 @@ class OverlapOp:
         if max_refine is None:
             max_refine = 0 if inner == F64 else 10
         self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine),
-                                int(kind), 1 if relax else 0)
+                                int(kind), 1 if relax else 0, int(kernel))
         self.nrhs = int(nrhs)
         nbytes = ctypes.c_size_t(0)
         _check(

@@ -27,6 +27,13 @@ __host__ __device__ inline int disp_comp(int j, int mu) {
     return (j / p) % 3 - 1;
 }
 
+// Kernel operator of the stencils: the 81-point Brillouin operator (all 40 stored slabs) or the
+// 9-point Wilson operator (the four one-hop slabs of the same link array).
+enum KernelKind { KERN_BRI = BRI_KERNEL_BRILLOUIN, KERN_WIL = BRI_KERNEL_WILSON };
+
+// diagonal of the operator without the bare mass: 15/8 (Brillouin), 4 (Wilson)
+inline double kernel_diag(int kind) { return kind == KERN_WIL ? 4.0 : 15.0 / 8.0; }
+
 // ---------------------------------------------------------- stencil weights
 //
 // S_d = a_k + c_k sum_mu d_mu gamma_mu for a k-hop displacement d (k >= 1),

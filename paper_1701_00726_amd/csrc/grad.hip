@@ -486,6 +486,7 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     if (!prm || !work_bytes) return BRI_EINVAL;
     const int n = prm->kl_n;
     if (!params_ok(prm) || g.V % 64) return BRI_EINVAL;
+    if (prm->kernel != BRI_KERNEL_BRILLOUIN) return BRI_EINVAL;  // the force pulls back through W's paths
     GradPlan pl;
     rc = plan_grad(g, prm, pl);
     if (rc != BRI_OK) return rc;

@@ -142,7 +142,8 @@ struct Cascade {
     int apply_d(Level &L, const double2 *v, double2 *dst) {
         ++L.applies;
         if (L.kl_n == 0) {
-            const int r = ::bri_apply(geom, W64, BRI_F64, -rho, v, dst, 1, s);
+            const int r = L.prm.kernel == BRI_KERNEL_WILSON ? ::wil_apply(geom, W64, BRI_F64, -rho, v, dst, 1, s)
+                                                            : ::bri_apply(geom, W64, BRI_F64, -rho, v, dst, 1, s);
             if (r != BRI_OK) return r;
             lincomb(dst, rho, dst);
             return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;

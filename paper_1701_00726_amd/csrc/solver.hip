@@ -403,6 +403,7 @@ bool params_ok(const ov_params *prm) {
     if (prm->inner != BRI_F64 && prm->inner != BRI_F32 && prm->inner != BRI_F32_BF16W) return false;
     if (prm->max_refine < 0 || prm->max_refine > 100) return false;
     if (prm->kind != BRI_KL_DIAG && prm->kind != BRI_KL_UPPER) return false;
+    if (prm->kernel != BRI_KERNEL_BRILLOUIN && prm->kernel != BRI_KERNEL_WILSON) return false;
     return prm->relax == 0 || prm->relax == 1;
 }
 
@@ -426,6 +427,7 @@ struct MsSolve {
     int prec = BRI_F64;  // vector / stencil precision
     const void *W = nullptr;
     double m0 = 0.0;
+    int kind = KERN_BRI;  // kernel operator X = D_kind(m0)
     int ncol = 1, nshift = 1;
     bool store_x = false;  // keep x^sigma (else accumulate y)
     double c0 = 0.0;
@@ -571,14 +573,15 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
                        s.tol);
     BRI_HIP_CHECK(hipGetLastError());
 
-    const StencilConfig cfg = default_config(s.g, s.prec, s.ncol);
+    const StencilConfig cfg = default_config(s.g, s.prec, s.ncol, s.kind);
     StencilArgs a1{};
     a1.g = s.g;
     a1.W = s.W;
     a1.ncol = s.ncol;
     a1.in = s.p;
     a1.out = s.t;
-    a1.diag = 15.0 / 8.0 + s.m0;
+    a1.kind = s.kind;
+    a1.diag = kernel_diag(s.kind) + s.m0;
     a1.partial = s.partial;
     a1.st = s.st;
     StencilArgs a2 = a1;
@@ -612,7 +615,8 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
         uint64_t m0bits;
         std::memcpy(&m0bits, &s.m0, sizeof(m0bits));
         key = {(uint64_t)dev, (uint64_t)s.g.L[0], (uint64_t)s.g.L[1], (uint64_t)s.g.L[2], (uint64_t)s.g.L[3],
-               (uint64_t)s.g.tbc, (uint64_t)s.prec, (uint64_t)s.ncol, m0bits, (uint64_t)(uintptr_t)s.W,
+               (uint64_t)s.g.tbc, (uint64_t)s.prec, (uint64_t)s.kind, (uint64_t)s.ncol, m0bits,
+               (uint64_t)(uintptr_t)s.W,
                (uint64_t)(uintptr_t)s.st, (uint64_t)(uintptr_t)s.partial, (uint64_t)(uintptr_t)s.alldone,
                (uint64_t)(uintptr_t)s.r, (uint64_t)(uintptr_t)s.p, (uint64_t)(uintptr_t)s.t,
                (uint64_t)(uintptr_t)s.y, (uint64_t)(uintptr_t)s.x, (uint64_t)(uintptr_t)s.ps,
@@ -694,6 +698,7 @@ static void plan_overlap(OvPlan &pl, const Geom &g, const ov_params *prm, int nr
     m.prec = pl.mixed ? prm->inner : BRI_F64;
     m.W = pl.mixed ? Wlo : W64;
     m.m0 = -prm->rho;
+    m.kind = prm->kernel;
     m.ncol = nrhs;
     m.nshift = pl.n;
     m.store_x = pl.mixed;
@@ -724,6 +729,7 @@ static void plan_overlap(OvPlan &pl, const Geom &g, const ov_params *prm, int nr
         e.prec = prm->inner;
         e.W = Wlo;
         e.m0 = -prm->rho;
+        e.kind = prm->kernel;
         e.ncol = pl.chunk;
         e.nshift = 1;
         e.store_x = true;
@@ -769,8 +775,9 @@ static int refine(OvPlan &pl, const Geom &g, const ov_params *prm, const void *W
             a.ncol = nc;
             a.in = xc;
             a.out = pl.t64;
-            a.diag = 15.0 / 8.0 - prm->rho;
-            const StencilConfig cfg = default_config(g, BRI_F64, nc);
+            a.kind = prm->kernel;
+            a.diag = kernel_diag(prm->kernel) - prm->rho;
+            const StencilConfig cfg = default_config(g, BRI_F64, nc, prm->kernel);
             int rc = stencil_launch(a, BRI_F64, false, EPI_PLAIN, cfg, s);
             if (rc != BRI_OK) return rc;
             StencilArgs a2 = a;
@@ -883,10 +890,12 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
         a3.ncol = nrhs;
         a3.in = yfinal;
         a3.out = out;
-        a3.diag = 15.0 / 8.0 - prm->rho;
+        a3.kind = prm->kernel;
+        a3.diag = kernel_diag(prm->kernel) - prm->rho;
         a3.b = in;
         a3.rho = prm->rho;
-        rc = stencil_launch(a3, BRI_F64, false, overlap ? EPI_OV : EPI_SIGN, default_config(g, BRI_F64, nrhs), s);
+        rc = stencil_launch(a3, BRI_F64, false, overlap ? EPI_OV : EPI_SIGN,
+                            default_config(g, BRI_F64, nrhs, prm->kernel), s);
         if (rc != BRI_OK && result == BRI_OK) result = rc;
     }
     if (hipStreamSynchronize(s) != hipSuccess) result = BRI_EHIP;
@@ -936,6 +945,7 @@ int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_pa
         m.prec = BRI_F64;
         m.W = W64;
         m.m0 = -prm->rho;
+        m.kind = prm->kernel;
         m.ncol = ncol;
         m.nshift = n;
         m.store_x = true;

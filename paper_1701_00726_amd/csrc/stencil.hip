@@ -1,4 +1,5 @@
-// Brillouin stencil y = D_bri(m0) x on gfx950 (App. C.1).
+// Brillouin stencil y = D_bri(m0) x on gfx950 (App. C.1), and the Wilson stencil y = D_wil(m0) x
+// (eq. (def_wils)) as the same kernels restricted to the four one-hop slabs with Wilson weights.
 //
 //   (D psi)(x) = (15/8 + m0) psi(x) + sum_{d != 0} S_d W_d(x) psi(x + d)
 //   S_d = a_k + c_k sum_mu d_mu gamma_mu      (k = number of hops of d)
@@ -87,7 +88,7 @@ template <int MODE> __device__ __forceinline__ bool col_done(const StencilArgs &
 
 // ------------------------------------------------------- one right-hand side
 
-template <class LS, int NSPLIT, bool DAG, int MODE>
+template <class LS, int NSPLIT, bool DAG, int MODE, int KIND>
 __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
     using R = typename LS::R;
     using C = typename Cx<R>::T;
@@ -121,8 +122,9 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
             }
     }
 
-    for (int j = q; j < 40; j += NSPLIT) {
-        const DirW<R, DAG> dw(j);
+    for (int k = q; k < Slabs<KIND>::n; k += NSPLIT) {
+        const int j = Slabs<KIND>::at(k);
+        const DirW<R, DAG, KIND> dw(j);
         const typename LS::store_t *__restrict__ Wj = W + (size_t)j * 9 * V;
         C chi[4][3];
         const unsigned y = neighbour(j, +1, om, o0, op);
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
 
 // ------------------------------------------------------ many right-hand sides
 
-template <class LS, int R, bool DAG, int MODE>
+template <class LS, int R, bool DAG, int MODE, int KIND>
 __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilArgs a) {
     using RT = typename LS::R;
     using C = typename Cx<RT>::T;
@@ -231,8 +233,9 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilAr
                 acc[r][s][b] = v;
             }
 
-    for (int j = q; j < 40; j += NSPLIT) {
-        const DirW<RT, DAG> dw(j);
+    for (int k = q; k < Slabs<KIND>::n; k += NSPLIT) {
+        const int j = Slabs<KIND>::at(k);
+        const DirW<RT, DAG, KIND> dw(j);
         const typename LS::store_t *__restrict__ Wj = W + (size_t)j * 9 * V;
         C wl[3][3];
         C chi[4][3];
@@ -309,53 +312,60 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilAr
 
 // ------------------------------------------------------------------ launch
 
-template <class LS, int NSPLIT, bool DAG>
+template <class LS, int NSPLIT, bool DAG, int KIND>
 static hipError_t launch_1rhs(const StencilArgs &a, int mode, hipStream_t st) {
     const dim3 grid((unsigned)(a.g.V / 64), (unsigned)a.ncol), block(64 * NSPLIT);
     switch (mode) {
-    case EPI_PLAIN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
-    case EPI_NORMS: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
-    case EPI_CG_R: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_CG_R>), grid, block, 0, st, a); break;
-    case EPI_OV: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_OV>), grid, block, 0, st, a); break;
-    case EPI_SIGN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_SIGN>), grid, block, 0, st, a); break;
-    case EPI_RESID: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_RESID>), grid, block, 0, st, a); break;
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_PLAIN, KIND>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_NORMS, KIND>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_CG_R, KIND>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_OV, KIND>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_SIGN, KIND>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_RESID, KIND>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <class LS, int R, bool DAG>
+template <class LS, int R, bool DAG, int KIND>
 static hipError_t launch_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
     const int groups = (a.ncol + R - 1) / R;
     const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(64 * MRHS_SPLIT);
     switch (mode) {
-    case EPI_PLAIN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
-    case EPI_NORMS: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
-    case EPI_CG_R: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_CG_R>), grid, block, 0, st, a); break;
-    case EPI_OV: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_OV>), grid, block, 0, st, a); break;
-    case EPI_SIGN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_SIGN>), grid, block, 0, st, a); break;
-    case EPI_RESID: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_RESID>), grid, block, 0, st, a); break;
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_PLAIN, KIND>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_NORMS, KIND>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_CG_R, KIND>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_OV, KIND>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_SIGN, KIND>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_RESID, KIND>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <class LS, bool DAG>
-static hipError_t launch_prec(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
+template <class LS, bool DAG, int KIND>
+static hipError_t launch_cfg(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
     switch (cfg.rpt) {
     case 0:
         switch (cfg.nsplit) {
-        case 1: return launch_1rhs<LS, 1, DAG>(a, mode, st);
-        case 2: return launch_1rhs<LS, 2, DAG>(a, mode, st);
-        case 4: return launch_1rhs<LS, 4, DAG>(a, mode, st);
+        case 1: return launch_1rhs<LS, 1, DAG, KIND>(a, mode, st);
+        case 2: return launch_1rhs<LS, 2, DAG, KIND>(a, mode, st);
+        case 4: return launch_1rhs<LS, 4, DAG, KIND>(a, mode, st);
         default: return hipErrorInvalidValue;
         }
-    case 1: return launch_mrhs<LS, 1, DAG>(a, mode, st);
-    case 2: return launch_mrhs<LS, 2, DAG>(a, mode, st);
-    case 3: return launch_mrhs<LS, 3, DAG>(a, mode, st);
-    case 4: return launch_mrhs<LS, 4, DAG>(a, mode, st);
+    case 1: return launch_mrhs<LS, 1, DAG, KIND>(a, mode, st);
+    case 2: return launch_mrhs<LS, 2, DAG, KIND>(a, mode, st);
+    case 3: return launch_mrhs<LS, 3, DAG, KIND>(a, mode, st);
+    case 4: return launch_mrhs<LS, 4, DAG, KIND>(a, mode, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <class LS, bool DAG>
+static hipError_t launch_prec(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
+    if (a.kind == KERN_WIL) return launch_cfg<LS, DAG, KERN_WIL>(a, mode, cfg, st);
+    if (a.kind == KERN_BRI) return launch_cfg<LS, DAG, KERN_BRI>(a, mode, cfg, st);
+    return hipErrorInvalidValue;
 }
 
 // A 64-site tile that divides the lattice.  Column traversal: tile
@@ -439,9 +449,10 @@ static void default_traversal(const Geom &g, StencilConfig &c) {
     }
 }
 
-StencilConfig default_config(const Geom &g, int prec, int ncol) {
+StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
     StencilConfig c;
-    if (tuned_config(g, prec, ncol, &c)) return c;
+    // the tuned table holds Brillouin launches; the Wilson stencil keeps the defaults
+    if (kind == KERN_BRI && tuned_config(g, prec, ncol, &c)) return c;
     default_traversal(g, c);
     c.xcd_remap = 1;
     if (ncol >= 2) {
@@ -463,7 +474,7 @@ StencilConfig default_config(const Geom &g, int prec, int ncol) {
 extern "C" {
 
 static int apply_common(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
-                        void *stream, bool dag) {
+                        void *stream, bool dag, int kind) {
     using namespace bri;
     StencilArgs a{};
     int rc = geom_check(geom, &a.g);
@@ -474,18 +485,29 @@ static int apply_common(const bri_geom *geom, const void *W, int prec, double m0
     a.in = in;
     a.out = out;
     a.ncol = nrhs;
-    a.diag = 15.0 / 8.0 + m0;
-    return stencil_launch(a, prec, dag, EPI_PLAIN, default_config(a.g, prec, nrhs), (hipStream_t)stream);
+    a.kind = kind;
+    a.diag = kernel_diag(kind) + m0;
+    return stencil_launch(a, prec, dag, EPI_PLAIN, default_config(a.g, prec, nrhs, kind), (hipStream_t)stream);
 }
 
 int bri_apply(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
               void *stream) {
-    return apply_common(geom, W, prec, m0, in, out, nrhs, stream, false);
+    return apply_common(geom, W, prec, m0, in, out, nrhs, stream, false, bri::KERN_BRI);
 }
 
 int bri_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
                   void *stream) {
-    return apply_common(geom, W, prec, m0, in, out, nrhs, stream, true);
+    return apply_common(geom, W, prec, m0, in, out, nrhs, stream, true, bri::KERN_BRI);
+}
+
+int wil_apply(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
+              void *stream) {
+    return apply_common(geom, W, prec, m0, in, out, nrhs, stream, false, bri::KERN_WIL);
+}
+
+int wil_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
+                  void *stream) {
+    return apply_common(geom, W, prec, m0, in, out, nrhs, stream, true, bri::KERN_WIL);
 }
 
 }  // extern "C"

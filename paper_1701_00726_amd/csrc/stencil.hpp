@@ -8,6 +8,7 @@ namespace bri {
 
 constexpr int MAXS = BRI_MAX_SHIFTS;
 
+
 // FP64 scalars of one column (one right-hand side) of a batched multi-shift CG.
 struct ColState {
     double rr, bnorm2, tol2;
@@ -45,7 +46,8 @@ struct StencilArgs {
     const void *W;
     const void *in;
     void *out;
-    double diag;  // 15/8 + m0
+    double diag;  // kernel_diag(kind) + m0
+    int kind;     // KernelKind
     // epilogue operands
     double *partial;        // EPI_NORMS / EPI_CG_R / EPI_RESID: [ncol][nblk][2]
     const void *p;          // EPI_CG_R
@@ -72,7 +74,7 @@ bool tuned_config(const Geom &g, int prec, int ncol, StencilConfig *out);
 
 int geom_check(const bri_geom *geom, Geom *g);
 int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]);
-StencilConfig default_config(const Geom &g, int prec, int ncol);
+StencilConfig default_config(const Geom &g, int prec, int ncol, int kind = KERN_BRI);
 int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilConfig &cfg, hipStream_t st);
 
 inline int stencil_blocks(const Geom &g) { return g.V / 64; }

@@ -196,6 +196,16 @@ __device__ __forceinline__ int xcd_order(int blk, int nblk, int remap) {
     return (remap && (nblk & 7) == 0) ? (blk & 7) * (nblk >> 3) + (blk >> 3) : blk;
 }
 
+// stored slabs a kernel walks: all 40 (Brillouin), or the one-hop slabs j = 40 - 3^(3-k) (Wilson:
+// displacements -t, -z, -y, -x)
+template <int KIND> struct Slabs {
+    static constexpr int n = KIND == KERN_WIL ? 4 : 40;
+    __device__ __forceinline__ static int at(int k) {
+        if constexpr (KIND == KERN_WIL) return 40 - (k == 0 ? 27 : k == 1 ? 9 : k == 2 ? 3 : 1);
+        return k;
+    }
+};
+
 // neighbour x + s*d of a stored displacement index j (s = +1 or -1)
 __device__ __forceinline__ unsigned neighbour(int j, int s, const unsigned om[4], const unsigned o0[4],
                                               const unsigned op[4]) {
@@ -204,14 +214,18 @@ __device__ __forceinline__ unsigned neighbour(int j, int s, const unsigned om[4]
            sel3(d3, om[3], o0[3], op[3]);
 }
 
-// weights of stored displacement j: a_k and c_mu = c_k d_mu (negated for the adjoint)
-template <typename R, bool DAG> struct DirW {
+// weights of stored displacement j: a_k and c_mu = c_k d_mu (negated for the adjoint).
+// Brillouin: the Laplacian and isotropic-derivative weights of a k-hop point.  Wilson (one-hop
+// slabs only): -1/2 from -(1/2) lap^std and 1/2 d_mu from gamma_mu nabla^std_mu, i.e.
+// S_{+-mu} = -(1/2)(1 -+ gamma_mu).
+template <typename R, bool DAG, int KIND = KERN_BRI> struct DirW {
     R a, c0, c1, c2, c3;
     __device__ __forceinline__ explicit DirW(int j) {
         const int d0 = j % 3 - 1, d1 = (j / 3) % 3 - 1, d2 = (j / 9) % 3 - 1, d3 = j / 27 - 1;
         const int k = (d0 != 0) + (d1 != 0) + (d2 != 0) + (d3 != 0);
-        a = (R)lap_weight(k);
-        const R ck = (R)(DAG ? -iso_weight(k) : iso_weight(k));
+        a = (R)(KIND == KERN_WIL ? -0.5 : lap_weight(k));
+        const double cw = KIND == KERN_WIL ? 0.5 : iso_weight(k);
+        const R ck = (R)(DAG ? -cw : cw);
         c0 = ck * (R)d0;
         c1 = ck * (R)d1;
         c2 = ck * (R)d2;

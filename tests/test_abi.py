@@ -242,3 +242,20 @@ def test_kind_and_relax_validated():
     om = (ctypes.c_double * 1)()
     assert lib.bri_kl_upper_coeffs(0, om, om) == bri.EINVAL
     assert lib.bri_kl_upper_coeffs(bri.MAX_SHIFTS + 1, om, om) == bri.EINVAL
+
+
+def test_kernel_selector_validated():
+    lib = bri.load()
+    g = bri._geom((8, 8, 8, 8))
+    nb = ctypes.c_size_t(0)
+    for kernel, want_apply, want_grad in ((0, bri.OK, bri.OK), (1, bri.OK, bri.EINVAL), (2, bri.EINVAL, bri.EINVAL)):
+        prm = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0, 0, 0, kernel)
+        assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb),
+                            None, None) == want_apply
+        # the gradient pulls back through the Brillouin paths only
+        assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None,
+                                 None, ctypes.byref(nb), None, None) == want_grad
+    # the Wilson applies validate like bri_apply before launching anything
+    assert lib.wil_apply(ctypes.byref(g), None, 0, 0.0, None, None, 1, None) == bri.EINVAL
+    assert lib.wil_apply_dag(ctypes.byref(g), ctypes.c_void_p(256), 7, 0.0, ctypes.c_void_p(256),
+                             ctypes.c_void_p(512), 1, None) == bri.EINVAL
