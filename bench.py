@@ -467,6 +467,20 @@ def main():
         ms_f = timed(lambda: bri.link_grad(L, U, W, pairs), 3)
         extra["grad_fp64_1src"] = {"ms_per_call": ms_g, "ratio_to_step": ms_g / ms_step,
                                    "link_force_ms_%d_pairs" % (2 * KL_N + 1): ms_f}
+        # the Wilson kernel (eq. (def_wils)) on the same links: its 9-point stencil (four link
+        # matrices, one spinor in and out per site: 960 B/site in FP64) and its overlap apply
+        for _ in range(5):
+            bri.wilson_apply(L, W, bri.F64, -RHO, t_in, out=t_out)
+        ms_w = timed(lambda: bri.wilson_apply(L, W, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps)
+        opw = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=20000, kernel=bri.KERNEL_WILSON)
+        ow = torch.empty_like(b)
+        _, stw = opw.apply(b, out=ow)
+        ms_ow = timed(lambda: opw.apply(b, out=ow), 3)
+        extra["wilson_kernel_fp64_1src"] = {
+            "stencil_us": ms_w * 1e3, "stencil_GBps_alg": 960 * V / (ms_w * 1e-3) / 1e9,
+            "overlap_applies_per_s": 1 / (ms_ow / 1e3), "overlap_ms_per_call": ms_ow, "cg_iterations": stw.iters,
+            "brillouin_cg_iterations": int(np.median(iters)), "brillouin_stencil_us": us_launch}
+        del opw, ow
         # relaxed per-shift stopping (tol * omega_max / omega_i) against the strict apply
         opr = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, relax=True)
         orl = torch.empty_like(b)
