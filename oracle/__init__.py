@@ -75,9 +75,11 @@ def _load():
             lib.orc_wilson.argtypes = [P, I, P, D, P, P, I]
             lib.orc_wilson_adj.argtypes = [P, I, P, D, P, P, I]
             lib.orc_wilson_dense.argtypes = [P, I, P, D, P]
-            lib.orc_cg.argtypes = [P, I, I, P, D, D, P, P, D, I, P]
+            lib.orc_clover.argtypes = [P, P, D, P]
+            lib.orc_clover_apply.argtypes = [P, P, P, P, I, I]
+            lib.orc_cg.argtypes = [P, I, I, P, P, D, D, P, P, D, I, P]
             lib.orc_cg.restype = I
-            lib.orc_rational.argtypes = [P, I, I, P, D, I, D, P, P, P, P, D, I, P, P]
+            lib.orc_rational.argtypes = [P, I, I, P, P, D, I, D, P, P, P, P, D, I, P, P]
             lib.orc_rational.restype = I
             lib.orc_num_threads.restype = I
             lib.orc_lambda.argtypes = [I, P]
@@ -145,23 +147,48 @@ def links(L, U: np.ndarray, tbc: int = 0) -> np.ndarray:
 
 
 class WilsonKernel:
-    """The Wilson operator of eq. (def_wils) (c_SW = 0) as the kernel: the gauge field U
-    (4, V, 3, 3) and the t boundary condition.  Wherever the functions below take the Brillouin
-    link array W, an instance of this class selects the Wilson operator instead."""
+    """The Wilson operator of eq. (def_wils) as the kernel: the gauge field U (4, V, 3, 3), the
+    t boundary condition and optionally a clover field (V, 12, 12) from `clover_field`.
+    Wherever the functions below take the Brillouin link array W, an instance of this class
+    selects the Wilson operator instead."""
 
-    def __init__(self, U: np.ndarray, tbc: int = 0):
+    def __init__(self, U: np.ndarray, tbc: int = 0, clover: np.ndarray | None = None):
         self.U = _c128(U)
         self.tbc = int(tbc)
+        self.clover = None if clover is None else _c128(clover)
+
+
+class BrillouinKernel:
+    """The Brillouin operator with a clover term: the link array W of `links` and a clover field
+    (V, 12, 12).  A bare W array is the Brillouin operator with c_SW = 0."""
+
+    def __init__(self, W: np.ndarray, clover: np.ndarray | None = None):
+        self.W = _c128(W)
+        self.clover = None if clover is None else _c128(clover)
 
 
 def _kernel_args(W):
-    """(kern, tbc, array) for the C solvers: 0 = Brillouin link array, 1 = Wilson gauge field."""
+    """(kern, tbc, array, clover) for the C solvers: 0 = Brillouin link array, 1 = Wilson gauge
+    field; clover None or (V, 12, 12)."""
     if isinstance(W, WilsonKernel):
-        return 1, W.tbc, W.U
-    return 0, 0, _c128(W)
+        return 1, W.tbc, W.U, W.clover
+    if isinstance(W, BrillouinKernel):
+        return 0, 0, W.W, W.clover
+    return 0, 0, _c128(W), None
 
 
-def _apply(fn, L, W, m0, psi, wfn=None):
+def clover_field(L, U: np.ndarray, csw: float) -> np.ndarray:
+    """-(c_SW/2) sum_{mu<nu} sigma_mu_nu F_mu_nu per site, (V, 12, 12), index 3*spin + colour,
+    with the clover-leaf F_mu_nu (see oracle.c)."""
+    V = volume(L)
+    U = _c128(U)
+    assert U.shape == (4, V, 3, 3)
+    out = np.zeros((V, 12, 12), dtype=np.complex128)
+    _load().orc_clover(_ptr(_geom(L)), _ptr(U), float(csw), _ptr(out))
+    return out
+
+
+def _apply(fn, L, W, m0, psi, wfn=None, adj=False):
     V = volume(L)
     psi = _c128(psi)
     squeeze = psi.ndim == 3
@@ -169,12 +196,15 @@ def _apply(fn, L, W, m0, psi, wfn=None):
         psi = psi[None]
     assert psi.shape[1:] == (V, 4, 3)
     out = np.zeros_like(psi)
-    if isinstance(W, WilsonKernel):
-        assert W.U.shape == (4, V, 3, 3)
-        wfn(_ptr(_geom(L)), W.tbc, _ptr(W.U), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
+    kern, tbc, arr, clov = _kernel_args(W)
+    if kern == 1:
+        assert arr.shape == (4, V, 3, 3)
+        wfn(_ptr(_geom(L)), tbc, _ptr(arr), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
     else:
-        W = _c128(W)
-        fn(_ptr(_geom(L)), _ptr(W), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
+        fn(_ptr(_geom(L)), _ptr(arr), float(m0), _ptr(psi), _ptr(out), int(psi.shape[0]))
+    if clov is not None:
+        _load().orc_clover_apply(_ptr(_geom(L)), _ptr(clov), _ptr(psi), _ptr(out), int(psi.shape[0]),
+                                 1 if adj else 0)
     return out[0] if squeeze else out
 
 
@@ -185,7 +215,7 @@ def dirac(L, W, m0: float, psi: np.ndarray) -> np.ndarray:
 
 def dirac_adj(L, W, m0: float, psi: np.ndarray) -> np.ndarray:
     """D(m0)^dag psi by the transposed sum (no gamma5 trick); Brillouin or Wilson."""
-    return _apply(_load().orc_dirac_adj, L, W, m0, psi, _load().orc_wilson_adj)
+    return _apply(_load().orc_dirac_adj, L, W, m0, psi, _load().orc_wilson_adj, adj=True)
 
 
 def dense_matrix(L, W, m0: float) -> np.ndarray:
@@ -193,10 +223,14 @@ def dense_matrix(L, W, m0: float) -> np.ndarray:
     V = volume(L)
     n = 12 * V
     M = np.zeros((n, n), dtype=np.complex128)
-    if isinstance(W, WilsonKernel):
-        _load().orc_wilson_dense(_ptr(_geom(L)), W.tbc, _ptr(W.U), float(m0), _ptr(M))
+    kern, tbc, arr, clov = _kernel_args(W)
+    if kern == 1:
+        _load().orc_wilson_dense(_ptr(_geom(L)), tbc, _ptr(arr), float(m0), _ptr(M))
     else:
-        _load().orc_dirac_dense(_ptr(_geom(L)), _ptr(_c128(W)), float(m0), _ptr(M))
+        _load().orc_dirac_dense(_ptr(_geom(L)), _ptr(arr), float(m0), _ptr(M))
+    if clov is not None:
+        for x in range(V):
+            M[12 * x:12 * x + 12, 12 * x:12 * x + 12] += clov[x]
     return M
 
 
@@ -230,9 +264,9 @@ def cg(L, W, m0: float, sigma: float, b: np.ndarray, tol: float = 1e-13, maxit: 
     b = _c128(b)
     x = np.zeros_like(b)
     rel = ctypes.c_double(0)
-    kern, tbc, arr = _kernel_args(W)
+    kern, tbc, arr, clov = _kernel_args(W)
     it = _load().orc_cg(
-        _ptr(_geom(L)), kern, tbc, _ptr(arr), float(m0), float(sigma), _ptr(b), _ptr(x), float(tol), int(maxit),
+        _ptr(_geom(L)), kern, tbc, _ptr(arr), None if clov is None else _ptr(clov), float(m0), float(sigma), _ptr(b), _ptr(x), float(tol), int(maxit),
         ctypes.byref(rel),
     )
     return x, it, rel.value
@@ -279,9 +313,9 @@ def rational_apply_coeffs(L, W, m0: float, c0: float, om, sg, b: np.ndarray, tol
     sg = np.ascontiguousarray(sg, dtype=np.float64)
     iters = np.zeros(n, dtype=np.int32)
     rel = np.zeros(n, dtype=np.float64)
-    kern, tbc, arr = _kernel_args(W)
+    kern, tbc, arr, clov = _kernel_args(W)
     _load().orc_rational(
-        _ptr(_geom(L)), kern, tbc, _ptr(arr), float(m0), int(n), float(c0), _ptr(om), _ptr(sg), _ptr(b), _ptr(y),
+        _ptr(_geom(L)), kern, tbc, _ptr(arr), None if clov is None else _ptr(clov), float(m0), int(n), float(c0), _ptr(om), _ptr(sg), _ptr(b), _ptr(y),
         float(tol), int(maxit), _ptr(iters), _ptr(rel),
     )
     return y, iters, rel

@@ -39,6 +39,9 @@
  *   orc_wilson, orc_wilson_adj, orc_wilson_dense  the Wilson operator of eq. (def_wils)
  *                  (c_SW = 0) from its covariant derivative and 9-point Laplacian, applied
  *                  block by block straight from U; the adjoint as the transposed sum.
+ *   orc_clover, orc_clover_apply  the clover term -(c_SW/2) sum sigma_mu_nu F_mu_nu with the
+ *                  clover-leaf F_mu_nu (the paper gives no discretisation; see orc_clover),
+ *                  and its site-local application (any kernel, and its adjoint).
  *   orc_cg         textbook conjugate gradient on (D^dag D + sigma) x = b, for either kernel
  *                  (kern 0: Brillouin with its link array W; kern 1: Wilson with U and tbc).
  *   orc_rational   y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, every
@@ -573,6 +576,105 @@ void orc_wilson_dense(const int *L, int tbc, const cplx *U, double m0, cplx *M) 
     }
 }
 
+/* ------------------------------------------------------------------- clover */
+
+/*
+ * Clover term of eqs. (def_wils), (def_bril): -(c_SW/2) sum_{mu<nu} sigma_mu_nu F_mu_nu on the
+ * diagonal.  The paper does not give the discretisation of F_mu_nu; used here (a reading):
+ *   sigma_mu_nu = (i/2) [gamma_mu, gamma_nu],
+ *   Q_mu_nu(x)  = the four plaquettes in the mu-nu plane that start and end at x, each taken
+ *                 counter-clockwise (mu first, then nu),
+ *   F_mu_nu(x)  = (Q_mu_nu - Q_mu_nu^dag) / (8 i), minus its trace / 3 (hermitian, traceless).
+ * The gauge loops are closed, so the fermion boundary condition does not enter.
+ * out[V][12][12], index 3*spin + colour.
+ */
+static void plaq_leaves(const int *L, const cplx *U, long x, int mu, int nu, cplx Q[9]) {
+    const long V = vol(L);
+    int c[4];
+    coords(L, x, c);
+    /* a leaf is a closed path of four steps (+-mu, +-nu), given by the signs of its first two steps */
+    const int leaf[4][2] = {{+1, +1}, {+1, -1}, {-1, -1}, {-1, +1}};
+    memset(Q, 0, sizeof(cplx) * 9);
+    for (int l = 0; l < 4; ++l) {
+        /* counter-clockwise in the (mu, nu) plane: steps a*mu, b*nu, -a*mu, -b*nu with a*b = +1, or
+         * b*nu, a*mu, -b*nu, -a*mu with a*b = -1 */
+        const int a = leaf[l][0], b = leaf[l][1];
+        int dirs[4], sg[4];
+        if (a * b > 0) {
+            dirs[0] = mu; sg[0] = a; dirs[1] = nu; sg[1] = b; dirs[2] = mu; sg[2] = -a; dirs[3] = nu; sg[3] = -b;
+        } else {
+            dirs[0] = nu; sg[0] = b; dirs[1] = mu; sg[1] = a; dirs[2] = nu; sg[2] = -b; dirs[3] = mu; sg[3] = -a;
+        }
+        cplx M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        int y[4] = {c[0], c[1], c[2], c[3]};
+        for (int st = 0; st < 4; ++st) {
+            cplx T[9];
+            const int d = dirs[st];
+            if (sg[st] > 0) {
+                mat_mul(M, U + ((size_t)d * V + site_of(L, y)) * 9, T);
+                y[d] += 1;
+            } else {
+                y[d] -= 1;
+                mat_mul_dag(M, U + ((size_t)d * V + site_of(L, y)) * 9, T);
+            }
+            memcpy(M, T, sizeof(T));
+        }
+        for (int e = 0; e < 9; ++e) Q[e] += M[e];
+    }
+}
+
+void orc_clover(const int *L, const cplx *U, double csw, cplx *out) {
+    const long V = vol(L);
+    init_gammas();
+    /* sigma_mu_nu = (i/2)(gamma_mu gamma_nu - gamma_nu gamma_mu) */
+    cplx sig[4][4][4][4];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    cplx v = 0;
+                    for (int k = 0; k < 4; ++k) v += GAM[mu][a][k] * GAM[nu][k][b] - GAM[nu][a][k] * GAM[mu][k][b];
+                    sig[mu][nu][a][b] = 0.5 * _Complex_I * v;
+                }
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        cplx *C = out + (size_t)x * 144;
+        memset(C, 0, sizeof(cplx) * 144);
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                cplx Q[9], F[9];
+                plaq_leaves(L, U, x, mu, nu, Q);
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) F[3 * i + j] = (Q[3 * i + j] - conj(Q[3 * j + i])) / (8.0 * _Complex_I);
+                const cplx tr = (F[0] + F[4] + F[8]) / 3.0;
+                for (int i = 0; i < 3; ++i) F[4 * i] -= tr;
+                for (int s = 0; s < 4; ++s)
+                    for (int t = 0; t < 4; ++t)
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j)
+                                C[(3 * s + i) * 12 + 3 * t + j] += -0.5 * csw * sig[mu][nu][s][t] * F[3 * i + j];
+            }
+    }
+}
+
+/* out[x] += C(x) in[x] (adj: C(x)^dag in[x]) for nrhs right-hand sides */
+void orc_clover_apply(const int *L, const cplx *Cf, const cplx *in, cplx *out, int nrhs, int adj) {
+    const long V = vol(L);
+    for (int r = 0; r < nrhs; ++r) {
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < V; ++x) {
+            const cplx *C = Cf + (size_t)x * 144;
+            const cplx *p = in + ((size_t)r * V + x) * 12;
+            cplx *o = out + ((size_t)r * V + x) * 12;
+            for (int i = 0; i < 12; ++i) {
+                cplx v = 0;
+                for (int j = 0; j < 12; ++j) v += (adj ? conj(C[j * 12 + i]) : C[i * 12 + j]) * p[j];
+                o[i] += v;
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------ solvers */
 
 static cplx dotc(const cplx *a, const cplx *b, long n) {
@@ -593,6 +695,7 @@ static double norm2(const cplx *a, long n) { return creal(dotc(a, a, n)); }
 typedef struct {
     int kern, tbc;
     const cplx *W;
+    const cplx *clov; /* clover field [V][12][12] or NULL */
 } kernel_t;
 
 static void kernel_apply(const int *L, const kernel_t *K, double m0, const cplx *x, cplx *y, int adj) {
@@ -607,6 +710,7 @@ static void kernel_apply(const int *L, const kernel_t *K, double m0, const cplx 
         else
             orc_dirac(L, K->W, m0, x, y, 1);
     }
+    if (K->clov) orc_clover_apply(L, K->clov, x, y, 1, adj);
 }
 
 /* y = (D^dag D + sigma) x */
@@ -622,10 +726,10 @@ static void normal_op(const int *L, const kernel_t *K, double m0, double sigma, 
  * recursive residual is below tol*|b|, then recomputes the true residual and
  * restarts from the current x if that is still above tol*|b|.
  * Returns the iteration count; *true_rel receives |b - (A+sigma)x|/|b|. */
-int orc_cg(const int *L, int kern, int tbc, const cplx *W, double m0, double sigma, const cplx *b, cplx *x,
-           double tol, int maxit, double *true_rel) {
+int orc_cg(const int *L, int kern, int tbc, const cplx *W, const cplx *clov, double m0, double sigma,
+           const cplx *b, cplx *x, double tol, int maxit, double *true_rel) {
     const long n = 12 * vol(L);
-    const kernel_t Kv = {kern, tbc, W};
+    const kernel_t Kv = {kern, tbc, W, clov};
     const kernel_t *K = &Kv;
     cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
     cplx *Ap = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
@@ -675,7 +779,7 @@ int orc_cg(const int *L, int kern, int tbc, const cplx *W, double m0, double sig
 
 /* y = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, each shift separately.
  * iters[i], rel[i] receive the per-shift CG iteration count and true residual. */
-int orc_rational(const int *L, int kern, int tbc, const cplx *W, double m0, int nshift, double c0,
+int orc_rational(const int *L, int kern, int tbc, const cplx *W, const cplx *clov, double m0, int nshift, double c0,
                  const double *omega, const double *sigma, const cplx *b, cplx *y, double tol, int maxit, int *iters,
                  double *rel) {
     const long n = 12 * vol(L);
@@ -683,7 +787,7 @@ int orc_rational(const int *L, int kern, int tbc, const cplx *W, double m0, int 
     for (long i = 0; i < n; ++i) y[i] = c0 * b[i];
     int worst = 0;
     for (int s = 0; s < nshift; ++s) {
-        iters[s] = orc_cg(L, kern, tbc, W, m0, sigma[s], b, xs, tol, maxit, &rel[s]);
+        iters[s] = orc_cg(L, kern, tbc, W, clov, m0, sigma[s], b, xs, tol, maxit, &rel[s]);
         if (rel[s] > tol) worst = 1;
         for (long i = 0; i < n; ++i) y[i] += omega[s] * xs[i];
     }
