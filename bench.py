@@ -58,7 +58,8 @@ def stencil_bytes_per_site(spinor_bytes_per_real: int, link_bytes_per_real: int,
     return (24 + 24) * nrhs * spinor_bytes_per_real + 720 * link_bytes_per_real
 
 
-STENCIL_SOURCES = ("common.hpp", "stencil.hpp", "stencil_core.hpp", "stencil.hip", "tune.hip")
+STENCIL_SOURCES = ("common.hpp", "stencil.hpp", "stencil_core.hpp", "stencil_kernels.hpp", "stencil.hip",
+                   "stencil_f64_bri.hip", "tune.hip")
 
 
 def kernel_source_digest() -> str:

@@ -46,6 +46,9 @@ extern "C" {
 typedef struct {
     int32_t L[4];
     int32_t tbc;
+    double csw; /* clover coefficient c_SW of eqs. (def_wils), (def_bril); 0 = no clover term.
+                   bri_build_links then appends the clover field to the link array, and
+                   every operator built on that array applies it (pass the same value). */
 } bri_geom;
 
 /* storage / arithmetic precision of a field */

@@ -43,7 +43,7 @@ class BriError(RuntimeError):
 
 
 class _Geom(ctypes.Structure):
-    _fields_ = [("L", ctypes.c_int32 * 4), ("tbc", ctypes.c_int32)]
+    _fields_ = [("L", ctypes.c_int32 * 4), ("tbc", ctypes.c_int32), ("csw", ctypes.c_double)]
 
 
 class _OvParams(ctypes.Structure):
@@ -234,12 +234,19 @@ def _torch():
     return torch
 
 
-def _geom(L, tbc=0):
+def _geom(L, tbc=0, csw=0.0):
     g = _Geom()
     for i in range(4):
         g.L[i] = int(L[i])
     g.tbc = int(tbc)
+    g.csw = float(csw)
     return g
+
+
+def _clover_flag(W):
+    """csw for the geometry of an apply: the applies read the clover field from the link array
+    (48 slabs: 40 link slabs and 8 of clover entries) and only test csw != 0."""
+    return 1.0 if W.shape[0] == 48 else 0.0
 
 
 def _stream(stream=None):
@@ -295,6 +302,17 @@ def spinor_to_host(psi_t):
     return np.ascontiguousarray(np.transpose(a, (0, 3, 1, 2)))
 
 
+def clover_to_host(W_t, prec=F64):
+    """The clover term stored after the link slabs of a (48, 3, 3, V) array, as (V, 12, 12)
+    complex128 (block diagonal in the two chiralities)."""
+    V = W_t.shape[-1]
+    a = links_W_to_host(W_t, prec)[:, 40:].reshape(V, 2, 6, 6)
+    out = np.zeros((V, 12, 12), dtype=np.complex128)
+    out[:, :6, :6] = a[:, 0]
+    out[:, 6:, 6:] = a[:, 1]
+    return out
+
+
 def links_W_to_host(W_t, prec=F64):
     """(40, 3, 3, V) tensor -> (V, 40, 3, 3) complex128 numpy (bfloat16 pairs unpacked)."""
     if prec == F32_BF16W:
@@ -310,15 +328,20 @@ def links_W_to_host(W_t, prec=F64):
 # ------------------------------------------------------------------ the ABI
 
 
-def build_links(L, U, prec=F64, tbc=0, stream=None, out=None):
-    """Off-axis links W [40][3][3][V] in precision `prec` from device links U [4][3][3][V]."""
+def build_links(L, U, prec=F64, tbc=0, stream=None, out=None, csw=0.0):
+    """Off-axis links W [40][3][3][V] in precision `prec` from device links U [4][3][3][V];
+    with csw != 0 the clover term follows as 8 more slabs ([48][3][3][V] in all, the clover
+    entries [2][6][6][V] after the links)."""
     torch = _torch()
     V = int(np.prod(L))
     if U.dtype != torch.complex128 or tuple(U.shape) != (4, 3, 3, V):
         raise ValueError("U must be complex128 of shape (4, 3, 3, V)")
+    nslab = 48 if csw else 40
     if out is None:
-        out = torch.empty((40, 3, 3, V), dtype=link_dtype(prec), device=U.device)
-    g = _geom(L, tbc)
+        out = torch.empty((nslab, 3, 3, V), dtype=link_dtype(prec), device=U.device)
+    if tuple(out.shape) != (nslab, 3, 3, V):
+        raise ValueError(f"out must be ({nslab}, 3, 3, V)")
+    g = _geom(L, tbc, csw)
     _check("bri_build_links", load().bri_build_links(ctypes.byref(g), _dptr(U), _dptr(out), int(prec), _stream(stream)))
     return out
 
@@ -328,11 +351,11 @@ def _apply(fn, L, W, prec, m0, psi, out=None, stream=None):
     V = int(np.prod(L))
     if psi.dim() != 4 or tuple(psi.shape[1:]) != (4, 3, V) or psi.dtype != spinor_dtype(prec):
         raise ValueError("psi must be (nrhs, 4, 3, V) of the spinor dtype of prec")
-    if W.dtype != link_dtype(prec) or tuple(W.shape) != (40, 3, 3, V):
-        raise ValueError("W must be (40, 3, 3, V) of the link dtype of prec")
+    if W.dtype != link_dtype(prec) or W.shape[0] not in (40, 48) or tuple(W.shape[1:]) != (3, 3, V):
+        raise ValueError("W must be (40 or 48, 3, 3, V) of the link dtype of prec")
     if out is None:
         out = torch.empty_like(psi)
-    g = _geom(L)
+    g = _geom(L, 0, _clover_flag(W))
     st = getattr(load(), fn)(ctypes.byref(g), _dptr(W), int(prec), float(m0), _dptr(psi), _dptr(out),
                              int(psi.shape[0]), _stream(stream))
     _check(fn, st)
@@ -371,7 +394,9 @@ class OverlapOp:
         at tol * omega_max / omega_i; kernel = KERNEL_WILSON builds the overlap on the
         Wilson operator (the one-hop slabs of W64) instead of the Brillouin one."""
         self.L = tuple(int(v) for v in L)
-        self.g = _geom(self.L, tbc)
+        if Wlo is not None and Wlo.shape[0] != W64.shape[0]:
+            raise ValueError("W64 and Wlo must both carry the clover term or both not")
+        self.g = _geom(self.L, tbc, _clover_flag(W64))
         self.W64 = W64
         self.Wlo = Wlo
         if inner != F64 and Wlo is None:
@@ -527,8 +552,8 @@ def _tune_check(L, W, prec, psi):
     torch = _torch()
     if psi.dim() != 4 or tuple(psi.shape[1:]) != (4, 3, V) or psi.dtype != spinor_dtype(prec):
         raise ValueError("psi must be (nrhs, 4, 3, V) of the spinor dtype of prec")
-    if W.dtype != link_dtype(prec) or tuple(W.shape) != (40, 3, 3, V):
-        raise ValueError("W must be (40, 3, 3, V) of the link dtype of prec")
+    if W.dtype != link_dtype(prec) or W.shape[0] not in (40, 48) or tuple(W.shape[1:]) != (3, 3, V):
+        raise ValueError("W must be (40 or 48, 3, 3, V) of the link dtype of prec")
     return torch.empty_like(psi)
 
 
@@ -536,7 +561,7 @@ def stencil_time(L, W, prec, psi, cfg=None, reps=10, stream=None):
     """Microseconds per bri_apply launch with configuration cfg (None: current default)."""
     out = _tune_check(L, W, prec, psi)
     us = ctypes.c_double()
-    g = _geom(L)
+    g = _geom(L, 0, _clover_flag(W))
     _check("bri_stencil_time", load().bri_stencil_time(ctypes.byref(g), _dptr(W), int(prec), _dptr(psi), _dptr(out),
                                                        int(psi.shape[0]), None if cfg is None else ctypes.byref(cfg),
                                                        int(reps), ctypes.byref(us), _stream(stream)))
@@ -550,7 +575,7 @@ def autotune(L, W, prec, psi, reps=5, stream=None):
     out = _tune_check(L, W, prec, psi)
     best = StencilCfg()
     us = ctypes.c_double()
-    g = _geom(L)
+    g = _geom(L, 0, _clover_flag(W))
     _check("bri_autotune", load().bri_autotune(ctypes.byref(g), _dptr(W), int(prec), _dptr(psi), _dptr(out),
                                                int(psi.shape[0]), int(reps), ctypes.byref(best), ctypes.byref(us),
                                                _stream(stream)))

@@ -36,7 +36,7 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     srcs = sources()
     tmpdir = tempfile.mkdtemp(prefix="bri_build_")
     try:

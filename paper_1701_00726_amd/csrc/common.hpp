@@ -19,7 +19,18 @@ struct Geom {
     int L[4];
     int V;
     int tbc;
+    double csw;  // clover coefficient; nonzero: the link array carries the clover field
 };
+
+// Link array layout: 40 stored slabs of 3x3 complex entries ([40][3][3][V]), followed when
+// csw != 0 by the clover term -(c_SW/2) sum_{mu<nu} sigma_mu_nu F_mu_nu as its two chirality
+// blocks of 6x6 complex entries ([2][6][6][V], row and column index 3*spin + colour within the
+// block; spins 0,1 and 2,3).
+constexpr int LINK_SLAB_ENTRIES = 360;   // per site
+constexpr int CLOVER_ENTRIES = 72;       // per site
+inline size_t link_entries(const Geom &g) {
+    return (size_t)g.V * (LINK_SLAB_ENTRIES + (g.csw != 0.0 ? CLOVER_ENTRIES : 0));
+}
 
 __host__ __device__ inline int disp_comp(int j, int mu) {
     int p = 1;

@@ -455,6 +455,7 @@ int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs
     Geom g;
     int rc = geom_check(geom, &g);
     if (rc != BRI_OK) return rc;
+    if (g.csw != 0.0) return BRI_EINVAL;  // the clover term's derivative is not built
     if (!work_bytes || npairs < 1 || npairs > BRI_MAX_PAIRS) return BRI_EINVAL;
     const size_t need = grad_g_bytes(g);
     if (!work) {
@@ -483,7 +484,7 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     Geom g;
     int rc = geom_check(geom, &g);
     if (rc != BRI_OK) return rc;
-    if (!prm || !work_bytes) return BRI_EINVAL;
+    if (!prm || !work_bytes || g.csw != 0.0) return BRI_EINVAL;
     const int n = prm->kl_n;
     if (!params_ok(prm) || g.V % 64) return BRI_EINVAL;
     if (prm->kernel != BRI_KERNEL_BRILLOUIN) return BRI_EINVAL;  // the force pulls back through W's paths

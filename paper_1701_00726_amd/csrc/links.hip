@@ -9,6 +9,8 @@
 // level by level (k = 1..4 hops), one kernel per level, in FP64.  A level-(k-1)
 // link that is not stored is the hermitian conjugate of a stored one at the
 // far end, W_{d'}(y) = W_{-d'}(y + d')^dag.
+#include <cmath>
+
 #include "common.hpp"
 
 namespace bri {
@@ -133,11 +135,136 @@ int geom_check(const bri_geom *geom, Geom *g) {
         g->L[mu] = geom->L[mu];
         V *= geom->L[mu];
     }
-    // 40 link slabs of 9 complex entries per site must stay addressable by a 32-bit element offset
-    if (V * 360LL >= (1LL << 31)) return BRI_EINVAL;
+    // the link array (40 slabs of 9 complex entries per site, plus 72 clover entries) must stay
+    // addressable by a 32-bit element offset
+    if (!std::isfinite(geom->csw)) return BRI_EINVAL;
+    if (V * (geom->csw != 0.0 ? 432LL : 360LL) >= (1LL << 31)) return BRI_EINVAL;
     if (geom->tbc != 0 && geom->tbc != 1) return BRI_EINVAL;
     g->V = (int)V;
     g->tbc = geom->tbc;
+    g->csw = geom->csw;
+    return BRI_OK;
+}
+
+// ------------------------------------------------------------------- clover
+
+// One site: the clover-leaf field strength of every plane and its contribution to the two
+// chirality blocks of -(c_SW/2) sum_{mu<nu} sigma_mu_nu F_mu_nu.
+//   Q_mu_nu(x) = sum of the four plaquettes at x in the mu-nu plane, all counter-clockwise
+//               (mu before nu): steps (+mu,+nu,-mu,-nu), (+nu,-mu,-nu,+mu), (-mu,-nu,+mu,+nu),
+//               (-nu,+mu,+nu,-mu);
+//   F_mu_nu = (Q - Q^dag) / (8i) minus its trace / 3.
+// With sigma_mu_nu = (i/2)[gamma_mu, gamma_nu] in the chiral basis, sigma_jk = -eps_jkl s_l in
+// both blocks and sigma_j4 = +s_j (spins 0,1) and -s_j (spins 2,3), s_l the Pauli matrices, so
+// plane (mu, nu) enters with one Pauli matrix s_l and a sign per block:
+//   xy: s_3, (-,-)   xz: s_2, (+,+)   yz: s_1, (-,-)   xt: s_1, (+,-)   yt: s_2, (+,-)   zt: s_3, (+,-)
+__device__ void leaf_walk(const Geom &g, const double2 *__restrict__ U, const int c0[4], const int dir[4],
+                          const int sgn[4], double2 (&M)[3][3]) {
+    int c[4] = {c0[0], c0[1], c0[2], c0[3]};
+    const unsigned V = (unsigned)g.V;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+    for (int st = 0; st < 4; ++st) {
+        const int d = dir[st];
+        if (sgn[st] < 0) c[d] = c[d] == 0 ? g.L[d] - 1 : c[d] - 1;
+        const unsigned y = (unsigned)(c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3])));
+        double2 u[3][3], T[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double2 e = U[((size_t)(d * 3 + a) * 3 + b) * V + y];
+                if (sgn[st] > 0)
+                    u[a][b] = e;
+                else
+                    u[b][a] = make_double2(e.x, -e.y);
+            }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double re = 0.0, im = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    re += M[a][k].x * u[k][b].x - M[a][k].y * u[k][b].y;
+                    im += M[a][k].x * u[k][b].y + M[a][k].y * u[k][b].x;
+                }
+                T[a][b] = make_double2(re, im);
+            }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a][b] = T[a][b];
+        if (sgn[st] > 0) c[d] = c[d] == g.L[d] - 1 ? 0 : c[d] + 1;
+    }
+}
+
+__global__ void clover_build_kernel(Geom g, const double2 *__restrict__ U, double2 *__restrict__ C) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.V) return;
+    const unsigned V = (unsigned)g.V;
+    int c[4];
+    for (int mu = 0, r = x; mu < 4; ++mu) {
+        c[mu] = r % g.L[mu];
+        r /= g.L[mu];
+    }
+    double2 blk[2][6][6];
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) blk[k][a][b] = make_double2(0.0, 0.0);
+    const double h = -0.5 * g.csw;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            double2 Q[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Q[a][b] = make_double2(0.0, 0.0);
+            const int dirs[4][4] = {{mu, nu, mu, nu}, {nu, mu, nu, mu}, {mu, nu, mu, nu}, {nu, mu, nu, mu}};
+            const int sgns[4][4] = {{1, 1, -1, -1}, {1, -1, -1, 1}, {-1, -1, 1, 1}, {-1, 1, 1, -1}};
+            for (int l = 0; l < 4; ++l) {
+                double2 M[3][3];
+                leaf_walk(g, U, c, dirs[l], sgns[l], M);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        Q[a][b].x += M[a][b].x;
+                        Q[a][b].y += M[a][b].y;
+                    }
+            }
+            // F = (Q - Q^dag) / (8i): F_ab = [ (Q_ab - conj Q_ba) ] / (8i)
+            double2 F[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double dre = Q[a][b].x - Q[b][a].x, dim = Q[a][b].y + Q[b][a].y;
+                    F[a][b] = make_double2(dim / 8.0, -dre / 8.0);  // (dre + i dim) / (8i)
+                }
+            const double tr = (F[0][0].x + F[1][1].x + F[2][2].x) / 3.0;  // F hermitian: real trace
+            for (int a = 0; a < 3; ++a) F[a][a].x -= tr;
+            // Pauli matrix and block signs of this plane
+            const bool tplane = nu == 3;
+            const int l = tplane ? mu + 1 : 4 - mu - nu;  // xy -> 3, xz -> 2, yz -> 1; xt,yt,zt -> 1,2,3
+            const int sgn_sp = (mu == 0 && nu == 2) ? 1 : -1;  // xz: +, xy and yz: -
+            for (int k = 0; k < 2; ++k) {
+                const double kap = h * (tplane ? (k == 0 ? 1.0 : -1.0) : (double)sgn_sp);
+                // nonzero entries z of s_l at (s, t)
+                for (int s = 0; s < 2; ++s)
+                    for (int t = 0; t < 2; ++t) {
+                        double zr = 0.0, zi = 0.0;
+                        if (l == 1 && s != t) zr = 1.0;
+                        if (l == 2 && s == 0 && t == 1) zi = -1.0;
+                        if (l == 2 && s == 1 && t == 0) zi = 1.0;
+                        if (l == 3 && s == t) zr = s == 0 ? 1.0 : -1.0;
+                        if (zr == 0.0 && zi == 0.0) continue;
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) {
+                                const double fr = F[a][b].x, fi = F[a][b].y;
+                                double2 &o = blk[k][s * 3 + a][t * 3 + b];
+                                o.x += kap * (zr * fr - zi * fi);
+                                o.y += kap * (zr * fi + zi * fr);
+                            }
+                    }
+            }
+        }
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) C[((size_t)(k * 6 + a) * 6 + b) * V + x] = blk[k][a][b];
+}
+
+int build_clover(const Geom &g, const double2 *U, double2 *C, hipStream_t st) {
+    const int threads = 64;
+    hipLaunchKernelGGL(clover_build_kernel, dim3((g.V + threads - 1) / threads), dim3(threads), 0, st, g, U, C);
+    BRI_HIP_CHECK(hipGetLastError());
     return BRI_OK;
 }
 
@@ -167,11 +294,16 @@ extern "C" int bri_build_links(const bri_geom *geom, const void *U, void *W, int
     if (!U || !W) return BRI_EINVAL;
     if (wprec != BRI_F64 && wprec != BRI_F32 && wprec != BRI_F32_BF16W) return BRI_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (wprec == BRI_F64) return build_links_f64(g, (const double2 *)U, (double2 *)W, s);
-    const size_t n = (size_t)360 * g.V;
+    if (wprec == BRI_F64) {
+        st = build_links_f64(g, (const double2 *)U, (double2 *)W, s);
+        if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, (double2 *)W + (size_t)360 * g.V, s);
+        return st;
+    }
+    const size_t n = link_entries(g);
     double2 *tmp = nullptr;
     BRI_HIP_CHECK(hipMalloc(&tmp, n * sizeof(double2)));
     st = build_links_f64(g, (const double2 *)U, tmp, s);
+    if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, tmp + (size_t)360 * g.V, s);
     if (st == BRI_OK) {
         const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
         if (wprec == BRI_F32)

@@ -612,10 +612,13 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
     if (use_graph) {
         int dev = 0;
         BRI_HIP_CHECK(hipGetDevice(&dev));
-        uint64_t m0bits;
+        // everything the captured launches bake in: geometry (with the clover switch), precision,
+        // kernel, mass, every buffer address and the launch configuration
+        uint64_t m0bits, cswbits;
         std::memcpy(&m0bits, &s.m0, sizeof(m0bits));
+        std::memcpy(&cswbits, &s.g.csw, sizeof(cswbits));
         key = {(uint64_t)dev, (uint64_t)s.g.L[0], (uint64_t)s.g.L[1], (uint64_t)s.g.L[2], (uint64_t)s.g.L[3],
-               (uint64_t)s.g.tbc, (uint64_t)s.prec, (uint64_t)s.kind, (uint64_t)s.ncol, m0bits,
+               (uint64_t)s.g.tbc, cswbits, (uint64_t)s.prec, (uint64_t)s.kind, (uint64_t)s.ncol, m0bits,
                (uint64_t)(uintptr_t)s.W,
                (uint64_t)(uintptr_t)s.st, (uint64_t)(uintptr_t)s.partial, (uint64_t)(uintptr_t)s.alldone,
                (uint64_t)(uintptr_t)s.r, (uint64_t)(uintptr_t)s.p, (uint64_t)(uintptr_t)s.t,

@@ -7,6 +7,7 @@
 namespace bri {
 
 constexpr int MAXS = BRI_MAX_SHIFTS;
+constexpr int MRHS_SPLIT = 4;  // waves per tile of the multi-RHS stencil kernel
 
 
 // FP64 scalars of one column (one right-hand side) of a batched multi-shift CG.

@@ -1,0 +1,376 @@
+// Brillouin stencil y = D_bri(m0) x on gfx950 (App. C.1), and the Wilson stencil y = D_wil(m0) x
+// (eq. (def_wils)) as the same kernels restricted to the four one-hop slabs with Wilson weights.
+//
+//   (D psi)(x) = (15/8 + m0) psi(x) + C(x) psi(x) + sum_{d != 0} S_d W_d(x) psi(x + d)
+//   S_d = a_k + c_k sum_mu d_mu gamma_mu      (k = number of hops of d)
+// with C(x) the clover term stored after the link slabs (only when the geometry's csw != 0;
+// it commutes with gamma5 and is hermitian, so the adjoint uses it unchanged).
+//
+// Both kernels walk the 40 stored link slabs j and apply, for each, the pair
+// of opposite displacements
+//   own:        S_{d}  W_j(x)            psi(x + d)
+//   neighbour:  S_{-d} W_j(x - d)^dag    psi(x - d)
+// so that a stored link is read by its own site and, as W^dag, by the site
+// across the link at nearly the same time.  The adjoint uses
+// D^dag = gamma5 D gamma5: the same stencil with the derivative weights c_k
+// negated (gamma5 anticommutes with every gamma_mu).
+//
+// stencil_kernel (one right-hand side per block row): a block owns a tile of
+// 64 sites and NSPLIT waves; wave q takes the slabs j = q, q + NSPLIT, ... so
+// that small lattices still fill the 1024 SIMDs.  The NSPLIT partial sums meet
+// in LDS; wave q finishes 12/NSPLIT of the spin-colour components.
+//
+// stencil_mrhs_kernel (many right-hand sides): a block owns a tile of 64 sites
+// and R right-hand sides; its MRHS_SPLIT waves split the slabs as above and
+// every thread carries all R right-hand sides, so each link entry is loaded
+// once per R right-hand sides while the tile still spreads over MRHS_SPLIT
+// waves.  The partial sums meet in LDS one column at a time.
+//
+// The templates are instantiated by the per-variant translation units
+// stencil_<precision>_<kernel>.hip, one (link precision, kernel) pair each, so that the variants
+// compile in parallel.
+#pragma once
+
+#include "stencil.hpp"
+#include "stencil_core.hpp"
+
+namespace bri {
+
+template <typename C> __device__ __forceinline__ double norm2(const C &v) {
+    return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Epilogue for component comp of column col at site x.  Returns the two norm
+// contributions (n0, n1) where the mode has any.
+template <int MODE, typename C, typename R>
+__device__ __forceinline__ void epilogue(const StencilArgs &a, int col, int comp, unsigned x, unsigned V, C v,
+                                         double &n0, double &n1) {
+    const size_t idx = ((size_t)col * 12 + comp) * V + x;
+    if constexpr (MODE == EPI_PLAIN) {
+        ((C *)a.out)[idx] = v;
+    } else if constexpr (MODE == EPI_NORMS) {
+        ((C *)a.out)[idx] = v;
+        n0 += norm2(v);
+        n1 += norm2(((const C *)a.in)[idx]);
+    } else if constexpr (MODE == EPI_CG_R) {
+        const C pp = ((const C *)a.p)[idx];
+        C *rr = (C *)a.r;
+        C r = rr[idx];
+        const R al = (R)a.st[col].alpha;
+        const R s0 = (R)a.st[col].sigma0;
+        const R apx = v.x + s0 * pp.x, apy = v.y + s0 * pp.y;
+        r.x = fma(-al, apx, r.x);
+        r.y = fma(-al, apy, r.y);
+        rr[idx] = r;
+        n0 += norm2(r);
+    } else if constexpr (MODE == EPI_OV) {
+        const C b = ((const C *)a.b)[idx];
+        const R rho = (R)a.rho;
+        ((C *)a.out)[idx] = cmake<C>(rho * (b.x + v.x), rho * (b.y + v.y));
+    } else if constexpr (MODE == EPI_SIGN) {
+        const R sg = comp < 6 ? (R)1 : (R)-1;  // gamma5 = diag(1, 1, -1, -1)
+        ((C *)a.out)[idx] = cmake<C>(sg * v.x, sg * v.y);
+    } else if constexpr (MODE == EPI_RESID) {
+        const size_t bidx = ((size_t)(col % a.b_mod) * 12 + comp) * V + x;
+        const C b = ((const C *)a.b)[bidx];
+        const C xv = ((const C *)a.xs)[idx];
+        const R s = (R)a.sig[col];
+        const C o = cmake<C>(b.x - (v.x + s * xv.x), b.y - (v.y + s * xv.y));
+        ((C *)a.out)[idx] = o;
+        n0 += norm2(o);
+    }
+}
+
+template <int MODE> __device__ __forceinline__ bool col_done(const StencilArgs &a, int col) {
+    if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R) return a.st && a.st[col].done;
+    return false;
+}
+
+// ------------------------------------------------------- one right-hand side
+
+template <class LS, int NSPLIT, bool DAG, int MODE, int KIND>
+__global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
+    using R = typename LS::R;
+    using C = typename Cx<R>::T;
+    constexpr int NCOMP = 12 / NSPLIT;
+    const int col = blockIdx.y;
+    if (col_done<MODE>(a, col)) return;  // whole block: this column has converged
+
+    const unsigned V = (unsigned)a.g.V;
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
+    unsigned om[4], o0[4], op[4];
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+
+    const C *__restrict__ in = (const C *)a.in + (size_t)col * 12 * V;
+    const typename LS::store_t *__restrict__ W = (const typename LS::store_t *)a.W;
+
+    C acc[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[s][b] = cmake<C>((R)0, (R)0);
+    if (q == 0) {
+        const R diag = (R)a.diag;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const C v = in[(size_t)(s * 3 + b) * V + x];
+                acc[s][b] = cmake<C>(diag * v.x, diag * v.y);
+            }
+        if (a.g.csw != 0.0) clover_add<LS>(acc, W + (size_t)LINK_SLAB_ENTRIES * V, in, x, V);
+    }
+
+    for (int k = q; k < Slabs<KIND>::n; k += NSPLIT) {
+        const int j = Slabs<KIND>::at(k);
+        const DirW<R, DAG, KIND> dw(j);
+        const typename LS::store_t *__restrict__ Wj = W + (size_t)j * 9 * V;
+        C chi[4][3];
+        const unsigned y = neighbour(j, +1, om, o0, op);
+        transport<LS, false>(chi, Wj, x, in, y, V);
+        spin_accumulate(acc, chi, dw.a, dw.c0, dw.c1, dw.c2, dw.c3);
+        const unsigned z = neighbour(j, -1, om, o0, op);
+        transport<LS, true>(chi, Wj, z, in, z, V);
+        spin_accumulate(acc, chi, dw.a, -dw.c0, -dw.c1, -dw.c2, -dw.c3);
+    }
+
+    // combine the NSPLIT partial sums through LDS
+    __shared__ C red[NSPLIT > 1 ? NSPLIT : 1][12][64];
+    __shared__ double wsum[NSPLIT][2];
+    C res[NCOMP];
+    if constexpr (NSPLIT > 1) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) red[q][s * 3 + b][lane] = acc[s][b];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) {
+            const int comp = q * NCOMP + i;
+            C v = red[0][comp][lane];
+#pragma unroll
+            for (int w = 1; w < NSPLIT; ++w) {
+                const C u = red[w][comp][lane];
+                v.x += u.x;
+                v.y += u.y;
+            }
+            res[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) res[s * 3 + b] = acc[s][b];
+    }
+
+    double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NCOMP; ++i) epilogue<MODE, C, R>(a, col, q * NCOMP + i, x, V, res[i], n0, n1);
+    if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
+        // deterministic: wave sums, then the NSPLIT wave totals in order
+        n0 = wave_sum(n0);
+        n1 = wave_sum(n1);
+        if (lane == 0) {
+            wsum[q][0] = n0;
+            wsum[q][1] = n1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < NSPLIT; ++w) {
+                s0 += wsum[w][0];
+                s1 += wsum[w][1];
+            }
+            const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+            a.partial[2 * pb] = s0;
+            a.partial[2 * pb + 1] = s1;
+        }
+    }
+}
+
+// ------------------------------------------------------ many right-hand sides
+
+template <class LS, int R, bool DAG, int MODE, int KIND>
+__global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilArgs a) {
+    using RT = typename LS::R;
+    using C = typename Cx<RT>::T;
+    constexpr int NSPLIT = MRHS_SPLIT;
+    constexpr int NCOMP = 12 / NSPLIT;
+    const unsigned V = (unsigned)a.g.V;
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col0 = blockIdx.y * R;
+    // block-uniform: every wave of the block carries the same R columns
+    bool live[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        live[r] = (col0 + r < a.ncol) && !col_done<MODE>(a, col0 + r);
+        any |= live[r];
+    }
+    if (!any) return;
+
+    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
+    unsigned om[4], o0[4], op[4];
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
+    const typename LS::store_t *__restrict__ W = (const typename LS::store_t *)a.W;
+
+    C acc[R][4][3];
+    const RT diag = (RT)a.diag;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                C v = cmake<C>((RT)0, (RT)0);
+                if (q == 0 && live[r]) {
+                    const C u = in[((size_t)r * 12 + s * 3 + b) * V + x];
+                    v = cmake<C>(diag * u.x, diag * u.y);
+                }
+                acc[r][s][b] = v;
+            }
+    if (q == 0 && a.g.csw != 0.0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (live[r]) clover_add<LS>(acc[r], W + (size_t)LINK_SLAB_ENTRIES * V, in + (size_t)r * 12 * V, x, V);
+    }
+
+    for (int k = q; k < Slabs<KIND>::n; k += NSPLIT) {
+        const int j = Slabs<KIND>::at(k);
+        const DirW<RT, DAG, KIND> dw(j);
+        const typename LS::store_t *__restrict__ Wj = W + (size_t)j * 9 * V;
+        C wl[3][3];
+        C chi[4][3];
+        {
+            const unsigned y = neighbour(j, +1, om, o0, op);
+            load_link<LS>(wl, Wj, x, V);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!live[r]) continue;
+                transport_reg<C, RT, false>(chi, wl, in + (size_t)r * 12 * V, y, V);
+                spin_accumulate(acc[r], chi, dw.a, dw.c0, dw.c1, dw.c2, dw.c3);
+            }
+        }
+        {
+            const unsigned z = neighbour(j, -1, om, o0, op);
+            load_link<LS>(wl, Wj, z, V);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!live[r]) continue;
+                transport_reg<C, RT, true>(chi, wl, in + (size_t)r * 12 * V, z, V);
+                spin_accumulate(acc[r], chi, dw.a, -dw.c0, -dw.c1, -dw.c2, -dw.c3);
+            }
+        }
+    }
+
+    // per column: the NSPLIT partial sums meet in LDS, wave q finishes NCOMP components
+    __shared__ C red[NSPLIT][12][64];
+    __shared__ double wsum[NSPLIT][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!live[r]) continue;
+        const int col = col0 + r;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) red[q][s * 3 + b][lane] = acc[r][s][b];
+        __syncthreads();
+        double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) {
+            const int comp = q * NCOMP + i;
+            C v = red[0][comp][lane];
+#pragma unroll
+            for (int w = 1; w < NSPLIT; ++w) {
+                const C u = red[w][comp][lane];
+                v.x += u.x;
+                v.y += u.y;
+            }
+            epilogue<MODE, C, RT>(a, col, comp, x, V, v, n0, n1);
+        }
+        if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
+            // deterministic: wave sums, then the NSPLIT wave totals in order
+            n0 = wave_sum(n0);
+            n1 = wave_sum(n1);
+            if (lane == 0) {
+                wsum[q][0] = n0;
+                wsum[q][1] = n1;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s0 = 0.0, s1 = 0.0;
+                for (int w = 0; w < NSPLIT; ++w) {
+                    s0 += wsum[w][0];
+                    s1 += wsum[w][1];
+                }
+                const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+                a.partial[2 * pb] = s0;
+                a.partial[2 * pb + 1] = s1;
+            }
+        }
+        __syncthreads();  // red and wsum are reused by the next column
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+template <class LS, int NSPLIT, bool DAG, int KIND>
+inline hipError_t launch_1rhs(const StencilArgs &a, int mode, hipStream_t st) {
+    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)a.ncol), block(64 * NSPLIT);
+    switch (mode) {
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_PLAIN, KIND>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_NORMS, KIND>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_CG_R, KIND>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_OV, KIND>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_SIGN, KIND>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_RESID, KIND>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class LS, int R, bool DAG, int KIND>
+inline hipError_t launch_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
+    const int groups = (a.ncol + R - 1) / R;
+    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(64 * MRHS_SPLIT);
+    switch (mode) {
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_PLAIN, KIND>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_NORMS, KIND>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_CG_R, KIND>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_OV, KIND>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_SIGN, KIND>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_RESID, KIND>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class LS, bool DAG, int KIND>
+inline hipError_t launch_cfg(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
+    switch (cfg.rpt) {
+    case 0:
+        switch (cfg.nsplit) {
+        case 1: return launch_1rhs<LS, 1, DAG, KIND>(a, mode, st);
+        case 2: return launch_1rhs<LS, 2, DAG, KIND>(a, mode, st);
+        case 4: return launch_1rhs<LS, 4, DAG, KIND>(a, mode, st);
+        default: return hipErrorInvalidValue;
+        }
+    case 1: return launch_mrhs<LS, 1, DAG, KIND>(a, mode, st);
+    case 2: return launch_mrhs<LS, 2, DAG, KIND>(a, mode, st);
+    case 3: return launch_mrhs<LS, 3, DAG, KIND>(a, mode, st);
+    case 4: return launch_mrhs<LS, 4, DAG, KIND>(a, mode, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bri

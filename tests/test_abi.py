@@ -259,3 +259,24 @@ def test_kernel_selector_validated():
     assert lib.wil_apply(ctypes.byref(g), None, 0, 0.0, None, None, 1, None) == bri.EINVAL
     assert lib.wil_apply_dag(ctypes.byref(g), ctypes.c_void_p(256), 7, 0.0, ctypes.c_void_p(256),
                              ctypes.c_void_p(512), 1, None) == bri.EINVAL
+
+
+def test_clover_geometry_validated():
+    lib = bri.load()
+    nb = ctypes.c_size_t(0)
+    g = bri._geom((8, 8, 8, 8), 0, float("nan"))
+    prm = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0)
+    assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb), None,
+                        None) == bri.EINVAL
+    g = bri._geom((8, 8, 8, 8), 0, 1.0)
+    assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb), None,
+                        None) == bri.OK
+    # the force does not differentiate the clover term: rejected before any launch
+    assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None, None,
+                             ctypes.byref(nb), None, None) == bri.EINVAL
+    w = (ctypes.c_double * 1)(1.0)
+    assert lib.bri_link_grad(ctypes.byref(g), None, None, 1, w, None, None, None, None, None, ctypes.byref(nb),
+                             None) == bri.EINVAL
+    # a lattice whose link array with the clover entries exceeds 32-bit offsets is refused
+    big = bri._geom((128, 128, 80, 4), 0, 1.0)  # 360 V fits 31 bits, 432 V does not
+    assert lib.bri_build_links(ctypes.byref(big), ctypes.c_void_p(256), ctypes.c_void_p(256), 0, None) == bri.EINVAL
