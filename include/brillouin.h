@@ -200,6 +200,7 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  * kl_n = 4 with prec = {n = 1, Brillouin}.  The same bare mass is used at every level.
  */
 #define BRI_MAX_LEVELS 4
+#define BRI_MAX_SOLVE_RHS 16
 
 typedef struct {
     double mass;  /* bare quark mass m, 0 <= m < 2 rho                               */
@@ -218,11 +219,13 @@ typedef struct {
 } ov_level;
 
 typedef struct {
-    int iters;                          /* outer BiCGstab iterations                          */
+    int iters;                          /* outer BiCGstab iterations (until every column met
+                                           tol)                                               */
     int inner_iters;                    /* multi-shift CG iterations summed over every level  */
     int applies;                        /* D_ov applies of the outer level (bt, two per
                                            iteration, the final check)                        */
-    double rel_resid;                   /* true |bt - (D_ov + mt) x| / |bt| at exit            */
+    double rel_resid;                   /* true |bt - (D_ov + mt) x| / |bt| at exit, worst
+                                           column                                             */
     int level_iters[BRI_MAX_LEVELS];    /* BiCGstab iterations summed per preconditioner level */
     int level_calls[BRI_MAX_LEVELS];    /* applications of each preconditioner level          */
     int level_applies[BRI_MAX_LEVELS];  /* operator applies of each preconditioner level      */
@@ -230,13 +233,16 @@ typedef struct {
 } ov_solve_stats;
 
 /*
- * ov_solve -- x = (D_ov + mt)^{-1} bt for one right-hand side.
+ * ov_solve -- x = (D_ov + mt)^{-1} bt for nrhs right-hand sides side by side (each with its own
+ * BiCGstab scalars and stopping test; every operator application treats all of them in one
+ * batched call, as the paper's 12-source solves do).
  *   W64, Wlo, params : as ov_apply (params->kl_n is the order of the operator solved for; Wlo is
  *          needed when params->inner or any level's inner is low precision)
  *   mp    : mass, form, outer tolerance and iteration cap
  *   nprec, prec : preconditioner chain, 0..BRI_MAX_LEVELS levels (prec may be NULL for 0);
  *          prec[0] preconditions the outer operator, prec[k+1] preconditions prec[k]
- *   in    : b, [4][3][V] complex double;  out : x, same layout, must not overlap in
+ *   in    : b, [nrhs][4][3][V] complex double;  out : x, same layout, must not overlap in
+ *   nrhs  : 1..BRI_MAX_SOLVE_RHS
  *   work, work_bytes : device workspace (query with work == NULL)
  *   stats : may be NULL
  * Synchronises `stream`.  Returns BRI_ENOCONV when max_iter outer iterations did not reach tol
@@ -246,8 +252,8 @@ typedef struct {
  * not errors.
  */
 int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params,
-             const ov_mass_params *mp, int nprec, const ov_level *prec, const void *in, void *out, void *work,
-             size_t *work_bytes, ov_solve_stats *stats, void *stream);
+             const ov_mass_params *mp, int nprec, const ov_level *prec, const void *in, void *out, int nrhs,
+             void *work, size_t *work_bytes, ov_solve_stats *stats, void *stream);
 
 /*
  * Stencil launch configuration and autotuner.  A configuration picks the

@@ -80,6 +80,7 @@ class _MassParams(ctypes.Structure):
 
 
 MAX_LEVELS = 4
+MAX_SOLVE_RHS = 16
 
 
 class _Level(ctypes.Structure):
@@ -194,7 +195,7 @@ def load():
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
             lib.bri_kl_upper_coeffs.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D)]
             lib.ov_solve.argtypes = [G, P, P, ctypes.POINTER(_OvParams), ctypes.POINTER(_MassParams), I,
-                                     ctypes.POINTER(_Level), P, P, P, SZ, ctypes.POINTER(_SolveStats), P]
+                                     ctypes.POINTER(_Level), P, P, I, P, SZ, ctypes.POINTER(_SolveStats), P]
             lib.ov_apply_grad.argtypes = [G, P, P, P, ctypes.POINTER(_OvParams), P, P, P, P, P, P, SZ,
                                           ctypes.POINTER(_OvStats), P]
             for fn in EXPORTS:
@@ -488,21 +489,27 @@ class OverlapOp:
 
 
     def solve(self, b, mass, complete=True, tol=1e-10, max_iter=1000, prec=(), stream=None, allow_noconv=False):
-        """x = (D_ov + mt)^{-1} bt for one right-hand side b: the massive overlap
-        equation of Sec. 4 (complete or traditional form), BiCGstab outer solver with
-        every D_ov apply run by this operator, optionally right-preconditioned by the
-        cascade `prec` (a sequence of Level, Sec. 8).  Returns (x, SolveStats)."""
+        """x = (D_ov + mt)^{-1} bt for the right-hand sides b, (nrhs, 4, 3, V) or one source of
+        12 V entries: the massive overlap equation of Sec. 4 (complete or traditional form),
+        BiCGstab outer solver with every D_ov apply run by this operator, optionally right-
+        preconditioned by the cascade `prec` (a sequence of Level, Sec. 8).  All right-hand
+        sides run side by side.  Returns (x of the shape of b, SolveStats)."""
         torch = _torch()
         V = int(np.prod(self.L))
-        if b.dtype != torch.complex128 or b.numel() != 12 * V:
-            raise ValueError("b must be complex128 with 12 V elements")
+        if b.dtype != torch.complex128 or b.numel() % (12 * V) or b.numel() == 0:
+            raise ValueError("b must be complex128 with a multiple of 12 V elements")
+        nrhs = b.numel() // (12 * V)
+        if nrhs > MAX_SOLVE_RHS:
+            raise ValueError(f"at most {MAX_SOLVE_RHS} right-hand sides per solve")
+        if not b.is_contiguous():
+            raise ValueError("b must be contiguous")
         mp = _MassParams(float(mass), 1 if complete else 0, float(tol), int(max_iter))
         nprec = len(prec)
         lv = (_Level * max(nprec, 1))(*[_Level(int(l.kl_n), float(l.tol), int(l.max_iter), float(l.ms_tol),
                                                 int(l.inner)) for l in prec])
         nb = ctypes.c_size_t(0)
         _check("ov_solve", load().ov_solve(ctypes.byref(self.g), None, None, ctypes.byref(self.params),
-                                           ctypes.byref(mp), nprec, lv, None, None, None, ctypes.byref(nb), None,
+                                           ctypes.byref(mp), nprec, lv, None, None, nrhs, None, ctypes.byref(nb), None,
                                            None))
         if getattr(self, "_swork", None) is None or self._swork.numel() < nb.value:
             self._swork = None
@@ -512,7 +519,7 @@ class OverlapOp:
         wb = ctypes.c_size_t(self._swork.numel())
         rc = load().ov_solve(
             ctypes.byref(self.g), _dptr(self.W64), None if self.Wlo is None else _dptr(self.Wlo),
-            ctypes.byref(self.params), ctypes.byref(mp), nprec, lv, _dptr(b), _dptr(x), _dptr(self._swork),
+            ctypes.byref(self.params), ctypes.byref(mp), nprec, lv, _dptr(b), _dptr(x), nrhs, _dptr(self._swork),
             ctypes.byref(wb), ctypes.byref(st), _stream(stream),
         )
         _check("ov_solve", rc, allow=(ENOCONV,) if allow_noconv else ())

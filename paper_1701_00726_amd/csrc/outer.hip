@@ -14,9 +14,14 @@
 // vectors themselves (phat = K p, shat = K s, v = A phat, t = A shat), so the recursive residual
 // stays the residual of x.
 //
-// The host drives the recurrences; every vector operation and reduction runs on the device,
-// reductions in FP64 with fixed block partial sums added in order on the host (deterministic).
+// Several right-hand sides run side by side, each with its own BiCGstab scalars; every operator
+// application treats all of them in one batched call.  A column that has converged keeps its x
+// and r (its coefficients become those of the identity) until every column is done.  The host
+// drives the recurrences; every vector operation and reduction runs on the device, reductions in
+// FP64 with fixed block partial sums added in order on the host (deterministic).
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <complex>
 #include <cstring>
 #include <vector>
@@ -29,10 +34,12 @@ int geom_check(const bri_geom *geom, Geom *g);
 
 using cplx = std::complex<double>;
 
-constexpr int DOT_BLOCKS = 512;
+constexpr int MAXC = BRI_MAX_SOLVE_RHS;
+constexpr int DOT_BLOCKS = 256;  // per column
 constexpr int DOT_THREADS = 256;
 
-// partial sums of up to three complex dot products <a_k, b_k> = sum conj(a_k) b_k
+// partial sums of up to three complex dot products <a_k, b_k> = sum conj(a_k) b_k per column
+// (column = blockIdx.y, vectors [ncol][n]); partial[k][col][block][2]
 __global__ __launch_bounds__(DOT_THREADS) void outer_dots_kernel(size_t n, int nd, const double2 *__restrict__ a0,
                                                                  const double2 *__restrict__ b0,
                                                                  const double2 *__restrict__ a1,
@@ -40,12 +47,13 @@ __global__ __launch_bounds__(DOT_THREADS) void outer_dots_kernel(size_t n, int n
                                                                  const double2 *__restrict__ a2,
                                                                  const double2 *__restrict__ b2,
                                                                  double *__restrict__ partial) {
+    const size_t off = (size_t)blockIdx.y * n;
     double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     const double2 *as[3] = {a0, a1, a2};
     const double2 *bs[3] = {b0, b1, b2};
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         for (int k = 0; k < nd; ++k) {
-            const double2 u = as[k][i], v = bs[k][i];
+            const double2 u = as[k][off + i], v = bs[k][off + i];
             acc[k][0] += u.x * v.x + u.y * v.y;
             acc[k][1] += u.x * v.y - u.y * v.x;
         }
@@ -59,39 +67,47 @@ __global__ __launch_bounds__(DOT_THREADS) void outer_dots_kernel(size_t n, int n
                 if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
                 __syncthreads();
             }
-            if (threadIdx.x == 0) partial[((size_t)k * gridDim.x + blockIdx.x) * 2 + c] = sh[0];
+            if (threadIdx.x == 0)
+                partial[(((size_t)k * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 2 + c] = sh[0];
             __syncthreads();
         }
 }
 
-// out = c0 x0 + c1 x1 + c2 x2 (complex coefficients; unused terms have a null vector); out may
-// be one of the inputs (elementwise)
-__global__ void outer_lincomb_kernel(size_t n, double2 *out, double2 c0, const double2 *x0, double2 c1,
-                                     const double2 *x1, double2 c2, const double2 *x2) {
+// per-column coefficients of a three-term combination
+struct Coef3 {
+    double2 c[MAXC][3];
+};
+
+// out = c0 x0 + c1 x1 + c2 x2 per column (column = blockIdx.y, vectors [ncol][n]); a null vector is
+// a zero term; out may be one of the inputs (elementwise)
+__global__ void outer_lincomb_kernel(size_t n, double2 *out, Coef3 cf, const double2 *x0, const double2 *x1,
+                                     const double2 *x2) {
+    const int col = blockIdx.y;
+    const size_t off = (size_t)col * n;
+    const double2 *xs[3] = {x0, x1, x2};
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
-        const double2 *xs[3] = {x0, x1, x2};
-        const double2 cs[3] = {c0, c1, c2};
         for (int k = 0; k < 3; ++k) {
             if (!xs[k]) continue;
-            const double2 u = xs[k][i];
-            v.x += cs[k].x * u.x - cs[k].y * u.y;
-            v.y += cs[k].x * u.y + cs[k].y * u.x;
+            const double2 u = xs[k][off + i], c = cf.c[col][k];
+            v.x += c.x * u.x - c.y * u.y;
+            v.y += c.x * u.y + c.y * u.x;
         }
-        out[i] = v;
+        out[off + i] = v;
     }
 }
 
 static inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
-static inline double2 c2d(cplx c) { return make_double2(c.real(), c.imag()); }
+
+using Cols = std::vector<cplx>;  // one coefficient per column
 
 // one level of the cascade: its operator and the BiCGstab vectors of its solves
 struct Level {
-    int kl_n;       // 0: Brillouin operator, else overlap approximant of this order
+    int kl_n;       // 0: kernel operator, else overlap approximant of this order
     ov_params prm;  // overlap apply parameters (kl_n > 0)
     double tol;
     int max_iter;
-    double2 *r, *r0, *p, *v, *s, *t, *ph, *sh;
+    double2 *r, *r0, *p, *v, *s, *t, *ph, *sh;  // [ncol][12 V] each
     int iters = 0, calls = 0, applies = 0;
 };
 constexpr int NVEC = 8;
@@ -101,7 +117,8 @@ struct Cascade {
     Geom g;
     const void *W64, *Wlo;
     double rho, mt;
-    size_t n;
+    size_t n;  // complex entries per column
+    int ncol;
     hipStream_t s;
     void *ov;
     size_t ov_bytes;
@@ -111,45 +128,56 @@ struct Cascade {
     int inner_iters = 0;
     ov_stats ist;
 
-    void lincomb(double2 *dst, cplx c0, const double2 *x0, cplx c1 = 0.0, const double2 *x1 = nullptr,
-                 cplx c2 = 0.0, const double2 *x2 = nullptr) {
-        hipLaunchKernelGGL(outer_lincomb_kernel, dim3(2048), dim3(256), 0, s, n, dst, c2d(c0), x0, c2d(c1), x1,
-                           c2d(c2), x2);
+    Cols all(cplx v) const { return Cols(ncol, v); }
+
+    int lincomb(double2 *dst, const Cols &c0, const double2 *x0, const Cols &c1 = Cols(), const double2 *x1 = nullptr,
+                const Cols &c2 = Cols(), const double2 *x2 = nullptr) {
+        Coef3 cf{};
+        for (int c = 0; c < ncol; ++c) {
+            const cplx k[3] = {c0.empty() ? 0.0 : c0[c], c1.empty() ? 0.0 : c1[c], c2.empty() ? 0.0 : c2[c]};
+            for (int j = 0; j < 3; ++j) cf.c[c][j] = make_double2(k[j].real(), k[j].imag());
+        }
+        hipLaunchKernelGGL(outer_lincomb_kernel, dim3(1024, ncol), dim3(256), 0, s, n, dst, cf, x0, x1, x2);
+        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     }
 
-    // up to three dot products, summed on the host in a fixed order; synchronises the stream
+    // up to three dot products per column, summed on the host in a fixed order; res[k][col];
+    // synchronises the stream
     int dots(int nd, const double2 *a0, const double2 *b0, const double2 *a1, const double2 *b1, const double2 *a2,
-             const double2 *b2, cplx *res) {
-        hipLaunchKernelGGL(outer_dots_kernel, dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, s, n, nd, a0, b0, a1, b1, a2,
-                           b2, partial);
+             const double2 *b2, std::vector<Cols> &res) {
+        hipLaunchKernelGGL(outer_dots_kernel, dim3(DOT_BLOCKS, ncol), dim3(DOT_THREADS), 0, s, n, nd, a0, b0, a1,
+                           b1, a2, b2, partial);
         if (hipGetLastError() != hipSuccess) return BRI_EHIP;
-        if (hipMemcpyAsync(hp.data(), partial, sizeof(double) * 2 * nd * DOT_BLOCKS, hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
+        const size_t cnt = (size_t)2 * nd * ncol * DOT_BLOCKS;
+        if (hipMemcpyAsync(hp.data(), partial, sizeof(double) * cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return BRI_EHIP;
-        for (int k = 0; k < nd; ++k) {
-            double re = 0.0, im = 0.0;
-            for (int i = 0; i < DOT_BLOCKS; ++i) {
-                re += hp[((size_t)k * DOT_BLOCKS + i) * 2];
-                im += hp[((size_t)k * DOT_BLOCKS + i) * 2 + 1];
+        res.assign(nd, Cols(ncol));
+        for (int k = 0; k < nd; ++k)
+            for (int c = 0; c < ncol; ++c) {
+                double re = 0.0, im = 0.0;
+                const double *q = hp.data() + ((size_t)k * ncol + c) * DOT_BLOCKS * 2;
+                for (int i = 0; i < DOT_BLOCKS; ++i) {
+                    re += q[2 * i];
+                    im += q[2 * i + 1];
+                }
+                res[k][c] = cplx(re, im);
             }
-            res[k] = cplx(re, im);
-        }
         return BRI_OK;
     }
 
-    // dst = D_ov^(n_k) v (kl_n > 0) or rho D_bri(-rho) v (kl_n = 0); dst != v
+    // dst = D_ov^(n_k) v (kl_n > 0) or rho D_kernel(-rho) v (kl_n = 0), all columns; dst != v
     int apply_d(Level &L, const double2 *v, double2 *dst) {
         ++L.applies;
         if (L.kl_n == 0) {
-            const int r = L.prm.kernel == BRI_KERNEL_WILSON ? ::wil_apply(geom, W64, BRI_F64, -rho, v, dst, 1, s)
-                                                            : ::bri_apply(geom, W64, BRI_F64, -rho, v, dst, 1, s);
+            const int r = L.prm.kernel == BRI_KERNEL_WILSON
+                              ? ::wil_apply(geom, W64, BRI_F64, -rho, v, dst, ncol, s)
+                              : ::bri_apply(geom, W64, BRI_F64, -rho, v, dst, ncol, s);
             if (r != BRI_OK) return r;
-            lincomb(dst, rho, dst);
-            return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+            return lincomb(dst, all(rho), dst);
         }
         size_t ob = ov_bytes;
-        const int r = ::ov_apply(geom, W64, Wlo, &L.prm, v, dst, 1, ov, &ob, &ist, s);
+        const int r = ::ov_apply(geom, W64, Wlo, &L.prm, v, dst, ncol, ov, &ob, &ist, s);
         inner_iters += ist.iters;
         // a loose preconditioner may stop its multi-shift at the cap
         return (r == BRI_ENOCONV && &L != &lev[0]) ? BRI_OK : r;
@@ -159,77 +187,132 @@ struct Cascade {
     int apply_a(Level &L, const double2 *v, double2 *dst) {
         const int r = apply_d(L, v, dst);
         if (r != BRI_OK) return r;
-        lincomb(dst, 1.0, dst, L.kl_n == 0 ? rho + mt : mt, v);
-        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+        return lincomb(dst, all(1.0), dst, all(L.kl_n == 0 ? rho + mt : mt), v);
     }
 
     // dst = approximate A_{k+1}^{-1} v, or v itself below the last level
     int precondition(int k, const double2 *v, double2 *dst) {
-        if (k + 1 >= (int)lev.size()) {
-            lincomb(dst, 1.0, v);
-            return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
-        }
-        double rel;
+        if (k + 1 >= (int)lev.size()) return lincomb(dst, all(1.0), v);
         int it;
-        const int r = solve(k + 1, v, dst, rel, it);
+        const int r = solve(k + 1, v, dst, it, nullptr);
         // an inner level that stops at its cap (or breaks down after progress) still preconditions
         return (r == BRI_ENOCONV) ? BRI_OK : r;
     }
 
-    // BiCGstab on A_k x = b from x = 0 (shadow residual r0 = b), right-preconditioned by level k+1
-    int solve(int k, const double2 *b, double2 *x, double &rel, int &it) {
+    // BiCGstab on A_k x = b from x = 0 (shadow residual r0 = b) for every column, right-
+    // preconditioned by level k+1.  A column stops at its own tolerance; at the outer level a
+    // breakdown is an error, inside the cascade the column keeps what it has.
+    int solve(int k, const double2 *b, double2 *x, int &it, std::vector<double> *rel_out) {
         Level &L = lev[k];
         ++L.calls;
-        cplx d[3];
-        lincomb(x, 0.0, nullptr);
-        lincomb(L.r, 1.0, b);
-        lincomb(L.r0, 1.0, b);
-        lincomb(L.p, 0.0, nullptr);
-        lincomb(L.v, 0.0, nullptr);
-        int rc = dots(1, b, b, nullptr, nullptr, nullptr, nullptr, d);
-        if (rc != BRI_OK) return rc;
-        const double bn = std::sqrt(d[0].real());
+        std::vector<Cols> d;
+        int rc;
+        if ((rc = lincomb(x, all(0.0), nullptr)) != BRI_OK) return rc;
+        if ((rc = lincomb(L.r, all(1.0), b)) != BRI_OK) return rc;
+        if ((rc = lincomb(L.r0, all(1.0), b)) != BRI_OK) return rc;
+        if ((rc = lincomb(L.p, all(0.0), nullptr)) != BRI_OK) return rc;
+        if ((rc = lincomb(L.v, all(0.0), nullptr)) != BRI_OK) return rc;
+        if ((rc = dots(1, b, b, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
+        std::vector<double> bn(ncol), rel(ncol, 0.0);
+        std::vector<char> active(ncol, 0);
+        Cols rho_new(ncol), rho_old(ncol, 1.0), alpha(ncol, 1.0), omega(ncol, 1.0);
+        int nact = 0;
+        for (int c = 0; c < ncol; ++c) {
+            bn[c] = std::sqrt(d[0][c].real());
+            if (!std::isfinite(bn[c])) return BRI_ENAN;
+            active[c] = bn[c] > 0.0;
+            nact += active[c];
+            rel[c] = active[c] ? 1.0 : 0.0;
+            rho_new[c] = d[0][c];
+        }
+        const bool outer = k == 0;
+        auto finish = [&](int status) {
+            if (rel_out) *rel_out = rel;
+            return status;
+        };
         it = 0;
-        rel = 0.0;
-        if (bn == 0.0) return BRI_OK;
-        if (!std::isfinite(bn)) return BRI_ENAN;
-        rel = 1.0;
-        cplx rho_new = d[0], rho_old = 1.0, alpha = 1.0, omega = 1.0;
-        while (it < L.max_iter) {
+        while (nact > 0 && it < L.max_iter) {
             ++it;
             ++L.iters;
-            const cplx beta = (rho_new / rho_old) * (alpha / omega);
-            lincomb(L.p, 1.0, L.r, beta, L.p, -beta * omega, L.v);  // p = r + beta (p - omega v)
+            Cols beta(ncol, 0.0), mbw(ncol, 0.0);
+            for (int c = 0; c < ncol; ++c)
+                if (active[c]) {
+                    beta[c] = (rho_new[c] / rho_old[c]) * (alpha[c] / omega[c]);
+                    mbw[c] = -beta[c] * omega[c];
+                }
+            // p = r + beta (p - omega v); a finished column gets p = r
+            if ((rc = lincomb(L.p, all(1.0), L.r, beta, L.p, mbw, L.v)) != BRI_OK) return rc;
             if ((rc = precondition(k, L.p, L.ph)) != BRI_OK) return rc;
             if ((rc = apply_a(L, L.ph, L.v)) != BRI_OK) return rc;  // v = A K p
             if ((rc = dots(1, L.r0, L.v, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
-            if (std::abs(d[0]) == 0.0 || !std::isfinite(d[0].real())) return k == 0 || it == 1 ? BRI_ENAN : BRI_ENOCONV;
-            alpha = rho_new / d[0];
-            lincomb(L.s, 1.0, L.r, -alpha, L.v);  // s = r - alpha v
-            if ((rc = dots(1, L.s, L.s, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
-            const double srel = std::sqrt(d[0].real()) / bn;
-            if (!std::isfinite(srel)) return BRI_ENAN;
-            if (srel <= L.tol) {
-                lincomb(x, 1.0, x, alpha, L.ph);
-                rel = srel;
-                return BRI_OK;
+            Cols ma(ncol, 0.0), half(ncol, 0.0);
+            for (int c = 0; c < ncol; ++c) {
+                if (!active[c]) continue;
+                if (std::abs(d[0][c]) == 0.0 || !std::isfinite(d[0][c].real())) {
+                    if (outer) return finish(BRI_ENAN);
+                    active[c] = 0;
+                    --nact;
+                    continue;
+                }
+                alpha[c] = rho_new[c] / d[0][c];
+                ma[c] = -alpha[c];
             }
+            if ((rc = lincomb(L.s, all(1.0), L.r, ma, L.v)) != BRI_OK) return rc;  // s = r - alpha v
+            if ((rc = dots(1, L.s, L.s, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
+            bool any_half = false;
+            for (int c = 0; c < ncol; ++c) {
+                if (!active[c]) continue;
+                const double srel = std::sqrt(d[0][c].real()) / bn[c];
+                if (!std::isfinite(srel)) return finish(BRI_ENAN);
+                if (srel <= L.tol) {  // converged half way: x += alpha K p
+                    half[c] = alpha[c];
+                    rel[c] = srel;
+                    active[c] = 0;
+                    --nact;
+                    any_half = true;
+                }
+            }
+            if (any_half && (rc = lincomb(x, all(1.0), x, half, L.ph)) != BRI_OK) return rc;
+            if (nact == 0) break;
             if ((rc = precondition(k, L.s, L.sh)) != BRI_OK) return rc;
             if ((rc = apply_a(L, L.sh, L.t)) != BRI_OK) return rc;  // t = A K s
             if ((rc = dots(2, L.t, L.s, L.t, L.t, nullptr, nullptr, d)) != BRI_OK) return rc;
-            if (d[1].real() == 0.0 || !std::isfinite(d[1].real())) return k == 0 ? BRI_ENAN : BRI_ENOCONV;
-            omega = d[0] / d[1].real();
-            lincomb(x, 1.0, x, alpha, L.ph, omega, L.sh);  // x += alpha K p + omega K s
-            lincomb(L.r, 1.0, L.s, -omega, L.t);           // r = s - omega t
+            Cols ax(ncol, 0.0), ox(ncol, 0.0), keep(ncol, 1.0), rs(ncol, 0.0), rt(ncol, 0.0);
+            for (int c = 0; c < ncol; ++c) {
+                if (!active[c]) continue;
+                if (d[1][c].real() == 0.0 || !std::isfinite(d[1][c].real())) {
+                    if (outer) return finish(BRI_ENAN);
+                    active[c] = 0;
+                    --nact;
+                    continue;
+                }
+                omega[c] = d[0][c] / d[1][c].real();
+                ax[c] = alpha[c];
+                ox[c] = omega[c];
+                keep[c] = 0.0;
+                rs[c] = 1.0;
+                rt[c] = -omega[c];
+            }
+            if ((rc = lincomb(x, all(1.0), x, ax, L.ph, ox, L.sh)) != BRI_OK) return rc;  // x += alpha Kp + omega Ks
+            if ((rc = lincomb(L.r, keep, L.r, rs, L.s, rt, L.t)) != BRI_OK) return rc;    // r = s - omega t
             rho_old = rho_new;
             if ((rc = dots(2, L.r, L.r, L.r0, L.r, nullptr, nullptr, d)) != BRI_OK) return rc;
-            rel = std::sqrt(d[0].real()) / bn;
-            rho_new = d[1];
-            if (!std::isfinite(rel)) return BRI_ENAN;
-            if (rel <= L.tol) return BRI_OK;
-            if (std::abs(omega) == 0.0 || std::abs(rho_new) == 0.0) return k == 0 ? BRI_ENAN : BRI_ENOCONV;
+            for (int c = 0; c < ncol; ++c) {
+                if (!active[c]) continue;
+                rel[c] = std::sqrt(d[0][c].real()) / bn[c];
+                rho_new[c] = d[1][c];
+                if (!std::isfinite(rel[c])) return finish(BRI_ENAN);
+                if (rel[c] <= L.tol) {
+                    active[c] = 0;
+                    --nact;
+                } else if (std::abs(omega[c]) == 0.0 || std::abs(rho_new[c]) == 0.0) {
+                    if (outer) return finish(BRI_ENAN);
+                    active[c] = 0;
+                    --nact;
+                }
+            }
         }
-        return BRI_ENOCONV;
+        return finish(nact > 0 ? BRI_ENOCONV : BRI_OK);
     }
 };
 
@@ -244,7 +327,7 @@ static int check_levels(const ov_params *prm, const ov_mass_params *mp, int npre
         if (l.kl_n < 0 || l.kl_n > BRI_MAX_SHIFTS || !(l.tol > 0.0) || l.max_iter < 1) return BRI_EINVAL;
         if (l.kl_n > 0 && !(l.ms_tol > 0.0)) return BRI_EINVAL;
         if (l.kl_n > 0 && l.inner != BRI_F64 && l.inner != BRI_F32 && l.inner != BRI_F32_BF16W) return BRI_EINVAL;
-        if (l.kl_n == 0 && k != nprec - 1) return BRI_EINVAL;  // the Brillouin level ends the chain
+        if (l.kl_n == 0 && k != nprec - 1) return BRI_EINVAL;  // the kernel level ends the chain
     }
     return BRI_OK;
 }
@@ -265,14 +348,14 @@ static ov_params level_params(const ov_params *top, const ov_level &l) {
 extern "C" {
 
 int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params,
-             const ov_mass_params *mp, int nprec, const ov_level *prec, const void *in, void *out, void *work,
-             size_t *work_bytes, ov_solve_stats *stats, void *stream) {
+             const ov_mass_params *mp, int nprec, const ov_level *prec, const void *in, void *out, int nrhs,
+             void *work, size_t *work_bytes, ov_solve_stats *stats, void *stream) {
     using namespace bri;
     const auto t0 = std::chrono::steady_clock::now();
     Geom g;
     int rc = geom_check(geom, &g);
     if (rc != BRI_OK) return rc;
-    if (!params || !mp || !work_bytes) return BRI_EINVAL;
+    if (!params || !mp || !work_bytes || nrhs < 1 || nrhs > MAXC) return BRI_EINVAL;
     if ((rc = check_levels(params, mp, nprec, prec)) != BRI_OK) return rc;
     // workspace: the largest ov_apply workspace of all levels, NVEC vectors per level, bt, partials
     size_t ovb = 0;
@@ -282,13 +365,13 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
         const ov_params p = k < 0 ? *params : level_params(params, prec[k]);
         low = low || p.inner != BRI_F64;
         size_t b = 0;
-        rc = ov_apply(geom, nullptr, nullptr, &p, nullptr, nullptr, 1, nullptr, &b, nullptr, nullptr);
+        rc = ov_apply(geom, nullptr, nullptr, &p, nullptr, nullptr, nrhs, nullptr, &b, nullptr, nullptr);
         if (rc != BRI_OK) return rc;
         ovb = b > ovb ? b : ovb;
     }
-    const size_t vb = al256((size_t)12 * g.V * sizeof(double2));
+    const size_t vb = al256((size_t)12 * g.V * sizeof(double2) * nrhs);
     const size_t nvec = (size_t)NVEC * (nprec + 1) + 1;
-    const size_t pb = al256(sizeof(double) * 2 * 3 * DOT_BLOCKS);
+    const size_t pb = al256(sizeof(double) * 2 * 3 * DOT_BLOCKS * nrhs);
     const size_t need = nvec * vb + pb + al256(ovb);
     if (!work) {
         *work_bytes = need;
@@ -306,8 +389,9 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
     const double den = 1.0 - m / (2.0 * rho);
     c.mt = m / den;
     c.n = (size_t)12 * g.V;
+    c.ncol = nrhs;
     c.s = (hipStream_t)stream;
-    c.hp.resize(2 * 3 * DOT_BLOCKS);
+    c.hp.resize((size_t)2 * 3 * DOT_BLOCKS * nrhs);
     char *base = (char *)work;
     auto take = [&](size_t b) {
         char *p = base;
@@ -341,27 +425,26 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
     double2 *x = (double2 *)out;
     Level &top = c.lev[0];
     if (mp->complete) {
-        rc = c.apply_d(top, b, top.t);
-        if (rc != BRI_OK) return rc;
-        c.lincomb(bt, (1.0 + m / (2.0 * rho)) / den, b, -m / (4.0 * rho * rho) / den, top.t);
+        if ((rc = c.apply_d(top, b, top.t)) != BRI_OK) return rc;
+        rc = c.lincomb(bt, c.all((1.0 + m / (2.0 * rho)) / den), b, c.all(-m / (4.0 * rho * rho) / den), top.t);
     } else {
-        c.lincomb(bt, 1.0 / den, b);
+        rc = c.lincomb(bt, c.all(1.0 / den), b);
     }
-    double rel = 0.0;
+    if (rc != BRI_OK) return rc;
     int it = 0;
-    const int result = c.solve(0, bt, x, rel, it);
+    const int result = c.solve(0, bt, x, it, nullptr);
     if (result != BRI_OK && result != BRI_ENOCONV) return result;
-    // true residual |bt - A x| / |bt|
+    // true residual |bt - A x| / |bt|, worst column
     double true_rel = 0.0;
     {
-        cplx d[1];
+        std::vector<Cols> d, e;
         if ((rc = c.dots(1, bt, bt, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
-        const double bn = std::sqrt(d[0].real());
-        if (bn > 0.0) {
-            if ((rc = c.apply_a(top, x, top.t)) != BRI_OK) return rc;
-            c.lincomb(top.t, 1.0, bt, -1.0, top.t);
-            if ((rc = c.dots(1, top.t, top.t, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
-            true_rel = std::sqrt(d[0].real()) / bn;
+        if ((rc = c.apply_a(top, x, top.t)) != BRI_OK) return rc;
+        if ((rc = c.lincomb(top.t, c.all(1.0), bt, c.all(-1.0), top.t)) != BRI_OK) return rc;
+        if ((rc = c.dots(1, top.t, top.t, nullptr, nullptr, nullptr, nullptr, e)) != BRI_OK) return rc;
+        for (int k = 0; k < nrhs; ++k) {
+            const double bn = std::sqrt(d[0][k].real());
+            if (bn > 0.0) true_rel = std::max(true_rel, std::sqrt(e[0][k].real()) / bn);
         }
     }
     if (stats) {

@@ -147,7 +147,7 @@ def test_massive_solve_workspace_and_invalid_args():
     assert st == bri.OK
     nb = ctypes.c_size_t(0)
     mp_ = bri._MassParams(0.1, 1, 1e-10, 100)
-    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, None, None, None,
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, None, None, 1, None,
                         ctypes.byref(nb), None, None) == bri.OK
     # the ov_apply workspace plus bt and eight BiCGstab vectors (r, r0, p, v, s, t, K p, K s) and
     # dot partials
@@ -156,19 +156,19 @@ def test_massive_solve_workspace_and_invalid_args():
     for bad in (bri._MassParams(-0.1, 1, 1e-10, 100), bri._MassParams(2.0, 1, 1e-10, 100),
                 bri._MassParams(0.1, 2, 1e-10, 100), bri._MassParams(0.1, 1, 0.0, 100),
                 bri._MassParams(0.1, 0, 1e-10, 0)):
-        assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(bad), 0, None, None, None,
+        assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(bad), 0, None, None, None, 1,
                             None, ctypes.byref(nb), None, None) == bri.EINVAL
     # bad inner parameters are rejected through the ov_apply query
     badp = bri._OvParams(0, 1.0, 1e-12, 200, 0, 0)
-    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(badp), ctypes.byref(mp_), 0, None, None, None, None,
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(badp), ctypes.byref(mp_), 0, None, None, None, 1, None,
                         ctypes.byref(nb), None, None) == bri.EINVAL
     # a workspace that is too small, or in == out, is rejected before any launch
     small = ctypes.c_size_t(nb.value - 1)
     p = ctypes.c_void_p(256)
     assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, p, ctypes.c_void_p(512),
-                        p, ctypes.byref(small), None, None) == bri.EINVAL
+                        1, p, ctypes.byref(small), None, None) == bri.EINVAL
     full = ctypes.c_size_t(nb.value)
-    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, p, p, p,
+    assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, p, p, 1, p,
                         ctypes.byref(full), None, None) == bri.EINVAL
 
 
@@ -185,7 +185,7 @@ def test_cascade_levels_validated():
         arr = (bri._Level * max(len(levels), 1))(*levels)
         nb = ctypes.c_size_t(0)
         st = lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_),
-                          len(levels) if n is None else n, arr, None, None, None, ctypes.byref(nb), None, None)
+                          len(levels) if n is None else n, arr, None, None, 1, None, ctypes.byref(nb), None, None)
         return st, nb.value
 
     st0, nb0 = query([])
@@ -209,11 +209,11 @@ def test_cascade_levels_validated():
     # a low-precision level needs Wlo: rejected at the call, before any launch
     arr = (bri._Level * 1)(bri._Level(1, 0.1, 20, 1e-5, 1))
     nb = ctypes.c_size_t(0)
-    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 1, arr, None, None, None,
-                        ctypes.byref(nb), None, None) == bri.OK
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 1, arr, None, None, 1,
+                        None, ctypes.byref(nb), None, None) == bri.OK
     p = ctypes.c_void_p(256)
     assert lib.ov_solve(ctypes.byref(g), p, None, ctypes.byref(prm), ctypes.byref(mp_), 1, arr, p,
-                        ctypes.c_void_p(512), p, ctypes.byref(nb), None, None) == bri.EINVAL
+                        ctypes.c_void_p(512), 1, p, ctypes.byref(nb), None, None) == bri.EINVAL
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 16, 32])
@@ -280,3 +280,23 @@ def test_clover_geometry_validated():
     # a lattice whose link array with the clover entries exceeds 32-bit offsets is refused
     big = bri._geom((128, 128, 80, 4), 0, 1.0)  # 360 V fits 31 bits, 432 V does not
     assert lib.bri_build_links(ctypes.byref(big), ctypes.c_void_p(256), ctypes.c_void_p(256), 0, None) == bri.EINVAL
+
+
+def test_massive_solve_nrhs_validated():
+    lib = bri.load()
+    g = bri._geom((8, 8, 8, 8))
+    prm = bri._OvParams(4, 1.0, 1e-12, 200, 0, 0)
+    mp_ = bri._MassParams(0.1, 1, 1e-10, 100)
+    sizes = []
+    for nrhs, want in ((0, bri.EINVAL), (1, bri.OK), (4, bri.OK), (bri.MAX_SOLVE_RHS, bri.OK),
+                       (bri.MAX_SOLVE_RHS + 1, bri.EINVAL)):
+        nb = ctypes.c_size_t(0)
+        assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, None, None,
+                            nrhs, None, ctypes.byref(nb), None, None) == want, nrhs
+        if want == bri.OK:
+            sizes.append((nrhs, nb.value))
+    # nine vectors per column beyond the batched ov_apply workspace
+    vec = 12 * 8**4 * 16
+    for nrhs, nbytes in sizes:
+        _, ovb = _ov_query((8, 8, 8, 8), kl_n=4, tol=1e-12, max_iter=200)
+        assert nbytes >= 9 * vec * nrhs
