@@ -231,6 +231,50 @@ CASCADE_ROWS = (
 )
 
 
+# the operator-quality comparison of Sec. 7: the f_{1,1} overlap (rho = 1) with Brillouin or Wilson
+# kernel, 1 or 3 APE steps (alpha = 0.72, the paper's), c_SW = 0 or 1, on a 16^3x32 field
+QUALITY_L = (16, 16, 16, 32)
+QUALITY_APE_ALPHA = 0.72
+
+
+def quality_table(dev):
+    """Normality and Ginsparg-Wilson defects (mean over 4 Gaussian vectors) and the locality decay
+    rate delta (mean over 2 point sources) for each kernel setting."""
+    import torch
+
+    import paper_1701_00726_amd as bri
+    import synth
+    from paper_1701_00726_amd import quality
+
+    L = QUALITY_L
+    V = int(np.prod(L))
+    rows = []
+    eta = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED + 40, nrhs=4), bri.F64, dev)
+    for ape in (1, 3):
+        U = synth.smeared_links_torch(L, LINK_EPS, LINK_SEED + 40, QUALITY_APE_ALPHA, ape, device=dev, chunk=1 << 18)
+        U = U.permute(0, 2, 3, 1).contiguous()
+        for csw in (0.0, 1.0):
+            W = bri.build_links(L, U, bri.F64, csw=csw)
+            for kname, kernel in (("brillouin", bri.KERNEL_BRILLOUIN), ("wilson", bri.KERNEL_WILSON)):
+                op = bri.OverlapOp(L, W, kl_n=1, rho=1.0, tol=1e-12, max_iter=20000, kernel=kernel, nrhs=4)
+                t0 = time.perf_counter()
+                nd = quality.normality_defect(op, eta)
+                gw = quality.gw_defect(op, eta)
+                deltas = []
+                for seed in (1, 2):
+                    r, mag = quality.locality_profile(op, L, quality.point_source(L, seed, dev))
+                    deltas.append(quality.decay_rate(r, mag, rmin=2.0, rmax=8.0))
+                torch.cuda.synchronize()
+                rows.append({"kernel": kname, "ape_steps": ape, "csw": csw, "normality": float(np.mean(nd)),
+                             "gw_defect": float(np.mean(gw)), "locality_delta": float(np.mean(deltas)),
+                             "seconds": time.perf_counter() - t0})
+                del op
+            del W
+        del U
+    return {"lattice": list(L), "operator": "f_{1,1} overlap, rho = 1", "ape_alpha": QUALITY_APE_ALPHA,
+            "rows": rows}
+
+
 def cascade_table(dev):
     """Outer BiCGstab iterations and seconds per right-hand side for f_{1,1} and f_{4,4}, without
     and with cascaded preconditioning (complete massive form), one Gaussian source."""
@@ -508,6 +552,7 @@ def main():
             "true_rel_resid_worst": st12.rel_resid}
         del x12
         extra["cascaded_16x16x16x32"] = cascade_table(dev)
+        extra["kernel_quality_16x16x16x32"] = quality_table(dev)
         best_mixed = max(extra[k]["applies_per_s"] for k in extra if k.startswith("mixed"))
         extra["fp64_1src_applies_per_s"] = value
         extra["speedup_batched_fp64_vs_fp64_1src"] = extra["batched_fp64_12src"]["applies_per_s"] / value
