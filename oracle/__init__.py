@@ -86,6 +86,7 @@ def _load():
             lib.orc_dirac_at.argtypes = [P, I, P, D, P, I, P, P]
             lib.orc_dirac_adj_at.argtypes = [P, I, P, D, P, I, P, P]
             lib.orc_link_force.argtypes = [P, I, P, I, P, P, P, P]
+            lib.orc_wilson_force.argtypes = [P, I, P, I, P, P, P, P]
             _lib = lib
     return _lib
 
@@ -347,9 +348,11 @@ def gell_mann(a: int) -> np.ndarray:
     return out.reshape(3, 3)
 
 
-def link_force(L, U: np.ndarray, tbc: int, pairs) -> np.ndarray:
+def link_force(L, U: np.ndarray, tbc: int, pairs, kernel: str = "bri") -> np.ndarray:
     """F (4, V, 8): dS/d omega^a_mu(z) at omega = 0 for U_mu(z) -> exp(i omega lambda_a / 2) U_mu(z),
-    S = Re sum_p w_p u_p^dag D_bri v_p; pairs = [(w, u, v), ...] with u, v of shape (V, 4, 3)."""
+    S = Re sum_p w_p u_p^dag D v_p with D = D_bri (kernel "bri", product rule along every path of
+    every off-axis link) or D = D_wil (kernel "wil", the two hops each link enters);
+    pairs = [(w, u, v), ...] with u, v of shape (V, 4, 3)."""
     V = volume(L)
     U = _c128(U)
     assert U.shape == (4, V, 3, 3)
@@ -357,13 +360,15 @@ def link_force(L, U: np.ndarray, tbc: int, pairs) -> np.ndarray:
     u = _c128(np.stack([np.asarray(p[1]).reshape(V, 4, 3) for p in pairs]))
     v = _c128(np.stack([np.asarray(p[2]).reshape(V, 4, 3) for p in pairs]))
     F = np.zeros((4, V, 8), dtype=np.float64)
-    _load().orc_link_force(_ptr(_geom(L)), int(tbc), _ptr(U), len(pairs), _ptr(w), _ptr(u), _ptr(v), _ptr(F))
+    fn = {"bri": _load().orc_link_force, "wil": _load().orc_wilson_force}[kernel]
+    fn(_ptr(_geom(L)), int(tbc), _ptr(U), len(pairs), _ptr(w), _ptr(u), _ptr(v), _ptr(F))
     return F
 
 
 def ov_force(L, U: np.ndarray, tbc: int, rho: float, n: int, chi: np.ndarray, psi: np.ndarray,
-             tol: float = 1e-13, maxit: int = 10000, kind: str = "diag"):
-    """Gradient of S = Re chi^dag D_ov psi, D_ov = rho (1 + X r_n(X^dag X)), X = D_bri(-rho).
+             tol: float = 1e-13, maxit: int = 10000, kind: str = "diag", kernel: str = "bri"):
+    """Gradient of S = Re chi^dag D_ov psi, D_ov = rho (1 + X r_n(X^dag X)), X = D_bri(-rho)
+    (kernel "bri") or X = D_wil(-rho) (kernel "wil").
 
     With a_i = (A + sigma_i)^{-1} psi, b_i = (A + sigma_i)^{-1} X^dag chi, A = X^dag X and
     y = c0 psi + sum_i omega_i a_i, the derivative of the partial fractions gives
@@ -372,7 +377,7 @@ def ov_force(L, U: np.ndarray, tbc: int, rho: float, n: int, chi: np.ndarray, ps
     kind selects g_{2n+1} or g_{2n} as in rational_apply.
     Returns (F (4, V, 8), grad_psi (V, 4, 3))."""
     c0, om, sg = kl_coeffs(n, kind)
-    W = links(L, U, tbc)
+    W = links(L, U, tbc) if kernel == "bri" else WilsonKernel(U, tbc)
     m0 = -rho
     xdc = dirac_adj(L, W, m0, chi)
     pairs = []
@@ -386,4 +391,4 @@ def ov_force(L, U: np.ndarray, tbc: int, rho: float, n: int, chi: np.ndarray, ps
         pairs.append((-rho * om[i], dirac(L, W, m0, a), b))
         pairs.append((-rho * om[i], dirac(L, W, m0, b), a))
     pairs.insert(0, (rho, chi, y))
-    return link_force(L, U, tbc, pairs), rho * gpsi
+    return link_force(L, U, tbc, pairs, kernel), rho * gpsi

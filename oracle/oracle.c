@@ -950,3 +950,53 @@ void orc_link_force(const int *L, int tbc, const cplx *U, int npairs, const doub
         for (long e = 0; e < 4 * V * 8; ++e) F[e] += part[(size_t)t * 4 * V * 8 + e];
     free(part);
 }
+
+/*
+ * Link force of S = Re sum_p w_p u_p^dag D_wil v_p (Sec. 9 convention: U_mu(z) -> exp(i omega^a
+ * lambda_a / 2) U_mu(z), F^a = dS/d omega^a at 0).  U_mu(z) enters two blocks: the forward hop
+ * D(z, z+mu) = S_+ (s U_mu(z)), whose colour matrix changes by i (lambda_a/2) M, and the backward
+ * hop D(z+mu, z) = S_- (s U_mu(z)^dag), whose colour matrix changes by -i M (lambda_a/2).
+ * F[mu][z][a]; u, v [npairs][V][4][3].
+ */
+void orc_wilson_force(const int *L, int tbc, const cplx *U, int npairs, const double *w, const cplx *u,
+                      const cplx *v, double *F) {
+    const long V = vol(L);
+    init_gammas();
+    init_lambdas();
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < V; ++z) {
+        for (int mu = 0; mu < 4; ++mu) {
+            cplx Sf[4][4], Mf[9], Sb[4][4], Mb[9];
+            const long zp = wilson_block(L, tbc, U, z, mu, +1, Sf, Mf);
+            wilson_block(L, tbc, U, zp, mu, -1, Sb, Mb);
+            for (int a = 0; a < 8; ++a) {
+                /* dMf = i (lambda/2) Mf ; dMb = -i Mb (lambda/2) */
+                cplx dMf[9], dMb[9];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        cplx sf = 0, sb = 0;
+                        for (int k = 0; k < 3; ++k) {
+                            sf += LAM[a][i][k] * Mf[3 * k + j];
+                            sb += Mb[3 * i + k] * LAM[a][k][j];
+                        }
+                        dMf[3 * i + j] = 0.5 * _Complex_I * sf;
+                        dMb[3 * i + j] = -0.5 * _Complex_I * sb;
+                    }
+                double acc = 0.0;
+                for (int p = 0; p < npairs; ++p) {
+                    const cplx *up = u + (size_t)p * V * 12, *vp = v + (size_t)p * V * 12;
+                    cplx sum = 0;
+                    for (int s = 0; s < 4; ++s)
+                        for (int t = 0; t < 4; ++t)
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j) {
+                                    sum += conj(up[z * 12 + 3 * s + i]) * Sf[s][t] * dMf[3 * i + j] * vp[zp * 12 + 3 * t + j];
+                                    sum += conj(up[zp * 12 + 3 * s + i]) * Sb[s][t] * dMb[3 * i + j] * vp[z * 12 + 3 * t + j];
+                                }
+                    acc += w[p] * creal(sum);
+                }
+                F[((size_t)mu * V + z) * 8 + a] = acc;
+            }
+        }
+    }
+}

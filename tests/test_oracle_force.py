@@ -146,3 +146,51 @@ def test_overlap_force_matches_dense_finite_differences():
     Dov = rho * (np.eye(12 * V) + d.G5[:, None] * G)
     ref = Dov.conj().T @ chi.ravel()
     assert np.linalg.norm(gpsi.ravel() - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("tbc", [0, 1])
+def test_wilson_link_force_matches_finite_differences(tbc):
+    """The Wilson force (the two hops every link enters) against five-point differences of
+    Re sum_p w_p u_p^dag D_wil v_p, t-boundary links included."""
+    L = (3, 3, 3, 4)
+    V = int(np.prod(L))
+    U = synth.random_links(L, 0.5, 41 + tbc)
+    rng = np.random.default_rng(17 + tbc)
+    pairs = [(0.7, _rand_spinor(rng, V), _rand_spinor(rng, V)), (-1.3, _rand_spinor(rng, V), _rand_spinor(rng, V))]
+    m0 = -1.0
+    F = oracle.link_force(L, U, tbc, pairs, kernel="wil")
+
+    def S(Uw):
+        K = oracle.WilsonKernel(Uw, tbc)
+        return sum(w * np.vdot(u.ravel(), oracle.dirac(L, K, m0, v).ravel()).real for w, u, v in pairs)
+
+    scale = np.abs(F).max()
+    for mu, z, a in _samples(L, rng, 10):
+        fd = _fd5(S, U, mu, z, a, 1e-3)
+        assert abs(fd - F[mu, z, a]) <= 1e-9 * scale, (mu, z, a, fd, F[mu, z, a])
+
+
+def test_wilson_overlap_force_matches_dense_finite_differences():
+    L = (2, 2, 3, 4)
+    V = int(np.prod(L))
+    rho, n = 1.0, 4
+    U = synth.random_links(L, 0.3, 29)
+    rng = np.random.default_rng(23)
+    chi = _rand_spinor(rng, V)
+    psi = _rand_spinor(rng, V)
+    F, gpsi = oracle.ov_force(L, U, 1, rho, n, chi, psi, tol=1e-14, kernel="wil")
+
+    def dov(Uw):
+        return odense.DenseOverlap(oracle.dense_matrix(L, oracle.WilsonKernel(Uw, 1), -rho), V, rho)
+
+    def S(Uw):
+        return np.vdot(chi.ravel(), dov(Uw).ov_apply(n, psi.ravel())).real
+
+    scale = np.abs(F).max()
+    for mu, z, a in _samples(L, rng, 6):
+        fd = _fd5(S, U, mu, z, a, 1e-3)
+        assert abs(fd - F[mu, z, a]) <= 1e-8 * scale, (mu, z, a, fd, F[mu, z, a])
+    d = dov(U)
+    G = d.fn_of_H(lambda lam: lam * oracle.kl.r_diag_f64(lam * lam, n))
+    Dov = rho * (np.eye(12 * V) + d.G5[:, None] * G)
+    assert np.linalg.norm(gpsi.ravel() - Dov.conj().T @ chi.ravel()) <= 1e-11 * np.linalg.norm(gpsi)
