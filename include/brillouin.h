@@ -345,6 +345,12 @@ int bri_kl_upper_coeffs(int n, double *omega, double *sigma);
 int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
                   const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream);
 
+/* wil_link_grad -- the same force for S = Re sum_p w_p u_p^dag D_wil v_p (eq. (def_wils)): each
+ * link U_mu(z) enters the hops z -> z+mu and z+mu -> z.  W is the link array of bri_build_links
+ * (only its one-hop slabs are read); arguments, workspace and errors as bri_link_grad. */
+int wil_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
+                  const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream);
+
 /*
  * ov_apply_grad -- gradient of S = Re chi^dag D_ov psi (one right-hand side),
  * D_ov = rho (1 + X r_n(A)), with the fixed-order rational of eq.

@@ -193,6 +193,7 @@ def load():
             lib.bri_set_solver_graphs.argtypes = [I]
             SZ = ctypes.POINTER(ctypes.c_size_t)
             lib.bri_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
+            lib.wil_link_grad.argtypes = [G, P, P, I, ctypes.POINTER(D), P, P, P, P, P, SZ, P]
             lib.bri_kl_upper_coeffs.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D)]
             lib.ov_solve.argtypes = [G, P, P, ctypes.POINTER(_OvParams), ctypes.POINTER(_MassParams), I,
                                      ctypes.POINTER(_Level), P, P, I, P, SZ, ctypes.POINTER(_SolveStats), P]
@@ -218,6 +219,7 @@ EXPORTS = (
     "bri_set_stencil_cfg",
     "bri_get_stencil_cfg",
     "bri_link_grad",
+    "wil_link_grad",
     "ov_apply_grad",
     "ov_solve",
     "bri_kl_upper_coeffs",
@@ -606,8 +608,9 @@ def set_stencil_cfg(L, prec, nrhs, cfg):
 # -------------------------------------------------------------- differentiation
 
 
-def link_grad(L, U, W, pairs, tbc=0, force=True, link_grad=False, stream=None):
-    """Gradient of S = Re sum_p w_p u_p^dag D_bri v_p with respect to the links.
+def link_grad(L, U, W, pairs, tbc=0, force=True, link_grad=False, stream=None, kernel=KERNEL_BRILLOUIN):
+    """Gradient of S = Re sum_p w_p u_p^dag D v_p with respect to the links, D = D_bri (or
+    D_wil for kernel = KERNEL_WILSON).
 
     pairs = [(w, u, v), ...] with u, v complex128 tensors of 12 V elements in the
     (4, 3, V) spinor layout; W the FP64 off-axis links built from U with `tbc`.
@@ -631,12 +634,14 @@ def link_grad(L, U, W, pairs, tbc=0, force=True, link_grad=False, stream=None):
     g = _geom(L, tbc)
     nb = ctypes.c_size_t(0)
     lib = load()
-    _check("bri_link_grad", lib.bri_link_grad(ctypes.byref(g), None, None, len(pairs), w, None, None, None, None, None,
+    fname = "wil_link_grad" if kernel == KERNEL_WILSON else "bri_link_grad"
+    fn = getattr(lib, fname)
+    _check(fname, fn(ctypes.byref(g), None, None, len(pairs), w, None, None, None, None, None,
                                               ctypes.byref(nb), None))
     work = torch.empty(int(nb.value), dtype=torch.uint8, device=U.device)
     F = torch.empty((4, 8, V), dtype=torch.float64, device=U.device) if force else None
     GU = torch.empty_like(U) if link_grad else None
-    _check("bri_link_grad", lib.bri_link_grad(ctypes.byref(g), _dptr(U), _dptr(W), len(pairs), w, _dptr(uu),
+    _check(fname, fn(ctypes.byref(g), _dptr(U), _dptr(W), len(pairs), w, _dptr(uu),
                                               _dptr(vv), None if F is None else _dptr(F),
                                               None if GU is None else _dptr(GU), _dptr(work), ctypes.byref(nb),
                                               _stream(stream)))

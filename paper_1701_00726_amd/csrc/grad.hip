@@ -117,16 +117,31 @@ struct PairTable {
 // each wave keeps the 3x3 accumulators of 2 displacements in registers while the pairs stream
 // through, so u_p(x) and the neighbourhood of v_p are read while hot in L2 (a pass per
 // displacement would stream every pair from HBM 80 times).
+// The Wilson operator has only the 8 one-hop displacements (one group), with its own weights.
 constexpr int OUTER_WAVES = 4;
 constexpr int OUTER_PER_WAVE = 2;
-constexpr int OUTER_GROUPS = 80 / (OUTER_WAVES * OUTER_PER_WAVE);
+template <int KIND> struct OuterDisp {
+    static constexpr int n = KIND == KERN_WIL ? 8 : 80;
+    static constexpr int groups = n / (OUTER_WAVES * OUTER_PER_WAVE);
+    // displacement index of the jj-th displacement (the centre j = 40 is skipped)
+    __device__ __forceinline__ static int at(int jj) {
+        if constexpr (KIND == KERN_WIL) {
+            const int half = jj < 4 ? jj : 7 - jj;  // 13, 31, 37, 39 and their opposites 67, 49, 43, 41
+            const int j = 40 - (half == 0 ? 27 : half == 1 ? 9 : half == 2 ? 3 : 1);
+            return jj < 4 ? j : 80 - j;
+        }
+        return jj < 40 ? jj : jj + 1;
+    }
+};
 
+template <int KIND>
 __global__ __launch_bounds__(64 * OUTER_WAVES) void grad_outer_kernel(Geom g, PairTable pt,
                                                                       double2 *__restrict__ G) {
+    constexpr int GROUPS = OuterDisp<KIND>::groups;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const unsigned grp = blockIdx.x % OUTER_GROUPS;
-    const unsigned x = (blockIdx.x / OUTER_GROUPS) * 64 + lane;
+    const unsigned grp = blockIdx.x % GROUPS;
+    const unsigned x = (blockIdx.x / GROUPS) * 64 + lane;
     const bool live = x < (unsigned)g.V;
     const size_t V = (size_t)g.V;
     const int jbase = (grp * OUTER_WAVES + w) * OUTER_PER_WAVE;
@@ -141,8 +156,7 @@ __global__ __launch_bounds__(64 * OUTER_WAVES) void grad_outer_kernel(Geom g, Pa
     unsigned ys[OUTER_PER_WAVE];
 #pragma unroll
     for (int i = 0; i < OUTER_PER_WAVE; ++i) {
-        const int jj = jbase + i;
-        const int j = jj < 40 ? jj : jj + 1;
+        const int j = OuterDisp<KIND>::at(jbase + i);
         int cy[4];
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) cy[mu] = wrapc(cx[mu] + dj(j, mu), g.L[mu]);
@@ -170,8 +184,7 @@ __global__ __launch_bounds__(64 * OUTER_WAVES) void grad_outer_kernel(Geom g, Pa
             }
 #pragma unroll
         for (int i = 0; i < OUTER_PER_WAVE; ++i) {
-            const int jj = jbase + i;
-            const DirW<double, false> dw(jj < 40 ? jj : jj + 1);  // S_d = a_k + c_k sum d_mu gamma_mu
+            const DirW<double, false, KIND> dw(OuterDisp<KIND>::at(jbase + i));  // S_d of the kernel
             double2 e[4][3];
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -196,8 +209,7 @@ __global__ __launch_bounds__(64 * OUTER_WAVES) void grad_outer_kernel(Geom g, Pa
     }
 #pragma unroll
     for (int i = 0; i < OUTER_PER_WAVE; ++i) {
-        const int jj = jbase + i;
-        const int j = jj < 40 ? jj : jj + 1;
+        const int j = OuterDisp<KIND>::at(jbase + i);
 #pragma unroll
         for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
@@ -267,9 +279,11 @@ __global__ __launch_bounds__(128) void grad_level_kernel(Geom g, const double2 *
 }
 
 // G_U_mu(z) from every level's first step, then F^a_mu(z) = -Im tr(lambda_a U G_U^T) / 2
+// (kind = KERN_WIL: only the one-hop displacements carry a coefficient, and their remainder link
+// is the identity)
 __global__ __launch_bounds__(128) void grad_force_kernel(Geom g, const double2 *__restrict__ U,
                                                          const double2 *__restrict__ W, const double2 *__restrict__ G,
-                                                         double *__restrict__ F, double2 *__restrict__ GUo) {
+                                                         double *__restrict__ F, double2 *__restrict__ GUo, int kind) {
     const unsigned z = (blockIdx.x >> 2) * blockDim.x + threadIdx.x;
     if (z >= (unsigned)g.V) return;
     const size_t V = (size_t)g.V;
@@ -299,6 +313,7 @@ __global__ __launch_bounds__(128) void grad_force_kernel(Geom g, const double2 *
             if (dmu == 0) continue;
             int k = 0;
             for (int nu = 0; nu < 4; ++nu) k += dj(jd, nu) != 0;
+            if (kind == KERN_WIL && k != 1) continue;
             const double invk = 1.0 / (double)k;
             double2 Gd[3][3], Wr[3][3];
             if (dmu > 0) {
@@ -395,11 +410,19 @@ static inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 static size_t grad_g_bytes(const Geom &g) { return al256((size_t)81 * 9 * g.V * sizeof(double2)); }
 
 static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, const PairTable &pt, double2 *G,
-                            double *F, double2 *GU, hipStream_t s) {
+                            double *F, double2 *GU, hipStream_t s, int kind) {
     const int threads = 128;
     const int blocks = (g.V + threads - 1) / threads;
-    hipLaunchKernelGGL(grad_outer_kernel, dim3(OUTER_GROUPS * ((g.V + 63) / 64)), dim3(64 * OUTER_WAVES), 0, s, g,
-                       pt, G);
+    const int tiles = (g.V + 63) / 64;
+    if (kind == KERN_WIL) {
+        // one-hop displacements only: no pull-back through the path average
+        hipLaunchKernelGGL(grad_outer_kernel<KERN_WIL>, dim3(OuterDisp<KERN_WIL>::groups * tiles),
+                           dim3(64 * OUTER_WAVES), 0, s, g, pt, G);
+        hipLaunchKernelGGL(grad_force_kernel, dim3(4 * blocks), dim3(threads), 0, s, g, U, W, G, F, GU, kind);
+        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+    }
+    hipLaunchKernelGGL(grad_outer_kernel<KERN_BRI>, dim3(OuterDisp<KERN_BRI>::groups * tiles), dim3(64 * OUTER_WAVES),
+                       0, s, g, pt, G);
     for (int k = 4; k >= 2; --k) {
         HopDirs lower{};
         for (int j = 0; j < 81; ++j) {
@@ -409,7 +432,7 @@ static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, c
         }
         hipLaunchKernelGGL(grad_level_kernel, dim3(lower.n * blocks), dim3(threads), 0, s, g, U, G, k, lower);
     }
-    hipLaunchKernelGGL(grad_force_kernel, dim3(4 * blocks), dim3(threads), 0, s, g, U, W, G, F, GU);
+    hipLaunchKernelGGL(grad_force_kernel, dim3(4 * blocks), dim3(threads), 0, s, g, U, W, G, F, GU, kind);
     return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
 }
 
@@ -449,8 +472,9 @@ static int plan_grad(const Geom &g, const ov_params *prm, GradPlan &pl) {
 
 extern "C" {
 
-int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
-                  const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream) {
+static int link_grad_impl(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
+                          const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes,
+                          void *stream, int kind) {
     using namespace bri;
     Geom g;
     int rc = geom_check(geom, &g);
@@ -473,7 +497,17 @@ int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs
         pt.w[p] = weights[p];
     }
     return force_from_pairs(g, (const double2 *)U, (const double2 *)W, pt, (double2 *)work, (double *)F,
-                            (double2 *)GU, (hipStream_t)stream);
+                            (double2 *)GU, (hipStream_t)stream, kind);
+}
+
+int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
+                  const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream) {
+    return link_grad_impl(geom, U, W, npairs, weights, u, v, F, GU, work, work_bytes, stream, bri::KERN_BRI);
+}
+
+int wil_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
+                  const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream) {
+    return link_grad_impl(geom, U, W, npairs, weights, u, v, F, GU, work, work_bytes, stream, bri::KERN_WIL);
 }
 
 int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const void *Wlo, const ov_params *prm,
@@ -487,7 +521,6 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     if (!prm || !work_bytes || g.csw != 0.0) return BRI_EINVAL;
     const int n = prm->kl_n;
     if (!params_ok(prm) || g.V % 64) return BRI_EINVAL;
-    if (prm->kernel != BRI_KERNEL_BRILLOUIN) return BRI_EINVAL;  // the force pulls back through W's paths
     GradPlan pl;
     rc = plan_grad(g, prm, pl);
     if (rc != BRI_OK) return rc;
@@ -517,8 +550,9 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     a.ncol = 1;
     a.in = chi;
     a.out = BIN + nel;
-    a.diag = 15.0 / 8.0 + m0;
-    rc = stencil_launch(a, BRI_F64, true, EPI_PLAIN, default_config(g, BRI_F64, 1), s);
+    a.kind = prm->kernel;
+    a.diag = kernel_diag(prm->kernel) + m0;
+    rc = stencil_launch(a, BRI_F64, true, EPI_PLAIN, default_config(g, BRI_F64, 1, prm->kernel), s);
     if (rc != BRI_OK) return rc;
     // a_i = (A + sigma_i)^{-1} psi and b_i = (A + sigma_i)^{-1} X^dag chi in one two-column multi-shift
     // solve; X holds them as [i][2][12 V], i.e. a_i = X[2 i], b_i = X[2 i + 1]
@@ -542,7 +576,7 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     ax.ncol = 2 * n;
     ax.in = X;
     ax.out = XAB;
-    rc = stencil_launch(ax, BRI_F64, false, EPI_PLAIN, default_config(g, BRI_F64, 2 * n), s);
+    rc = stencil_launch(ax, BRI_F64, false, EPI_PLAIN, default_config(g, BRI_F64, 2 * n, prm->kernel), s);
     if (rc != BRI_OK) return rc;
     PairTable pt;
     std::memset(&pt, 0, sizeof(pt));
@@ -559,7 +593,8 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
         pt.v[2 + 2 * i] = X + (size_t)(2 * i) * nel;
         pt.w[2 + 2 * i] = -prm->rho * om[i];
     }
-    rc = force_from_pairs(g, (const double2 *)U, (const double2 *)W64, pt, G, (double *)F, (double2 *)GU, s);
+    rc = force_from_pairs(g, (const double2 *)U, (const double2 *)W64, pt, G, (double *)F, (double2 *)GU, s,
+                          prm->kernel);
     if (rc != BRI_OK) return rc;
     if (hipStreamSynchronize(s) != hipSuccess) return BRI_EHIP;
     if (stats) {

@@ -170,3 +170,50 @@ def test_wilson_massive_solve_against_dense(levels):
     op = _wop(L, U, n)
     x, st = op.solve(bri.spinor_to_device(b[None]), m, complete=True, tol=1e-11, prec=levels)
     assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-9, (st.iters, st.level_iters)
+
+
+# ------------------------------------------------------------------------- gradient
+
+
+def _rand_spinor(rng, V):
+    return rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3))
+
+
+def _dev(psi):
+    return bri.spinor_to_device(psi[None])[0]
+
+
+def _force_host(F):
+    return np.ascontiguousarray(np.transpose(F.detach().cpu().numpy(), (0, 2, 1)))
+
+
+@pytest.mark.parametrize("tbc", [0, 1])
+def test_wilson_link_force(tbc):
+    need_gpu()
+    L = (4, 4, 4, 4)
+    U, _ = field(L, "rough", tbc)
+    rng = np.random.default_rng(51 + tbc)
+    pairs = [(0.9, _rand_spinor(rng, 256), _rand_spinor(rng, 256)), (-0.4, _rand_spinor(rng, 256),
+                                                                       _rand_spinor(rng, 256))]
+    ref = oracle.link_force(L, U, tbc, pairs, kernel="wil")
+    Ud = bri.links_to_device(U)
+    W = bri.build_links(L, Ud, bri.F64, tbc=tbc)
+    F, _ = bri.link_grad(L, Ud, W, [(w, _dev(u), _dev(v)) for w, u, v in pairs], tbc=tbc,
+                         kernel=bri.KERNEL_WILSON)
+    assert np.abs(_force_host(F) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("tbc", [0, 1])
+def test_wilson_overlap_gradient(tbc):
+    need_gpu()
+    L = (4, 4, 4, 4)
+    U, _ = field(L, "cfg1", tbc)
+    rng = np.random.default_rng(61 + tbc)
+    chi, psi = _rand_spinor(rng, 256), _rand_spinor(rng, 256)
+    n = 5
+    Fref, gref = oracle.ov_force(L, U, tbc, 1.0, n, chi, psi, tol=1e-13, kernel="wil")
+    Ud = bri.links_to_device(U)
+    op = _wop(L, U, n, tbc=tbc)
+    F, _, gpsi, st = op.grad(Ud, _dev(chi), _dev(psi))
+    assert np.abs(_force_host(F) - Fref).max() <= 1e-9 * np.abs(Fref).max(), st.shift_iters
+    assert rel_l2(bri.spinor_to_host(gpsi[None])[0], gref) < 1e-10
