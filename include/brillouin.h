@@ -215,7 +215,10 @@ typedef struct {
     double tol;    /* stop of this level's BiCGstab, relative to the vector it is applied to   */
     int max_iter;  /* iteration cap of this level's BiCGstab, per application                  */
     double ms_tol; /* multi-shift CG tolerance of this level's overlap applies (kl_n > 0)       */
-    int inner;     /* bri_prec of this level's multi-shift (kl_n > 0); low precision needs Wlo  */
+    int inner;     /* bri_prec of this level's multi-shift (kl_n > 0) or of its kernel stencil
+                      (kl_n = 0: vectors narrowed to complex float around each apply); low
+                      precision reads Wlo, so every low-precision level must name Wlo's
+                      precision                                                           */
 } ov_level;
 
 typedef struct {

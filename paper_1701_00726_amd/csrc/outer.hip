@@ -97,6 +97,35 @@ __global__ void outer_lincomb_kernel(size_t n, double2 *out, Coef3 cf, const dou
     }
 }
 
+// Column maps of the kernel level: only the columns still iterating go through its stencil.
+struct ColMap {
+    int idx[MAXC];
+};
+
+template <typename T> __device__ __forceinline__ T conv(double2 v);
+template <> __device__ __forceinline__ double2 conv<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 conv<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
+// out column k = in column map.idx[k] (k = blockIdx.y), converted to T (complex float narrows)
+template <typename T>
+__global__ void outer_gather_kernel(size_t n, ColMap map, const double2 *__restrict__ in, T *__restrict__ out) {
+    const double2 *src = in + (size_t)map.idx[blockIdx.y] * n;
+    T *dst = out + (size_t)blockIdx.y * n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = conv<T>(src[i]);
+}
+
+// out column c = scale * in column inv.idx[c], or zero where inv.idx[c] < 0 (c = blockIdx.y)
+template <typename T>
+__global__ void outer_scatter_kernel(size_t n, ColMap inv, double scale, const T *__restrict__ in,
+                                     double2 *__restrict__ out) {
+    const int k = inv.idx[blockIdx.y];
+    double2 *dst = out + (size_t)blockIdx.y * n;
+    const T *src = in + (size_t)(k < 0 ? 0 : k) * n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = k < 0 ? make_double2(0.0, 0.0) : make_double2(scale * (double)src[i].x, scale * (double)src[i].y);
+}
+
 static inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 using Cols = std::vector<cplx>;  // one coefficient per column
@@ -107,6 +136,7 @@ struct Level {
     ov_params prm;  // overlap apply parameters (kl_n > 0)
     double tol;
     int max_iter;
+    int kprec;  // kernel level: precision of its stencil (BRI_F64, or BRI_F32 / BRI_F32_BF16W on Wlo)
     double2 *r, *r0, *p, *v, *s, *t, *ph, *sh;  // [ncol][12 V] each
     int iters = 0, calls = 0, applies = 0;
 };
@@ -122,6 +152,8 @@ struct Cascade {
     hipStream_t s;
     void *ov;
     size_t ov_bytes;
+    float2 *lo_in = nullptr, *lo_out = nullptr;  // low-precision kernel level: [ncol][12 V] each
+    double2 *k_in = nullptr, *k_out = nullptr;   // FP64 kernel level, compacted columns
     double *partial;
     std::vector<double> hp;
     std::vector<Level> lev;
@@ -166,15 +198,45 @@ struct Cascade {
         return BRI_OK;
     }
 
-    // dst = D_ov^(n_k) v (kl_n > 0) or rho D_kernel(-rho) v (kl_n = 0), all columns; dst != v
-    int apply_d(Level &L, const double2 *v, double2 *dst) {
+    // dst = D_ov^(n_k) v (kl_n > 0) or rho D_kernel(-rho) v (kl_n = 0); dst != v.  Columns outside
+    // `act` are zero in v and come out zero: the multi-shift drops zero columns at its start, and
+    // the kernel level applies its stencil to the active columns only (gathered, in the level's
+    // precision, and scattered back).
+    int apply_d(Level &L, const double2 *v, double2 *dst, const std::vector<char> &act) {
         ++L.applies;
         if (L.kl_n == 0) {
-            const int r = L.prm.kernel == BRI_KERNEL_WILSON
-                              ? ::wil_apply(geom, W64, BRI_F64, -rho, v, dst, ncol, s)
-                              : ::bri_apply(geom, W64, BRI_F64, -rho, v, dst, ncol, s);
+            const bool wil = L.prm.kernel == BRI_KERNEL_WILSON;
+            ColMap map{}, inv{};
+            int k = 0;
+            for (int c = 0; c < ncol; ++c) {
+                inv.idx[c] = act[c] ? k : -1;
+                if (act[c]) map.idx[k++] = c;
+            }
+            if (k == 0) return lincomb(dst, all(0.0), nullptr);
+            const bool lo = L.kprec != BRI_F64;
+            if (!lo && k == ncol) {  // every column active: no compaction
+                const int r = wil ? ::wil_apply(geom, W64, BRI_F64, -rho, v, dst, ncol, s)
+                                  : ::bri_apply(geom, W64, BRI_F64, -rho, v, dst, ncol, s);
+                if (r != BRI_OK) return r;
+                return lincomb(dst, all(rho), dst);
+            }
+            if (lo)
+                hipLaunchKernelGGL(outer_gather_kernel<float2>, dim3(1024, k), dim3(256), 0, s, n, map, v, lo_in);
+            else
+                hipLaunchKernelGGL(outer_gather_kernel<double2>, dim3(1024, k), dim3(256), 0, s, n, map, v, k_in);
+            const void *Wk = lo ? Wlo : W64;
+            const void *in_k = lo ? (const void *)lo_in : (const void *)k_in;
+            void *out_k = lo ? (void *)lo_out : (void *)k_out;
+            const int r = wil ? ::wil_apply(geom, Wk, L.kprec, -rho, in_k, out_k, k, s)
+                              : ::bri_apply(geom, Wk, L.kprec, -rho, in_k, out_k, k, s);
             if (r != BRI_OK) return r;
-            return lincomb(dst, all(rho), dst);
+            if (lo)
+                hipLaunchKernelGGL(outer_scatter_kernel<float2>, dim3(1024, ncol), dim3(256), 0, s, n, inv, rho,
+                                   lo_out, dst);
+            else
+                hipLaunchKernelGGL(outer_scatter_kernel<double2>, dim3(1024, ncol), dim3(256), 0, s, n, inv, rho,
+                                   k_out, dst);
+            return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
         }
         size_t ob = ov_bytes;
         const int r = ::ov_apply(geom, W64, Wlo, &L.prm, v, dst, ncol, ov, &ob, &ist, s);
@@ -184,8 +246,8 @@ struct Cascade {
     }
 
     // dst = A_k v
-    int apply_a(Level &L, const double2 *v, double2 *dst) {
-        const int r = apply_d(L, v, dst);
+    int apply_a(Level &L, const double2 *v, double2 *dst, const std::vector<char> &act) {
+        const int r = apply_d(L, v, dst, act);
         if (r != BRI_OK) return r;
         return lincomb(dst, all(1.0), dst, all(L.kl_n == 0 ? rho + mt : mt), v);
     }
@@ -241,9 +303,12 @@ struct Cascade {
                     mbw[c] = -beta[c] * omega[c];
                 }
             // p = r + beta (p - omega v); a finished column gets p = r
-            if ((rc = lincomb(L.p, all(1.0), L.r, beta, L.p, mbw, L.v)) != BRI_OK) return rc;
+            // finished columns get p = 0, so the inner solves and the multi-shift skip them
+            Cols one_act(ncol, 0.0);
+            for (int c = 0; c < ncol; ++c) one_act[c] = active[c] ? 1.0 : 0.0;
+            if ((rc = lincomb(L.p, one_act, L.r, beta, L.p, mbw, L.v)) != BRI_OK) return rc;
             if ((rc = precondition(k, L.p, L.ph)) != BRI_OK) return rc;
-            if ((rc = apply_a(L, L.ph, L.v)) != BRI_OK) return rc;  // v = A K p
+            if ((rc = apply_a(L, L.ph, L.v, active)) != BRI_OK) return rc;  // v = A K p
             if ((rc = dots(1, L.r0, L.v, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
             Cols ma(ncol, 0.0), half(ncol, 0.0);
             for (int c = 0; c < ncol; ++c) {
@@ -257,7 +322,8 @@ struct Cascade {
                 alpha[c] = rho_new[c] / d[0][c];
                 ma[c] = -alpha[c];
             }
-            if ((rc = lincomb(L.s, all(1.0), L.r, ma, L.v)) != BRI_OK) return rc;  // s = r - alpha v
+            for (int c = 0; c < ncol; ++c) one_act[c] = active[c] ? 1.0 : 0.0;
+            if ((rc = lincomb(L.s, one_act, L.r, ma, L.v)) != BRI_OK) return rc;  // s = r - alpha v
             if ((rc = dots(1, L.s, L.s, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
             bool any_half = false;
             for (int c = 0; c < ncol; ++c) {
@@ -274,8 +340,12 @@ struct Cascade {
             }
             if (any_half && (rc = lincomb(x, all(1.0), x, half, L.ph)) != BRI_OK) return rc;
             if (nact == 0) break;
+            if (any_half) {  // the columns that just finished leave s as well
+                for (int c = 0; c < ncol; ++c) one_act[c] = active[c] ? 1.0 : 0.0;
+                if ((rc = lincomb(L.s, one_act, L.s)) != BRI_OK) return rc;
+            }
             if ((rc = precondition(k, L.s, L.sh)) != BRI_OK) return rc;
-            if ((rc = apply_a(L, L.sh, L.t)) != BRI_OK) return rc;  // t = A K s
+            if ((rc = apply_a(L, L.sh, L.t, active)) != BRI_OK) return rc;  // t = A K s
             if ((rc = dots(2, L.t, L.s, L.t, L.t, nullptr, nullptr, d)) != BRI_OK) return rc;
             Cols ax(ncol, 0.0), ox(ncol, 0.0), keep(ncol, 1.0), rs(ncol, 0.0), rt(ncol, 0.0);
             for (int c = 0; c < ncol; ++c) {
@@ -326,7 +396,7 @@ static int check_levels(const ov_params *prm, const ov_mass_params *mp, int npre
         const ov_level &l = prec[k];
         if (l.kl_n < 0 || l.kl_n > BRI_MAX_SHIFTS || !(l.tol > 0.0) || l.max_iter < 1) return BRI_EINVAL;
         if (l.kl_n > 0 && !(l.ms_tol > 0.0)) return BRI_EINVAL;
-        if (l.kl_n > 0 && l.inner != BRI_F64 && l.inner != BRI_F32 && l.inner != BRI_F32_BF16W) return BRI_EINVAL;
+        if (l.inner != BRI_F64 && l.inner != BRI_F32 && l.inner != BRI_F32_BF16W) return BRI_EINVAL;
         if (l.kl_n == 0 && k != nprec - 1) return BRI_EINVAL;  // the kernel level ends the chain
     }
     return BRI_OK;
@@ -357,6 +427,15 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
     if (rc != BRI_OK) return rc;
     if (!params || !mp || !work_bytes || nrhs < 1 || nrhs > MAXC) return BRI_EINVAL;
     if ((rc = check_levels(params, mp, nprec, prec)) != BRI_OK) return rc;
+    // every low-precision piece reads the one array Wlo, so they must agree on its precision
+    int lo_prec = params->inner != BRI_F64 ? params->inner : -1;
+    bool lo_kernel = false;
+    for (int k = 0; k < nprec; ++k) {
+        if (prec[k].inner == BRI_F64) continue;
+        if (lo_prec >= 0 && prec[k].inner != lo_prec) return BRI_EINVAL;
+        lo_prec = prec[k].inner;
+        lo_kernel = lo_kernel || prec[k].kl_n == 0;
+    }
     // workspace: the largest ov_apply workspace of all levels, NVEC vectors per level, bt, partials
     size_t ovb = 0;
     bool low = false;
@@ -372,12 +451,16 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
     const size_t vb = al256((size_t)12 * g.V * sizeof(double2) * nrhs);
     const size_t nvec = (size_t)NVEC * (nprec + 1) + 1;
     const size_t pb = al256(sizeof(double) * 2 * 3 * DOT_BLOCKS * nrhs);
-    const size_t need = nvec * vb + pb + al256(ovb);
+    bool f64_kernel = false;
+    for (int k = 0; k < nprec; ++k) f64_kernel = f64_kernel || (prec[k].kl_n == 0 && prec[k].inner == BRI_F64);
+    const size_t lb = lo_kernel ? al256((size_t)12 * g.V * sizeof(float2) * nrhs) : 0;
+    const size_t kb = f64_kernel ? vb : 0;
+    const size_t need = nvec * vb + pb + al256(ovb) + 2 * lb + 2 * kb;
     if (!work) {
         *work_bytes = need;
         return BRI_OK;
     }
-    if (*work_bytes < need || !W64 || !in || !out || in == out || (low && !Wlo)) return BRI_EINVAL;
+    if (*work_bytes < need || !W64 || !in || !out || in == out || ((low || lo_kernel) && !Wlo)) return BRI_EINVAL;
 
     Cascade c;
     c.geom = geom;
@@ -407,11 +490,13 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
             L.prm = *params;
             L.tol = mp->tol;
             L.max_iter = mp->max_iter;
+            L.kprec = BRI_F64;
         } else {
             L.kl_n = prec[k - 1].kl_n;
             L.prm = level_params(params, prec[k - 1]);
             L.tol = prec[k - 1].tol;
             L.max_iter = prec[k - 1].max_iter;
+            L.kprec = prec[k - 1].kl_n == 0 ? prec[k - 1].inner : BRI_F64;
         }
         double2 **vs[NVEC] = {&L.r, &L.r0, &L.p, &L.v, &L.s, &L.t, &L.ph, &L.sh};
         for (auto vp : vs) *vp = (double2 *)take(vb);
@@ -419,13 +504,22 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
     c.partial = (double *)take(pb);
     c.ov = take(al256(ovb));
     c.ov_bytes = ovb;
+    if (lo_kernel) {
+        c.lo_in = (float2 *)take(lb);
+        c.lo_out = (float2 *)take(lb);
+    }
+    if (f64_kernel) {
+        c.k_in = (double2 *)take(kb);
+        c.k_out = (double2 *)take(kb);
+    }
 
     // bt
     const double2 *b = (const double2 *)in;
     double2 *x = (double2 *)out;
     Level &top = c.lev[0];
+    const std::vector<char> every(nrhs, 1);
     if (mp->complete) {
-        if ((rc = c.apply_d(top, b, top.t)) != BRI_OK) return rc;
+        if ((rc = c.apply_d(top, b, top.t, every)) != BRI_OK) return rc;
         rc = c.lincomb(bt, c.all((1.0 + m / (2.0 * rho)) / den), b, c.all(-m / (4.0 * rho * rho) / den), top.t);
     } else {
         rc = c.lincomb(bt, c.all(1.0 / den), b);
@@ -439,7 +533,7 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
     {
         std::vector<Cols> d, e;
         if ((rc = c.dots(1, bt, bt, nullptr, nullptr, nullptr, nullptr, d)) != BRI_OK) return rc;
-        if ((rc = c.apply_a(top, x, top.t)) != BRI_OK) return rc;
+        if ((rc = c.apply_a(top, x, top.t, every)) != BRI_OK) return rc;
         if ((rc = c.lincomb(top.t, c.all(1.0), bt, c.all(-1.0), top.t)) != BRI_OK) return rc;
         if ((rc = c.dots(1, top.t, top.t, nullptr, nullptr, nullptr, nullptr, e)) != BRI_OK) return rc;
         for (int k = 0; k < nrhs; ++k) {

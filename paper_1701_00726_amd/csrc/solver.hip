@@ -529,6 +529,23 @@ static int graph_for(const std::vector<uint64_t> &key, F enqueue, hipGraphExec_t
     return BRI_OK;
 }
 
+// The pinned host word the solvers poll the all-done flag into: one per (host thread, device),
+// allocated on first use and kept for the life of the thread (a page of pinned memory), so that no
+// apply allocates or frees pinned memory on its path.
+static int pinned_flag(int **out) {
+    thread_local std::map<int, int *> flags;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BRI_EHIP;
+    auto it = flags.find(dev);
+    if (it == flags.end()) {
+        int *p = nullptr;
+        if (hipHostMalloc((void **)&p, sizeof(int), hipHostMallocDefault) != hipSuccess) return BRI_EHIP;
+        it = flags.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return BRI_OK;
+}
+
 static bool graphs_enabled() {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     return g_graphs_on;
@@ -856,7 +873,7 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     const size_t nel = (size_t)12 * g.V;
 
     int *hflag = nullptr;
-    BRI_HIP_CHECK(hipHostMalloc((void **)&hflag, sizeof(int), hipHostMallocDefault));
+    if (pinned_flag(&hflag) != BRI_OK) return BRI_EHIP;
     int result = BRI_OK;
     RunStats rs;
     int passes = 0;
@@ -918,7 +935,6 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
         }
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    (void)hipHostFree(hflag);
     return result;
 }
 
@@ -970,7 +986,7 @@ int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_pa
         if (work_bytes < ar.used || !W64 || !b || !x_out) return BRI_EINVAL;
     }
     int *hflag = nullptr;
-    BRI_HIP_CHECK(hipHostMalloc((void **)&hflag, sizeof(int), hipHostMallocDefault));
+    if (pinned_flag(&hflag) != BRI_OK) return BRI_EHIP;
     RunStats rs;
     int passes = 0;
     std::vector<double> shift_res((size_t)n, 0.0);
@@ -983,7 +999,6 @@ int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_pa
         rc = refine(pl, g, prm, W64, b, s, hflag, passes, shift_res);
         result = rc;
     }
-    (void)hipHostFree(hflag);
     if (result != BRI_OK && result != BRI_ENOCONV) return result;
     *x_out = mixed ? (void *)pl.x64 : m.x;
     if (st) {

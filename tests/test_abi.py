@@ -192,7 +192,8 @@ def test_cascade_levels_validated():
     assert st0 == bri.OK
     # the paper's two-level cascade for f_{4,4}: n = 1, then the Brillouin operator
     st2, nb2 = query([bri._Level(1, 0.1, 20, 1e-6, 0), bri._Level(0, 0.1, 20, 0.0, 0)])
-    assert st2 == bri.OK and nb2 == nb0 + 2 * 8 * vec
+    # eight BiCGstab vectors per level, and two for the compacted columns of the FP64 kernel level
+    assert st2 == bri.OK and nb2 == nb0 + (2 * 8 + 2) * vec
     bads = [
         [bri._Level(0, 0.1, 20, 0.0, 0), bri._Level(1, 0.1, 20, 1e-6, 0)],  # Brillouin not last
         [bri._Level(1, 0.0, 20, 1e-6, 0)],                                 # tol <= 0
@@ -299,3 +300,25 @@ def test_massive_solve_nrhs_validated():
     for nrhs, nbytes in sizes:
         _, ovb = _ov_query((8, 8, 8, 8), kl_n=4, tol=1e-12, max_iter=200)
         assert nbytes >= 9 * vec * nrhs
+
+
+def test_cascade_low_precision_levels_must_agree():
+    lib = bri.load()
+    g = bri._geom((8, 8, 8, 8))
+    prm = bri._OvParams(4, 1.0, 1e-12, 200, 0, 0)
+    mp_ = bri._MassParams(0.03, 1, 1e-9, 100)
+
+    def query(levels):
+        arr = (bri._Level * len(levels))(*levels)
+        nb = ctypes.c_size_t(0)
+        return lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), len(levels), arr,
+                            None, None, 1, None, ctypes.byref(nb), None, None), nb.value
+
+    st64, nb64 = query([bri._Level(1, 0.1, 20, 1e-6, 0), bri._Level(0, 0.1, 20, 0.0, 0)])
+    st32, nb32 = query([bri._Level(1, 0.1, 20, 1e-6, 0), bri._Level(0, 0.1, 20, 0.0, 1)])
+    assert st64 == bri.OK and st32 == bri.OK
+    # the narrowed kernel level keeps its two work vectors in complex float instead of double
+    assert nb64 - nb32 == 2 * 12 * 8**4 * 8
+    # one Wlo array: FP32 and bfloat16 levels cannot be mixed
+    assert query([bri._Level(1, 0.1, 20, 1e-5, 1), bri._Level(0, 0.1, 20, 0.0, 2)])[0] == bri.EINVAL
+    assert query([bri._Level(1, 0.1, 20, 1e-5, 2), bri._Level(0, 0.1, 20, 0.0, 2)])[0] == bri.OK

@@ -241,3 +241,20 @@ def test_batched_solve_mixed_norms_and_zero_column(dense4):
     for c in range(2):
         assert rel_l2(got[c], _dense_x(D, bb[c], M, True)) < 1e-9, c
     assert np.abs(got[2]).max() == 0.0
+
+
+@pytest.mark.parametrize("kprec", [bri.F32, bri.F32_BF16W])
+def test_cascade_low_precision_kernel_level(dense_dov4, kprec):
+    """The Brillouin level of the cascade in FP32 (or with bfloat16 links): only the preconditioner
+    changes, so the solution is the FP64 one."""
+    U, _, dov = dense_dov4
+    b = synth.gaussian_source(L4, synth.SOURCE_SEED_BASE + 4)[0]
+    Ud = bri.links_to_device(U)
+    W = bri.build_links(L4, Ud, bri.F64)
+    Wlo = bri.build_links(L4, Ud, kprec)
+    op = bri.OverlapOp(L4, W, kl_n=4, rho=RHO, tol=1e-13, max_iter=3000, Wlo=Wlo)
+    levels = [bri.Level(1, tol=0.1, max_iter=30, ms_tol=1e-8), bri.Level(0, tol=0.1, max_iter=30, inner=kprec)]
+    x, st = op.solve(bri.spinor_to_device(b[None]), M, complete=True, tol=1e-11, prec=levels)
+    want = _dense_x(_dense_dov(dov, 4), b, M, True)
+    assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-9, (st.iters, st.level_iters)
+    assert st.status == bri.OK and st.rel_resid < 1e-10
