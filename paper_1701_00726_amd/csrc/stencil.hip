@@ -103,9 +103,17 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
     c.xcd_remap = 1;
     if (ncol >= 2) {
         // link loads amortised over R right-hand sides per thread (a last, partial group of
-        // columns is allowed); four waves still split each tile's displacements
+        // columns is allowed); four waves still split each tile's displacements.  Below 4096
+        // tiles (up to 16^4) more column groups keep the chip busy: R = 2 (FP64, and FP32 up to 8
+        // columns) or 3 measured 5-40% faster than R = 4 at 8^4 and 16^4; at 24^3x48 R = 4 is
+        // fastest (by up to 25% in FP32).
         c.nsplit = MRHS_SPLIT;
-        c.rpt = ncol < 4 ? ncol : ((ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3);
+        if (ncol < 4)
+            c.rpt = ncol;
+        else if (g.V / 64 < 4096)
+            c.rpt = (prec == BRI_F64 || ncol <= 8) ? 2 : 3;
+        else
+            c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
     } else {
         // four waves split each tile's directions: fills the 1024 SIMDs on small lattices, and on
         // large ones keeps fewer tiles (and their link lines) in flight per XCD than two waves do

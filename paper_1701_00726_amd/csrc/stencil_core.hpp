@@ -196,27 +196,19 @@ __device__ __forceinline__ int xcd_order(int blk, int nblk, int remap) {
     return (remap && (nblk & 7) == 0) ? (blk & 7) * (nblk >> 3) + (blk >> 3) : blk;
 }
 
-// acc += C(x) psi(x) for the clover term stored after the link slabs: two chirality blocks of
-// 6x6 entries, component index 3*spin + colour, block k holding spins 2k and 2k+1
+// v += (C(x) psi(x))_comp for the clover term stored after the link slabs: two chirality blocks
+// of 6x6 entries, component index comp = 3*spin + colour, block k holding spins 2k and 2k+1.
+// Applied where a wave finishes its output components, after the slab loop, so the term adds
+// nothing to the loop's register footprint.
 template <class LS>
-__device__ __forceinline__ void clover_add(typename Cx<typename LS::R>::T (&acc)[4][3],
+__device__ __forceinline__ void clover_row(typename Cx<typename LS::R>::T &v,
                                            const typename LS::store_t *__restrict__ Cf,
-                                           const typename Cx<typename LS::R>::T *__restrict__ ps, unsigned x,
-                                           unsigned V) {
-    using C = typename Cx<typename LS::R>::T;
+                                           const typename Cx<typename LS::R>::T *__restrict__ ps, int comp,
+                                           unsigned x, unsigned V) {
+    const int k = comp / 6, a = comp % 6;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        C p[6];
-#pragma unroll
-        for (int b = 0; b < 6; ++b) p[b] = ps[(size_t)(k * 6 + b) * V + x];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-            C v = acc[2 * k + a / 3][a % 3];
-#pragma unroll
-            for (int b = 0; b < 6; ++b) cmac(v, LS::load(Cf, (size_t)((k * 6 + a) * 6 + b) * V + x), p[b]);
-            acc[2 * k + a / 3][a % 3] = v;
-        }
-    }
+    for (int b = 0; b < 6; ++b)
+        cmac(v, LS::load(Cf, (size_t)((k * 6 + a) * 6 + b) * V + x), ps[(size_t)(k * 6 + b) * V + x]);
 }
 
 // stored slabs a kernel walks: all 40 (Brillouin), or the one-hop slabs j = 40 - 3^(3-k) (Wilson:

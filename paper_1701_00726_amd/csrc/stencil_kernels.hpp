@@ -126,7 +126,6 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
                 const C v = in[(size_t)(s * 3 + b) * V + x];
                 acc[s][b] = cmake<C>(diag * v.x, diag * v.y);
             }
-        if (a.g.csw != 0.0) clover_add<LS>(acc, W + (size_t)LINK_SLAB_ENTRIES * V, in, x, V);
     }
 
     for (int k = q; k < Slabs<KIND>::n; k += NSPLIT) {
@@ -171,6 +170,10 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
             for (int b = 0; b < 3; ++b) res[s * 3 + b] = acc[s][b];
     }
 
+    if (a.g.csw != 0.0) {
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) clover_row<LS>(res[i], W + (size_t)LINK_SLAB_ENTRIES * V, in, q * NCOMP + i, x, V);
+    }
     double n0 = 0.0, n1 = 0.0;
 #pragma unroll
     for (int i = 0; i < NCOMP; ++i) epilogue<MODE, C, R>(a, col, q * NCOMP + i, x, V, res[i], n0, n1);
@@ -239,11 +242,6 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilAr
                 }
                 acc[r][s][b] = v;
             }
-    if (q == 0 && a.g.csw != 0.0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (live[r]) clover_add<LS>(acc[r], W + (size_t)LINK_SLAB_ENTRIES * V, in + (size_t)r * 12 * V, x, V);
-    }
 
     for (int k = q; k < Slabs<KIND>::n; k += NSPLIT) {
         const int j = Slabs<KIND>::at(k);
@@ -296,6 +294,8 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilAr
                 v.x += u.x;
                 v.y += u.y;
             }
+            if (a.g.csw != 0.0)
+                clover_row<LS>(v, W + (size_t)LINK_SLAB_ENTRIES * V, in + (size_t)r * 12 * V, comp, x, V);
             epilogue<MODE, C, RT>(a, col, comp, x, V, v, n0, n1);
         }
         if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
