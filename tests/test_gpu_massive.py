@@ -258,3 +258,44 @@ def test_cascade_low_precision_kernel_level(dense_dov4, kprec):
     want = _dense_x(_dense_dov(dov, 4), b, M, True)
     assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-9, (st.iters, st.level_iters)
     assert st.status == bri.OK and st.rel_resid < 1e-10
+
+
+def test_combined_wilson_clover_antiperiodic_cascade_batched():
+    """Everything at once: Wilson kernel with the clover term, antiperiodic in t, two sources
+    side by side, f_{4,4} with a two-level cascade whose kernel level runs in FP32; each column
+    against the dense solve of the same operator."""
+    need_gpu()
+    L = (4, 4, 4, 8)
+    U = synth.random_links(L, 0.35, 97)
+    tbc, csw, n, m = 1, 1.0, 4, 0.3
+    C = oracle.clover_field(L, U, csw)
+    K = oracle.WilsonKernel(U, tbc, C)
+    V = 512
+    d = odense.DenseOverlap(oracle.dense_matrix(L, K, -RHO), V, RHO)
+    G = d.fn_of_H(lambda lam: lam * kl.r_diag_f64(lam * lam, n))
+    D = RHO * (np.eye(12 * V) + d.G5[:, None] * G)
+    b = synth.gaussian_source(L, 98, nrhs=2)
+    Ud = bri.links_to_device(U)
+    W = bri.build_links(L, Ud, bri.F64, tbc=tbc, csw=csw)
+    W32 = bri.build_links(L, Ud, bri.F32, tbc=tbc, csw=csw)
+    op = bri.OverlapOp(L, W, kl_n=n, rho=RHO, tol=1e-13, max_iter=5000, tbc=tbc, Wlo=W32,
+                       kernel=bri.KERNEL_WILSON)
+    levels = [bri.Level(1, tol=0.1, max_iter=40, ms_tol=1e-8), bri.Level(0, tol=0.1, max_iter=60, inner=bri.F32)]
+    x, st = op.solve(bri.spinor_to_device(b), m, complete=True, tol=1e-11, prec=levels)
+    got = bri.spinor_to_host(x)
+    mt = massive.mass_tilde(m, RHO)
+    for c in range(2):
+        bv = b[c].ravel()
+        bt = ((1 + m / (2 * RHO)) * bv - (m / (4 * RHO**2)) * (D @ bv)) / (1 - m / (2 * RHO))
+        want = np.linalg.solve(D + mt * np.eye(12 * V), bt).reshape(b[c].shape)
+        assert rel_l2(got[c], want) < 1e-9, (c, st.iters, st.level_iters)
+    assert st.status == bri.OK
+
+
+def test_massless_solve(dense4):
+    """m = 0: mt = 0 and bt = b, so the solve inverts D_ov itself."""
+    U, D, b = dense4
+    op = _op(L4, U, N)
+    x, st = op.solve(bri.spinor_to_device(b[None]), 0.0, complete=True, tol=1e-11, max_iter=3000)
+    want = np.linalg.solve(D, b.ravel()).reshape(b.shape)
+    assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-8, st.iters
