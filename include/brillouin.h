@@ -3,7 +3,9 @@
  * operator (S. Duerr, G. Koutsou, arXiv:1701.00726).
  *
  * Operator conventions (lattice spacing a = 1):
- *   D_bri(m0) = sum_mu gamma_mu nabla^iso_mu - (1/2) lap^bri + m0   eq. (def_bril), c_SW = 0
+ *   D_bri(m0) = sum_mu gamma_mu nabla^iso_mu - (1/2) lap^bri + m0   eq. (def_bril)
+ *               [- (c_SW/2) sum_{mu<nu} sigma_mu_nu F_mu_nu when bri_geom.csw != 0]
+ *   D_wil(m0)   likewise with the standard derivative and 9-point Laplacian, eq. (def_wils)
  *   X         = D_bri(-rho),  H = gamma5 X,  A = X^dag X = H^2
  *   D_ov      = rho (1 + gamma5 sign(H))                               eq. (def_over)
  *   sign(H)  ~= g_{2n+1}(H) = H r_n(H^2),
@@ -15,7 +17,8 @@
  * are structure-of-arrays with the site index fastest and complex numbers
  * interleaved (re, im):
  *   U    [4][3][3][V]        thin (or smeared) gauge links, complex double
- *   W    [40][3][3][V]       off-axis links, complex double / float / bfloat16
+ *   W    [40][3][3][V]       off-axis links, complex double / float / bfloat16, followed
+ *                            when csw != 0 by the clover term [2][6][6][V] (48 slabs in all)
  *   psi  [nrhs][4][3][V]     spinors: spin, colour, site
  * Gamma matrices (chiral basis): gamma_k = [[0, -i s_k], [i s_k, 0]] with the
  * Pauli matrices s_k, gamma_4 = [[0, 1], [1, 0]], gamma5 = diag(1, 1, -1, -1).
@@ -26,9 +29,9 @@
  * Memory: every pointer argument named U, W*, in, out, work is a DEVICE pointer
  * owned by the caller; the library never frees caller memory.  Host pointers
  * are the geometry, parameter and statistics structs and work_bytes.
- * Streams: `stream` is a hipStream_t (NULL = the null stream); every call is
- * asynchronous on it, except ov_sign_apply / ov_apply, which synchronise the
- * stream before returning (they read convergence flags on the host).
+ * Streams: `stream` is a hipStream_t (NULL = the null stream); the stencil, link and
+ * force calls are asynchronous on it; the solver calls (ov_*) and the autotuner
+ * synchronise it before returning (they read convergence flags or timings on the host).
  * Errors: no call aborts, prints or throws.  A call returns BRI_OK or a
  * negative status; on BRI_EINVAL nothing was launched.
  */
@@ -76,11 +79,15 @@ typedef enum {
  * path; a step +mu at y contributes U_mu(y), a step -mu contributes
  * U_mu(y - mu)^dag.  No projection back to SU(3).  Computed in FP64 and rounded
  * to `wprec` on store.
+ * With geom->csw != 0 the clover term -(c_SW/2) sum_{mu<nu} sigma_mu_nu F_mu_nu follows the
+ * links: F_mu_nu the hermitian traceless part of the clover-leaf average of the four
+ * plaquettes at x, sigma_mu_nu = (i/2)[gamma_mu, gamma_nu]; stored as its two chirality
+ * blocks (spins 0,1 and 2,3), 6x6 entries each, index 3*spin + colour within the block.
  *   U  : [4][3][3][V] complex double (device, read)
- *   W  : [40][3][3][V] in precision wprec (device, written)
+ *   W  : [40][3][3][V] (csw = 0) or [48][3][3][V] (csw != 0) in precision wprec (device, written)
  * Returns BRI_EINVAL for L_mu < 1 or odd/zero sizes it cannot address,
- * BRI_EHIP on a HIP failure (a temporary FP64 buffer of 5760*V bytes is
- * allocated when wprec != BRI_F64).
+ * BRI_EHIP on a HIP failure (a temporary FP64 buffer of 5760*V bytes, 6912*V with the
+ * clover term, is allocated when wprec != BRI_F64).
  */
 int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, void *stream);
 
@@ -90,7 +97,8 @@ int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, voi
  *   S_d = -2^{-(k+3)} + c_k sum_{mu in supp d} d_mu gamma_mu,
  *   c_k = 4/27, 1/27, 1/108, 1/432 for k = 1..4 hops
  * (position-space weights of the isotropic derivative and the Brillouin
- * Laplacian, App. A momentum forms).
+ * Laplacian, App. A momentum forms), plus the clover term on the diagonal when
+ * geom->csw != 0 (W must then hold it; only whether csw is zero matters here).
  *   W   : [40][3][3][V] in precision prec (F64: double; F32: float;
  *         F32_BF16W: bfloat16 links with float spinors)
  *   in, out : [nrhs][4][3][V], complex double for BRI_F64, complex float
@@ -106,9 +114,10 @@ int bri_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, cons
 
 /* Kernel operator X of the overlap (ov_params.kernel). */
 enum bri_kernel {
-    BRI_KERNEL_BRILLOUIN = 0, /* D_bri, eq. (def_bril), c_SW = 0: the 81-point stencil         */
-    BRI_KERNEL_WILSON = 1     /* D_wil, eq. (def_wils), c_SW = 0: the 9-point stencil, reading
-                                 the four one-hop slabs of the same link array               */
+    BRI_KERNEL_BRILLOUIN = 0, /* D_bri, eq. (def_bril): the 81-point stencil                   */
+    BRI_KERNEL_WILSON = 1     /* D_wil, eq. (def_wils): the 9-point stencil, reading the four
+                                 one-hop slabs of the same link array (either with the clover
+                                 term when the geometry's csw != 0)                          */
 };
 
 /* Kenney-Laub family member used for sign(H) (ov_params.kind). */
@@ -119,9 +128,10 @@ enum bri_kl_kind {
 };
 
 /*
- * wil_apply     -- out = D_wil(m0) in,  eq. (def_wils) with c_SW = 0:
+ * wil_apply     -- out = D_wil(m0) in,  eq. (def_wils):
  *   (D psi)(x) = (4 + m0) psi(x) - (1/2) sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
  *                                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+ *               [+ the clover term when geom->csw != 0]
  * wil_apply_dag -- out = D_wil(m0)^dag in = gamma5 D_wil(m0) gamma5 in.
  * W is the link array of bri_build_links (its four one-hop slabs are U_mu(x - mu)^dag with the
  * boundary signs folded in; the other slabs are not read), so both kernels share one set-up.
@@ -159,15 +169,17 @@ typedef struct {
 } ov_stats;
 
 /*
- * ov_sign_apply -- out ~= sign(H) in = gamma5 X r_n(X^dag X) in, H = gamma5 D_bri(-rho)
+ * ov_sign_apply -- out ~= sign(H) in = gamma5 X r_n(X^dag X) in, H = gamma5 X, X = D_kernel(-rho)
+ *                  (params->kernel: Brillouin or Wilson; with the clover term when csw != 0)
  * ov_apply      -- out ~= D_ov in   = rho (in + X r_n(X^dag X) in)          eq. (def_over)
  * r_n(A) in is evaluated by one multi-shift CG on A + sigma_min for all n
- * shifts at once (Sec. 3.3), with the coefficients of eq. (KLnn_parfrac); the
+ * shifts at once (Sec. 3.3), with the coefficients of eq. (KLnn_parfrac) (or of the
+ * first upper diagonal, params->kind); the
  * nrhs right-hand sides run side by side, each with its own Krylov space.
  * With a low-precision inner solve the multi-shift runs on Wlo, every shift
  * solution is kept, and each (shift, source) column is corrected against its
  * FP64 residual (formed with W64) until it meets tol.
- *   W64 : [40][3][3][V] complex double off-axis links
+ *   W64 : [40][3][3][V] complex double off-axis links ([48]... with the clover term)
  *   Wlo : links in precision `inner` (from bri_build_links); NULL when inner = BRI_F64
  *   in, out : [nrhs][4][3][V] complex double (device); must not overlap
  *   work, work_bytes : device workspace; with work == NULL the call only writes
@@ -193,7 +205,7 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  * Cascaded preconditioning (Sec. 8, eqs. (cascaded_one), (cascaded_two)): the outer BiCGstab can
  * be preconditioned from the right by a chain of cheaper operators of the same massive form,
  *   A_k = rho [D^(k) + 1 + mt/rho],  D^(k) = X r_{n_k}(X^dag X)  (the overlap approximant of
- *   Kenney-Laub order n_k, so A_k = D_ov^(n_k) + mt),  D^(0) = X = D_bri(-rho),
+ *   Kenney-Laub order n_k, so A_k = D_ov^(n_k) + mt),  D^(0) = X = D_kernel(-rho),
  * each inverted approximately by its own BiCGstab (stopped at a loose tolerance or an iteration
  * cap) that is preconditioned by the next operator of the chain.  The paper's one-level scheme
  * for f_{1,1} is params->kl_n = 1 with prec = {Brillouin}; its two-level scheme for f_{4,4} is
@@ -211,7 +223,8 @@ typedef struct {
 
 /* One preconditioner level. */
 typedef struct {
-    int kl_n;      /* 0: the Brillouin operator (must be the last level), else 1..BRI_MAX_SHIFTS */
+    int kl_n;      /* 0: the kernel operator itself (Brillouin or Wilson as params->kernel; must
+                      be the last level), else 1..BRI_MAX_SHIFTS                          */
     double tol;    /* stop of this level's BiCGstab, relative to the vector it is applied to   */
     int max_iter;  /* iteration cap of this level's BiCGstab, per application                  */
     double ms_tol; /* multi-shift CG tolerance of this level's overlap applies (kl_n > 0)       */
@@ -251,8 +264,8 @@ typedef struct {
  * Synchronises `stream`.  Returns BRI_ENOCONV when max_iter outer iterations did not reach tol
  * (out holds the last iterate), BRI_ENAN on a non-finite or breaking-down outer recurrence, the
  * status of a failing outer ov_apply, BRI_EINVAL for bad arguments (m outside [0, 2 rho), a
- * Brillouin level that is not the last one).  Preconditioner levels that stop at their cap are
- * not errors.
+ * kernel level that is not the last one, low-precision levels of different precisions, no Wlo
+ * for a low-precision level).  Preconditioner levels that stop at their cap are not errors.
  */
 int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params,
              const ov_mass_params *mp, int nprec, const ov_level *prec, const void *in, void *out, int nrhs,
@@ -287,8 +300,9 @@ int bri_stencil_time(const bri_geom *geom, const void *W, int prec, const void *
 
 /* bri_autotune -- times every candidate configuration for (geom, prec, nrhs)
  * as bri_stencil_time does and installs the fastest in a process-wide table
- * used by bri_apply, bri_apply_dag and the overlap solvers for that lattice,
- * precision and column count.  best / best_us may be NULL. */
+ * used by the Brillouin stencils (bri_apply, bri_apply_dag and the overlap solvers on the
+ * Brillouin kernel) for that lattice, precision and column count; the Wilson stencil keeps
+ * the default configuration.  best / best_us may be NULL. */
 int bri_autotune(const bri_geom *geom, const void *W, int prec, const void *in, void *out, int nrhs, int reps,
                  bri_stencil_cfg *best, double *best_us, void *stream);
 
@@ -299,8 +313,9 @@ int bri_get_stencil_cfg(const bri_geom *geom, int prec, int nrhs, bri_stencil_cf
 
 /* bri_set_solver_graphs -- enable (1, the default) or disable (0) HIP-graph replay of
  * the multi-shift CG loop.  When enabled, each block of 8 iterations (six launches per
- * iteration) is captured once per solve layout (device, lattice, precision, column count,
- * workspace and link addresses, launch configuration) on a library-owned stream and
+ * iteration) is captured once per solve layout (device, lattice, boundary condition, clover
+ * switch, precision, kernel, mass, column count, workspace and link addresses, launch
+ * configuration) on a library-owned stream and
  * replayed on the caller's stream; up to 16 instantiated graphs are cached per process and
  * disabling clears them.  Results are identical either way (same kernels, same order).
  * Not thread-safe against solves running concurrently in other threads.  BRI_EINVAL for
