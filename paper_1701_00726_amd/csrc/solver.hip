@@ -53,20 +53,32 @@ constexpr int INIT_BLOCKS = 256;  // vector-kernel blocks per column
 
 // --------------------------------------------------------------- reductions
 
-// deterministic sum of n partials (stride 2, component comp) by one block
-__device__ double block_sum(const double *partial, int n, int comp) {
-    __shared__ double sh[RED_THREADS];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += RED_THREADS) s += partial[2 * i + comp];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
+// deterministic sums of n partial pairs (stride 2) by one block: each lane sums a strided slice,
+// each wave folds its lanes with shuffles, and every thread adds the wave sums in the same order,
+// so all threads return the same (x, y) = (sum of component 0, sum of component 1)
+static_assert(RED_THREADS % 64 == 0 && MAXS <= RED_THREADS, "one thread per shift");
+__device__ double2 block_sum2(const double *partial, int n) {
+    __shared__ double2 sh[RED_THREADS / 64];
+    double sx = 0.0, sy = 0.0;
+    for (int i = threadIdx.x; i < n; i += RED_THREADS) {
+        sx += partial[2 * i];
+        sy += partial[2 * i + 1];
     }
-    const double r = sh[0];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sx += __shfl_down(sx, off, 64);
+        sy += __shfl_down(sy, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = make_double2(sx, sy);
     __syncthreads();
-    return r;
+    double2 t = sh[0];
+#pragma unroll
+    for (int w = 1; w < RED_THREADS / 64; ++w) {
+        t.x += sh[w].x;
+        t.y += sh[w].y;
+    }
+    __syncthreads();
+    return t;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -118,7 +130,7 @@ __global__ void ms_init_kernel(size_t n, const B *__restrict__ b, C *__restrict_
 // one block per column
 __global__ void ms_scalar_init_kernel(ColState *states, const double *partial, int nblk, double tol) {
     ColState *st = states + blockIdx.x;
-    const double b2 = block_sum(partial + 2 * (size_t)blockIdx.x * nblk, nblk, 0);
+    const double b2 = block_sum2(partial + 2 * (size_t)blockIdx.x * nblk, nblk).x;
     if (threadIdx.x == 0) {
         st->bnorm2 = b2;
         st->rr = b2;
@@ -148,26 +160,20 @@ __global__ void ms_scalar_init_kernel(ColState *states, const double *partial, i
     }
 }
 
-// alpha and the shifted alpha^sigma after t = X p (partials: |t|^2, |p|^2)
+// alpha and the shifted alpha^sigma after t = X p (partials: |t|^2, |p|^2).  Every thread forms
+// alpha from the same sums; thread i < nshift updates shift i, thread 0 the column scalars.
 __global__ void ms_alpha_kernel(ColState *states, const double *partial, int nblk) {
     ColState *st = states + blockIdx.x;
     if (st->done) return;
-    const double *pt = partial + 2 * (size_t)blockIdx.x * nblk;
-    const double tt = block_sum(pt, nblk, 0);
-    const double pp = block_sum(pt, nblk, 1);
-    if (threadIdx.x == 0) {
-        const double pAp = tt + st->sigma0 * pp;
-        const double alpha = st->rr / pAp;
-        if (!isfinite(alpha) || pAp <= 0.0) {
-            st->status = BRI_ENAN;
-            st->done = 1;
-            for (int i = 0; i < st->nshift; ++i) st->upd_x[i] = 0;
-            return;
-        }
-        st->alpha = alpha;
-        for (int i = 0; i < st->nshift; ++i) {
-            st->upd_x[i] = st->active[i];
-            if (!st->active[i]) continue;
+    const double2 sums = block_sum2(partial + 2 * (size_t)blockIdx.x * nblk, nblk);
+    const double pAp = sums.x + st->sigma0 * sums.y;
+    const double alpha = st->rr / pAp;
+    const bool bad = !isfinite(alpha) || pAp <= 0.0;
+    const int i = threadIdx.x;
+    if (i < st->nshift) {
+        const int act = bad ? 0 : st->active[i];
+        st->upd_x[i] = act;
+        if (act) {
             const double z = st->zeta[i], zo = st->zeta_old[i];
             const double den =
                 alpha * st->beta_old * (zo - z) + zo * st->alpha_old * (1.0 + st->delta[i] * alpha);
@@ -176,41 +182,55 @@ __global__ void ms_alpha_kernel(ColState *states, const double *partial, int nbl
             st->alpha_s[i] = alpha * zn / z;
         }
     }
+    if (i == 0) {
+        if (bad) {
+            st->status = BRI_ENAN;
+            st->done = 1;
+        } else {
+            st->alpha = alpha;
+        }
+    }
 }
 
-// beta, beta^sigma, convergence after r -= alpha (A + sigma0) p (partials: |r|^2)
+// beta, beta^sigma, convergence after r -= alpha (A + sigma0) p (partials: |r|^2).  Thread
+// i < nshift updates shift i; the column scalars are written by thread 0 after a block-wide
+// vote on whether any shift is still active (every read of them precedes that barrier).
 __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk) {
     ColState *st = states + blockIdx.x;
     if (st->done) return;
-    const double rr_new = block_sum(partial + 2 * (size_t)blockIdx.x * nblk, nblk, 0);
-    if (threadIdx.x == 0) {
-        const int it = st->iter + 1;
-        st->iter = it;
-        if (!isfinite(rr_new)) {
-            st->status = BRI_ENAN;
-            st->done = 1;
-            for (int i = 0; i < st->nshift; ++i) {
-                st->active[i] = 0;
-                st->upd_x[i] = 0;
-            }
-            return;
-        }
-        const double beta = rr_new / st->rr;
-        int any = 0;
-        for (int i = 0; i < st->nshift; ++i) {
-            if (!st->active[i]) continue;
-            const double ratio = st->zeta_new[i] / st->zeta[i];
+    const double rr_new = block_sum2(partial + 2 * (size_t)blockIdx.x * nblk, nblk).x;
+    const bool bad = !isfinite(rr_new);
+    const double beta = rr_new / st->rr;
+    const int it = st->iter + 1;
+    const int i = threadIdx.x;
+    int still = 0;
+    if (i < st->nshift) {
+        if (bad) {
+            st->active[i] = 0;
+            st->upd_x[i] = 0;
+        } else if (st->active[i]) {
+            const double zn = st->zeta_new[i], z = st->zeta[i];
+            const double ratio = zn / z;
             st->beta_s[i] = beta * ratio * ratio;
-            st->zeta_old[i] = st->zeta[i];
-            st->zeta[i] = st->zeta_new[i];
-            const double res2 = st->zeta[i] * st->zeta[i] * rr_new;
+            st->zeta_old[i] = z;
+            st->zeta[i] = zn;
+            const double res2 = zn * zn * rr_new;
             if (res2 <= st->tol2 * st->tolf2[i]) {
                 st->active[i] = 0;
                 st->conv_iter[i] = it;
                 st->conv_res[i] = sqrt(res2 / st->bnorm2);
             } else {
-                any = 1;
+                still = 1;
             }
+        }
+    }
+    const int any = __syncthreads_or(still);
+    if (i == 0) {
+        st->iter = it;
+        if (bad) {
+            st->status = BRI_ENAN;
+            st->done = 1;
+            return;
         }
         st->alpha_old = st->alpha;
         st->beta_old = beta;
