@@ -302,8 +302,8 @@ struct Cascade {
                     beta[c] = (rho_new[c] / rho_old[c]) * (alpha[c] / omega[c]);
                     mbw[c] = -beta[c] * omega[c];
                 }
-            // p = r + beta (p - omega v); a finished column gets p = r
-            // finished columns get p = 0, so the inner solves and the multi-shift skip them
+            // p = r + beta (p - omega v); a finished column gets p = 0, so the inner solves and the
+            // multi-shift skip it
             Cols one_act(ncol, 0.0);
             for (int c = 0; c < ncol; ++c) one_act[c] = active[c] ? 1.0 : 0.0;
             if ((rc = lincomb(L.p, one_act, L.r, beta, L.p, mbw, L.v)) != BRI_OK) return rc;

@@ -43,6 +43,26 @@ def test_overlap_4_4_point_source(kind, n):
     assert rel_l2(bri.spinor_to_host(s_out)[0], sref) < TOL
 
 
+@pytest.mark.parametrize("kind", [bri.KL_DIAG, bri.KL_UPPER])
+def test_overlap_maximum_order(kind):
+    """Every one of the BRI_MAX_SHIFTS shifts runs (one scalar thread per shift in the solver)."""
+    need_gpu()
+    L = (4, 4, 4, 4)
+    n = bri.MAX_SHIFTS
+    U, Wo = field(L, "cfg1")
+    W = bri.build_links(L, bri.links_to_device(U), bri.F64)
+    op = bri.OverlapOp(L, W, kl_n=n, rho=1.0, tol=1e-12, max_iter=2000, kind=kind)
+    g = synth.gaussian_source(L, synth.SOURCE_SEED_BASE + 7)
+    out, st = op.apply(bri.spinor_to_device(g))
+    kname = "diag" if kind == bri.KL_DIAG else "upper"
+    ref, _, _ = oracle.ov_apply(L, Wo, 1.0, n, g[0], tol=1e-13, kind=kname)
+    assert rel_l2(bri.spinor_to_host(out)[0], ref) < TOL
+    assert len(st.shift_iters) == n and all(0 < k <= st.iters for k in st.shift_iters)
+    assert max(st.rel_resid) <= 1e-12
+    # the smallest shift is the base system and converges last
+    assert st.shift_iters[0] == st.iters
+
+
 def test_overlap_against_dense_eigendecomposition():
     need_gpu()
     L = (4, 4, 4, 4)
