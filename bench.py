@@ -22,6 +22,7 @@ extra        the same apply batched over the 12 spin-colour point sources and
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
        python bench.py --stencil-only     (copy calibration + stencil launches, for counters)
        python bench.py --stencil-only --lattice 32,32,32,64   (the same on a larger workload lattice)
+       python bench.py --stencil-only --stencil-rhs 12        (plus the multi-RHS kernel, FP64 and FP32)
 """
 
 from __future__ import annotations
@@ -103,6 +104,8 @@ def parse():
     ap.add_argument("--survey", action="store_true",
                     help="stencil (tuned, FP64/FP32/BF16-link, 1 and 12 RHS) and overlap timings at 16^4, 24^3x48, 32^3x64")
     ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
+    ap.add_argument("--stencil-rhs", type=int, default=1,
+                    help="with --stencil-only: also launch the multi-RHS kernel on this many RHS (FP64 and FP32)")
     ap.add_argument("--lattice", default=None,
                     help="with --stencil-only: another lattice, e.g. 32,32,32,64 (links exp(0.7iA) + 3 APE "
                          "built on the device)")
@@ -382,8 +385,21 @@ def main():
         for _ in range(args.stencil_reps):
             bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
         torch.cuda.synchronize()
-        print(json.dumps({"stencil_only": True, "launches": args.stencil_reps, "copy_bytes": 1 << 30,
-                          "kernel_src_sha": kernel_source_digest(), "config": tuned}), flush=True)
+        rec = {"stencil_only": True, "launches": args.stencil_reps, "copy_bytes": 1 << 30,
+               "kernel_src_sha": kernel_source_digest(), "config": tuned}
+        if args.stencil_rhs > 1:
+            # the multi-RHS kernel in its default configuration, FP64 and FP32 links and vectors
+            nr = args.stencil_rhs
+            src = synth.gaussian_source(L, SRC_SEED, nrhs=nr)
+            for prec, name in ((bri.F64, "f64"), (bri.F32, "f32")):
+                Wp = W if prec == bri.F64 else bri.build_links(L, U, prec)
+                xm = bri.spinor_to_device(src, prec, dev)
+                ym = torch.empty_like(xm)
+                bri.apply(L, Wp, prec, -RHO, xm, out=ym)  # first launch loads the kernel's code object
+                ms = timed(lambda: bri.apply(L, Wp, prec, -RHO, xm, out=ym), args.stencil_reps)
+                rec[f"mrhs_{name}_{nr}rhs"] = {"us": ms * 1e3, "config": bri.get_stencil_cfg(L, prec, nr).as_dict()}
+                del Wp, xm, ym
+        print(json.dumps(rec), flush=True)
         return
 
     op = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
