@@ -267,6 +267,13 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_out(out, dtype, shape, device):
+    """A caller-supplied output must be exactly what the kernels write: dtype, shape, device."""
+    if out.dtype != dtype or tuple(out.shape) != tuple(shape) or out.device != device:
+        raise ValueError(f"out must be {dtype} of shape {tuple(shape)} on {device}")
+    return out
+
+
 def _check(fn, status, allow=()):
     if status != OK and status not in allow:
         raise BriError(fn, status)
@@ -342,8 +349,7 @@ def build_links(L, U, prec=F64, tbc=0, stream=None, out=None, csw=0.0):
     nslab = 48 if csw else 40
     if out is None:
         out = torch.empty((nslab, 3, 3, V), dtype=link_dtype(prec), device=U.device)
-    if tuple(out.shape) != (nslab, 3, 3, V):
-        raise ValueError(f"out must be ({nslab}, 3, 3, V)")
+    _check_out(out, link_dtype(prec), (nslab, 3, 3, V), U.device)
     g = _geom(L, tbc, csw)
     _check("bri_build_links", load().bri_build_links(ctypes.byref(g), _dptr(U), _dptr(out), int(prec), _stream(stream)))
     return out
@@ -358,6 +364,7 @@ def _apply(fn, L, W, prec, m0, psi, out=None, stream=None):
         raise ValueError("W must be (40 or 48, 3, 3, V) of the link dtype of prec")
     if out is None:
         out = torch.empty_like(psi)
+    _check_out(out, psi.dtype, psi.shape, psi.device)
     g = _geom(L, 0, _clover_flag(W))
     st = getattr(load(), fn)(ctypes.byref(g), _dptr(W), int(prec), float(m0), _dptr(psi), _dptr(out),
                              int(psi.shape[0]), _stream(stream))
@@ -428,6 +435,7 @@ class OverlapOp:
             raise ValueError(f"workspace sized for {self.nrhs} right-hand sides, got {psi.shape[0]}")
         if out is None:
             out = torch.empty_like(psi)
+        _check_out(out, psi.dtype, psi.shape, psi.device)
         stats = _OvStats()
         wb = ctypes.c_size_t(self.work_bytes)
         st = getattr(load(), fn)(

@@ -510,14 +510,14 @@ void graph_cache_clear_locked() {
 }
 }  // namespace
 
+// Launches the graph cached under `key` on `strm`, capturing it first from `enqueue` if absent.
+// The launch happens under the cache lock, so another host thread cannot evict (destroy) the
+// executable graph between lookup and launch.
 template <typename F>
-static int graph_for(const std::vector<uint64_t> &key, F enqueue, hipGraphExec_t *out) {
+static int graph_launch(const std::vector<uint64_t> &key, F enqueue, hipStream_t strm) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) {
-        *out = it->second;
-        return BRI_OK;
-    }
+    if (it != g_graphs.end()) return hipGraphLaunch(it->second, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
     int dev = 0;
     BRI_HIP_CHECK(hipGetDevice(&dev));
     hipStream_t cs = g_capture_streams[dev];
@@ -545,8 +545,7 @@ static int graph_for(const std::vector<uint64_t> &key, F enqueue, hipGraphExec_t
     }
     g_graphs[key] = ex;
     g_graph_order.push_back(key);
-    *out = ex;
-    return BRI_OK;
+    return hipGraphLaunch(ex, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
 }
 
 // The pinned host word the solvers poll the all-done flag into: one per (host thread, device),
@@ -667,8 +666,7 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
     int it = 0;
     for (;;) {
         if (use_graph && it + CHECK_EVERY <= s.max_iter) {
-            hipGraphExec_t ex = nullptr;
-            const int rc = graph_for(
+            const int rc = graph_launch(
                 key,
                 [&](hipStream_t q) -> int {
                     for (int k = 0; k < CHECK_EVERY; ++k) {
@@ -677,9 +675,8 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
                     }
                     return BRI_OK;
                 },
-                &ex);
+                strm);
             if (rc != BRI_OK) return rc;
-            BRI_HIP_CHECK(hipGraphLaunch(ex, strm));
             it += CHECK_EVERY;
         } else {
             for (int k = 0; k < CHECK_EVERY && it < s.max_iter; ++k, ++it) {

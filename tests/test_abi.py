@@ -322,3 +322,25 @@ def test_cascade_low_precision_levels_must_agree():
     # one Wlo array: FP32 and bfloat16 levels cannot be mixed
     assert query([bri._Level(1, 0.1, 20, 1e-5, 1), bri._Level(0, 0.1, 20, 0.0, 2)])[0] == bri.EINVAL
     assert query([bri._Level(1, 0.1, 20, 1e-5, 2), bri._Level(0, 0.1, 20, 0.0, 2)])[0] == bri.OK
+
+
+def test_binding_rejects_mismatched_outputs():
+    """A caller-supplied output of the wrong dtype or shape is refused before any launch, since
+    the kernels write the full size of the expected layout into it."""
+    import torch
+
+    L = (4, 4, 4, 4)
+    V = 256
+    psi = torch.zeros((1, 4, 3, V), dtype=torch.complex128)
+    W = torch.zeros((40, 3, 3, V), dtype=torch.complex128)
+    U = torch.zeros((4, 3, 3, V), dtype=torch.complex128)
+    for bad in (torch.zeros((1, 4, 3, V), dtype=torch.complex64), torch.zeros((1, 4, 3, V - 1), dtype=torch.complex128)):
+        with pytest.raises(ValueError, match="out must be"):
+            bri.apply(L, W, bri.F64, -1.0, psi, out=bad)
+    with pytest.raises(ValueError, match="out must be"):
+        bri.build_links(L, U, bri.F64, out=torch.zeros((40, 3, 3, V), dtype=torch.complex64))
+    with pytest.raises(ValueError, match="out must be"):
+        bri.build_links(L, U, bri.F32, out=torch.zeros((40, 3, 3, V), dtype=torch.complex128))
+    op = bri.OverlapOp(L, W, kl_n=4)
+    with pytest.raises(ValueError, match="out must be"):
+        op.apply(psi, out=torch.zeros((1, 4, 3, V), dtype=torch.complex64))
