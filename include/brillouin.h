@@ -29,7 +29,7 @@
  * Memory: every pointer argument named U, W*, in, out, work is a DEVICE pointer
  * owned by the caller; the library never frees caller memory.  Host pointers
  * are the geometry, parameter and statistics structs and work_bytes.
- * Streams: `stream` is a hipStream_t (NULL = the null stream); the stencil, link and
+ * Streams: `stream` is a hipStream_t (NULL = the null stream); the stencil, FP64 link and
  * force calls are asynchronous on it; the solver calls (ov_*) and the autotuner
  * synchronise it before returning (they read convergence flags or timings on the host).
  * Errors: no call aborts, prints or throws.  A call returns BRI_OK or a
@@ -45,7 +45,11 @@
 extern "C" {
 #endif
 
-/* lattice geometry; tbc = 1 makes the fermion field antiperiodic in t */
+/* lattice geometry; tbc = 1 makes the fermion field antiperiodic in t.
+ * Accepted: L_mu in 1..4096, tbc 0 or 1, finite csw, and 360 V (432 V with the clover term)
+ * below 2^31 entries, i.e. V <= 5 965 232 sites (4 971 026 with clover): 40^3 x 80 fits
+ * without the clover term, 48^3 x 96 does not fit.  Every operator call also needs V to be a multiple of 64 (the
+ * stencil tiles 64 sites per wave).  Anything else returns BRI_EINVAL. */
 typedef struct {
     int32_t L[4];
     int32_t tbc;
@@ -85,9 +89,10 @@ typedef enum {
  * blocks (spins 0,1 and 2,3), 6x6 entries each, index 3*spin + colour within the block.
  *   U  : [4][3][3][V] complex double (device, read)
  *   W  : [40][3][3][V] (csw = 0) or [48][3][3][V] (csw != 0) in precision wprec (device, written)
- * Returns BRI_EINVAL for L_mu < 1 or odd/zero sizes it cannot address,
- * BRI_EHIP on a HIP failure (a temporary FP64 buffer of 5760*V bytes, 6912*V with the
- * clover term, is allocated when wprec != BRI_F64).
+ * Returns BRI_EINVAL for a geometry outside the limits stated at bri_geom or a null pointer,
+ * BRI_EHIP on a HIP failure.  Asynchronous on `stream` for wprec = BRI_F64; for the lower
+ * precisions a temporary FP64 buffer of 5760*V bytes (6912*V with the clover term) is
+ * allocated, and the call synchronises `stream` before freeing it.
  */
 int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, void *stream);
 

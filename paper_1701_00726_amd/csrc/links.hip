@@ -296,14 +296,14 @@ extern "C" int bri_build_links(const bri_geom *geom, const void *U, void *W, int
     hipStream_t s = (hipStream_t)stream;
     if (wprec == BRI_F64) {
         st = build_links_f64(g, (const double2 *)U, (double2 *)W, s);
-        if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, (double2 *)W + (size_t)360 * g.V, s);
+        if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, (double2 *)W + (size_t)LINK_SLAB_ENTRIES * g.V, s);
         return st;
     }
     const size_t n = link_entries(g);
     double2 *tmp = nullptr;
     BRI_HIP_CHECK(hipMalloc(&tmp, n * sizeof(double2)));
     st = build_links_f64(g, (const double2 *)U, tmp, s);
-    if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, tmp + (size_t)360 * g.V, s);
+    if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, tmp + (size_t)LINK_SLAB_ENTRIES * g.V, s);
     if (st == BRI_OK) {
         const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
         if (wprec == BRI_F32)
