@@ -114,3 +114,26 @@ def test_mixed_refine_cap_reports_noconv():
     op = bri.OverlapOp(L, W64, kl_n=8, tol=1e-13, Wlo=Wlo, inner=bri.F32_BF16W, max_refine=0)
     out, st = op.apply(bri.spinor_to_device(synth.point_source(L)), allow_noconv=True)
     assert st.status == bri.ENOCONV and st.refine == 0 and max(st.rel_resid) > 1e-13
+
+
+def test_more_columns_than_a_refinement_chunk():
+    """33 sources: the FP64 batch against the oracle, and the mixed-precision batch, whose
+    (shift, source) corrections then run in several chunks of whole sources, against FP64."""
+    need_gpu()
+    L = (4, 4, 4, 4)
+    U, Wo = field(L, "cfg1")
+    Ud = bri.links_to_device(U)
+    W64 = bri.build_links(L, Ud, bri.F64)
+    Wlo = bri.build_links(L, Ud, bri.F32)
+    n, nrhs = 8, 33
+    b = synth.gaussian_source(L, 961, nrhs=nrhs)
+    bd = bri.spinor_to_device(b)
+    out64, st64 = bri.OverlapOp(L, W64, kl_n=n, tol=1e-12, nrhs=nrhs).apply(bd)
+    outm, stm = bri.OverlapOp(L, W64, kl_n=n, tol=1e-12, Wlo=Wlo, inner=bri.F32, nrhs=nrhs).apply(bd)
+    g64, gm = bri.spinor_to_host(out64), bri.spinor_to_host(outm)
+    for r in (0, 16, 32):
+        ref, _, _ = oracle.ov_apply(L, Wo, 1.0, n, b[r], tol=1e-13)
+        assert rel_l2(g64[r], ref) < TOL, r
+    for r in range(nrhs):
+        assert rel_l2(gm[r], g64[r]) < TOL, (r, stm.refine)
+    assert stm.refine >= 1 and max(stm.rel_resid) <= 1e-12 and max(st64.rel_resid) <= 1e-12

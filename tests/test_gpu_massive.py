@@ -299,3 +299,22 @@ def test_massless_solve(dense4):
     x, st = op.solve(bri.spinor_to_device(b[None]), 0.0, complete=True, tol=1e-11, max_iter=3000)
     want = np.linalg.solve(D, b.ravel()).reshape(b.shape)
     assert rel_l2(bri.spinor_to_host(x.reshape(1, 4, 3, -1))[0], want) < 1e-8, st.iters
+
+
+def test_solve_maximum_batch_with_zero_column(dense4):
+    """BRI_MAX_SOLVE_RHS sources side by side, one of them zero: every column against the dense
+    solve, the zero column stays zero."""
+    U, D, _ = dense4
+    op = _op(L4, U, N)
+    nrhs = bri.MAX_SOLVE_RHS
+    b = synth.gaussian_source(L4, synth.SOURCE_SEED_BASE + 40, nrhs=nrhs)
+    b[5] = 0.0
+    x, st = op.solve(bri.spinor_to_device(b), M, complete=True, tol=1e-11)
+    got = bri.spinor_to_host(x)
+    assert st.status == bri.OK and st.rel_resid < 1e-10
+    assert np.count_nonzero(got[5]) == 0
+    for r in range(nrhs):
+        if r != 5:
+            assert rel_l2(got[r], _dense_x(D, b[r], M, True)) < 1e-9, r
+    with pytest.raises(ValueError):
+        op.solve(bri.spinor_to_device(synth.gaussian_source(L4, 3, nrhs=nrhs + 1)), M)
