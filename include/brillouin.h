@@ -46,10 +46,11 @@ extern "C" {
 #endif
 
 /* lattice geometry; tbc = 1 makes the fermion field antiperiodic in t.
- * Accepted: L_mu in 1..4096, tbc 0 or 1, finite csw, and 360 V (432 V with the clover term)
- * below 2^31 entries, i.e. V <= 5 965 232 sites (4 971 026 with clover): 40^3 x 80 fits
- * without the clover term, 48^3 x 96 does not fit.  Every operator call also needs V to be a multiple of 64 (the
- * stencil tiles 64 sites per wave).  Anything else returns BRI_EINVAL. */
+ * Accepted: L_mu in 1..4096, tbc 0 or 1, finite csw, and V = L_0 L_1 L_2 L_3 < 2^31 sites
+ * (site indices are 32-bit, element offsets 64-bit; device memory is the practical bound:
+ * 5760 V bytes of FP64 links, e.g. 61 GB at 48^3 x 96).  Every operator call also needs V to
+ * be a multiple of 64 (the stencil tiles 64 sites per wave).  Anything else returns
+ * BRI_EINVAL. */
 typedef struct {
     int32_t L[4];
     int32_t tbc;

@@ -135,10 +135,10 @@ int geom_check(const bri_geom *geom, Geom *g) {
         g->L[mu] = geom->L[mu];
         V *= geom->L[mu];
     }
-    // the link array (40 slabs of 9 complex entries per site, plus 72 clover entries) must stay
-    // addressable by a 32-bit element offset
+    // site indices are 32-bit; every element offset into the link, clover, spinor and
+    // workspace arrays is formed in 64 bits
     if (!std::isfinite(geom->csw)) return BRI_EINVAL;
-    if (V * (geom->csw != 0.0 ? 432LL : 360LL) >= (1LL << 31)) return BRI_EINVAL;
+    if (V >= (1LL << 31)) return BRI_EINVAL;
     if (geom->tbc != 0 && geom->tbc != 1) return BRI_EINVAL;
     g->V = (int)V;
     g->tbc = geom->tbc;

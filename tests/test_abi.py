@@ -277,9 +277,16 @@ def test_clover_geometry_validated():
     w = (ctypes.c_double * 1)(1.0)
     assert lib.bri_link_grad(ctypes.byref(g), None, None, 1, w, None, None, None, None, None, ctypes.byref(nb),
                              None) == bri.EINVAL
-    # a lattice whose link array with the clover entries exceeds 32-bit offsets is refused
-    big = bri._geom((128, 128, 80, 4), 0, 1.0)  # 360 V fits 31 bits, 432 V does not
+    # site indices are 32-bit: V = 2^31 is refused, V = 2^31 - 2^24 is sized (query only)
+    big = bri._geom((4096, 4096, 128, 1), 0, 1.0)
     assert lib.bri_build_links(ctypes.byref(big), ctypes.c_void_p(256), ctypes.c_void_p(256), 0, None) == bri.EINVAL
+    prm0 = bri._OvParams(4, 1.0, 1e-12, 200, 0, 0)
+    for L, want in (((4096, 4096, 128, 1), bri.EINVAL), ((4096, 4096, 127, 1), bri.OK)):
+        nb = ctypes.c_size_t(0)
+        assert lib.ov_apply(ctypes.byref(bri._geom(L)), None, None, ctypes.byref(prm0), None, None, 1, None,
+                            ctypes.byref(nb), None, None) == want, L
+        if want == bri.OK:
+            assert nb.value >= 7 * 12 * 16 * (4096 * 4096 * 127)  # r, p, t, y and 3 shifted directions
 
 
 def test_massive_solve_nrhs_validated():

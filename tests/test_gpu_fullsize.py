@@ -1,5 +1,6 @@
 """Parity at the full lattice sizes of the workloads: 24^3x48 (mixed-precision overlap,
-links exp(0.7 i A) + 3 APE steps) and 32^3x64 (12 spin-colour point sources x 16 shifts).
+links exp(0.7 i A) + 3 APE steps) and 32^3x64 (12 spin-colour point sources x 16 shifts), and
+at 48^3x96, whose link array is past 32-bit element offsets.
 
 The oracle cannot hold the link array of these lattices, so the stencil is checked at
 sampled sites (every face and corner class plus random sites) against the oracle's
@@ -138,4 +139,43 @@ def test_batched_point_sources_32_64():
         err = float(torch.linalg.vector_norm(om[k] - out12[r]) / torch.linalg.vector_norm(out12[r]))
         assert err < 1e-10, (r, err)
     del opm, Wlo
+    torch.cuda.empty_cache()
+
+
+def test_lattice_past_32_bit_link_offsets_48_96():
+    """48^3x96, 10.6 M sites: the FP64 link array holds 360 V = 3.8e9 complex entries (61 GB),
+    past 32-bit element offsets.  The FP64 and FP32 stencils and their adjoints at sampled sites
+    against the oracle, then sign(H)^2 = 1 and Ginsparg-Wilson through the overlap apply."""
+    need_gpu()
+    L = (48, 48, 48, 96)
+    seed = synth.LINK_SEED_BASE + 5
+    U, Ud = _links(L, 0.7, seed)
+    rng = np.random.default_rng(seed)
+    psi = synth.gaussian_source(L, seed + 1)
+    sites = _sites(L, rng, n_random=16)
+    Uh = U.cpu().numpy()
+    del U
+    m0 = -1.0
+    ref = oracle.dirac_at(L, Uh, 0, m0, psi[0], sites)
+    refd = oracle.dirac_adj_at(L, Uh, 0, m0, psi[0], sites)
+    del Uh
+    scale, scaled = np.abs(ref).max(), np.abs(refd).max()
+    idx = torch.tensor(sites, device="cuda")
+    for prec, tol in ((bri.F32, 1e-5), (bri.F64, 1e-13)):
+        W = bri.build_links(L, Ud, prec)
+        p = bri.spinor_to_device(psi, prec)
+        got = bri.apply(L, W, prec, m0, p)[0][:, :, idx].permute(2, 0, 1).cpu().numpy().astype(np.complex128)
+        gotd = bri.apply_dag(L, W, prec, m0, p)[0][:, :, idx].permute(2, 0, 1).cpu().numpy().astype(np.complex128)
+        assert np.abs(got - ref).max() <= tol * scale, prec
+        assert np.abs(gotd - refd).max() <= tol * scaled, prec
+        del p
+        if prec == bri.F32:
+            del W
+            torch.cuda.empty_cache()
+    del Ud
+    b = bri.spinor_to_device(psi)
+    op = bri.OverlapOp(L, W, kl_n=16, tol=1e-12, max_iter=5000)
+    _, st = _identities(op, b, 1e-9)
+    assert 10 < st.iters < 2000
+    del op, W, b
     torch.cuda.empty_cache()
