@@ -48,8 +48,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
             objs.append(obj)
-            if len([p for _, p in procs if p.poll() is None]) >= jobs:
-                procs[0][1].wait()
+            running = [p for _, p in procs if p.poll() is None]
+            if len(running) >= jobs:
+                running[0].wait()  # at most `jobs` compilers at a time
         failed = []
         for src, p in procs:
             out, _ = p.communicate()
