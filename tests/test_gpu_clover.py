@@ -86,3 +86,60 @@ def test_clover_overlap_4_4(kernel):
     ref0, _, _ = oracle.ov_apply(L, Wo if kernel == bri.KERNEL_BRILLOUIN else oracle.WilsonKernel(U), 1.0, 6,
                                  b[0], tol=1e-13)
     assert rel_l2(ref, ref0) > 1e-3
+
+
+def test_clover_every_brillouin_config():
+    """With c_SW != 0 every launch configuration the tuner may pick (1-RHS splits, R = 1..4
+    right-hand sides per thread, tiles and traversals) matches the oracle, FP64 and FP32."""
+    import itertools
+
+    from tests._gpu import torch
+
+    need_gpu()
+    L = (16, 8, 8, 6)
+    U = synth.random_links(L, 0.6, 4243)
+    Wo = oracle.links(L, U)
+    K = oracle.BrillouinKernel(Wo, oracle.clover_field(L, U, CSW))
+    nrhs = 5
+    psi = synth.gaussian_source(L, 4244, nrhs=nrhs)
+    ref = oracle.dirac(L, K, -0.9, psi)
+    trav = [(0, 0, 0, 0, 0), (16, 4, 1, 1, 4), (8, 8, 1, 1, 2)]
+    for prec, tol in ((bri.F64, 1e-14), (bri.F32, 1e-6)):
+        W = _W(L, U, prec)
+        x = bri.spinor_to_device(psi, prec)
+        try:
+            for t, rpt, xcd in itertools.product(trav, (1, 2, 3, 4), (0, 1)):
+                cfg = bri.StencilCfg(t[0], t[1], t[2], t[3], t[4], 4, rpt, xcd)
+                bri.set_stencil_cfg(L, prec, nrhs, cfg)
+                got = bri.spinor_to_host(bri.apply(L, W, prec, -0.9, x))
+                assert rel_l2(got, ref) < tol, (prec, cfg.as_dict())
+        finally:
+            bri.set_stencil_cfg(L, prec, nrhs, None)
+        del W, x
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kernel", ["bri", "wil"])
+def test_clover_wide_batches_match_single_launches(kernel):
+    """16^3x64 has 4096 tiles, where the default multi-RHS launch carries R = 4 (8 sources) or
+    R = 3 (6 sources) per thread: with the clover term, for both kernels and FP64 / FP32, every
+    batched column equals the single-source launch (oracle-checked above)."""
+    from tests._gpu import torch
+
+    need_gpu()
+    L = (16, 16, 16, 64)
+    U = synth.random_links(L, 0.4, 4245)
+    Ud = bri.links_to_device(U)
+    fn = bri.apply if kernel == "bri" else bri.wilson_apply
+    for prec in (bri.F64, bri.F32):
+        W = bri.build_links(L, Ud, prec, csw=CSW)
+        for nrhs in (8, 6):
+            assert bri.get_stencil_cfg(L, prec, nrhs).rpt == (4 if nrhs == 8 else 3)
+            x = bri.spinor_to_device(synth.gaussian_source(L, 4246 + nrhs, nrhs=nrhs), prec)
+            out = fn(L, W, prec, -0.9, x)
+            for r in range(nrhs):
+                one = fn(L, W, prec, -0.9, x[r:r + 1].contiguous())
+                err = float(torch.linalg.vector_norm(out[r] - one[0]) / torch.linalg.vector_norm(one[0]))
+                assert err < (1e-14 if prec == bri.F64 else 1e-6), (prec, nrhs, r, err)
+        del W
+        torch.cuda.empty_cache()
