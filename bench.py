@@ -561,6 +561,29 @@ def main():
             "applies_per_s": 1 / (ms_r / 1e3), "ms_per_call": ms_r, "cg_iterations": str_.iters,
             "rel_diff_vs_strict": float(torch.linalg.vector_norm(orl - ref64) / torch.linalg.vector_norm(ref64))}
         del opr, orl
+        # the first upper-diagonal rational g_{2n} (Sec. 3.3; no constant term), n = KL_N shifts
+        opu = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, kind=bri.KL_UPPER)
+        ou = torch.empty_like(b)
+        _, stu = opu.apply(b, out=ou)
+        ms_u = timed(lambda: opu.apply(b, out=ou), 10)
+        extra["upper_diagonal_fp64_1src"] = {
+            "applies_per_s": 1 / (ms_u / 1e3), "ms_per_call": ms_u, "cg_iterations": stu.iters,
+            "rel_diff_vs_diagonal": float(torch.linalg.vector_norm(ou - ref64) / torch.linalg.vector_norm(ref64))}
+        del opu, ou
+        # the clover-improved Brillouin kernel, c_SW = 1: 72 clover entries per site after the 40
+        # link slabs (7296 B/site algorithmic in FP64), and its overlap apply
+        Wc = bri.build_links(L, U, bri.F64, csw=1.0)
+        for _ in range(5):
+            bri.apply(L, Wc, bri.F64, -RHO, t_in, out=t_out)
+        ms_c = timed(lambda: bri.apply(L, Wc, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps)
+        opc = bri.OverlapOp(L, Wc, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+        oc = torch.empty_like(b)
+        _, stc = opc.apply(b, out=oc)
+        ms_oc = timed(lambda: opc.apply(b, out=oc), 10)
+        extra["clover_fp64_1src"] = {
+            "csw": 1.0, "stencil_us": ms_c * 1e3, "stencil_GBps_alg": 7296 * V / (ms_c * 1e-3) / 1e9,
+            "overlap_applies_per_s": 1 / (ms_oc / 1e3), "overlap_ms_per_call": ms_oc, "cg_iterations": stc.iters}
+        del Wc, opc, oc
         # massive overlap solve, complete form of Sec. 4 with the BiCGstab outer solver, am = 0.05
         xs, sts = op.solve(b, MASS, complete=True, tol=OUTER_TOL)
         ms_s = timed(lambda: op.solve(b, MASS, complete=True, tol=OUTER_TOL), 1)
