@@ -23,6 +23,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extr
        python bench.py --stencil-only     (copy calibration + stencil launches, for counters)
        python bench.py --stencil-only --lattice 32,32,32,64   (the same on a larger workload lattice)
        python bench.py --stencil-only --stencil-rhs 12        (plus the multi-RHS kernel, FP64 and FP32)
+       python bench.py --batched-only --steps 5 --warmup 1    (12-source FP64 apply only, for traces)
 """
 
 from __future__ import annotations
@@ -106,6 +107,8 @@ def parse():
     ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
     ap.add_argument("--stencil-rhs", type=int, default=1,
                     help="with --stencil-only: also launch the multi-RHS kernel on this many RHS (FP64 and FP32)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 12-source FP64 overlap apply, --steps times (for kernel traces)")
     ap.add_argument("--lattice", default=None,
                     help="with --stencil-only: another lattice, e.g. 32,32,32,64 (links exp(0.7iA) + 3 APE "
                          "built on the device)")
@@ -400,6 +403,20 @@ def main():
                 rec[f"mrhs_{name}_{nr}rhs"] = {"us": ms * 1e3, "config": bri.get_stencil_cfg(L, prec, nr).as_dict()}
                 del Wp, xm, ym
         print(json.dumps(rec), flush=True)
+        return
+
+    if args.batched_only:
+        # the 12 spin-colour point sources side by side, one multi-shift with per-column scalars
+        b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
+        o12 = torch.empty_like(b12)
+        op12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, nrhs=12)
+        for _ in range(args.warmup):
+            op12.apply(b12, out=o12)
+        ms = timed(lambda: op12.apply(b12, out=o12), args.steps)
+        _, st12 = op12.apply(b12, out=o12)
+        print(json.dumps({"batched_only": True, "sources": 12, "calls": args.steps, "ms_per_call": ms,
+                          "applies_per_s": 12 / (ms / 1e3), "cg_iterations": st12.iters,
+                          "config": bri.get_stencil_cfg(L, bri.F64, 12).as_dict()}), flush=True)
         return
 
     op = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
