@@ -108,7 +108,7 @@ int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, voi
  *   W   : [40][3][3][V] in precision prec (F64: double; F32: float;
  *         F32_BF16W: bfloat16 links with float spinors)
  *   in, out : [nrhs][4][3][V], complex double for BRI_F64, complex float
- *         otherwise; in and out must not overlap.
+ *         otherwise; in and out must not overlap (BRI_EINVAL if they do).
  */
 int bri_apply(const bri_geom *geom, const void *W, int prec, double m0, const void *in, void *out, int nrhs,
               void *stream);
@@ -187,7 +187,8 @@ typedef struct {
  * FP64 residual (formed with W64) until it meets tol.
  *   W64 : [40][3][3][V] complex double off-axis links ([48]... with the clover term)
  *   Wlo : links in precision `inner` (from bri_build_links); NULL when inner = BRI_F64
- *   in, out : [nrhs][4][3][V] complex double (device); must not overlap
+ *   in, out : [nrhs][4][3][V] complex double (device); must not overlap each other or the
+ *         used part of the workspace (BRI_EINVAL if they do)
  *   work, work_bytes : device workspace; with work == NULL the call only writes
  *         the required size into *work_bytes and returns BRI_OK.
  *   stats : may be NULL.
@@ -263,7 +264,8 @@ typedef struct {
  *   mp    : mass, form, outer tolerance and iteration cap
  *   nprec, prec : preconditioner chain, 0..BRI_MAX_LEVELS levels (prec may be NULL for 0);
  *          prec[0] preconditions the outer operator, prec[k+1] preconditions prec[k]
- *   in    : b, [nrhs][4][3][V] complex double;  out : x, same layout, must not overlap in
+ *   in    : b, [nrhs][4][3][V] complex double;  out : x, same layout; in, out and the used
+ *           workspace must not overlap (BRI_EINVAL if they do)
  *   nrhs  : 1..BRI_MAX_SOLVE_RHS
  *   work, work_bytes : device workspace (query with work == NULL)
  *   stats : may be NULL

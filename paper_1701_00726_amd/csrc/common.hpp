@@ -45,6 +45,12 @@ enum KernelKind { KERN_BRI = BRI_KERNEL_BRILLOUIN, KERN_WIL = BRI_KERNEL_WILSON 
 // diagonal of the operator without the bare mass: 15/8 (Brillouin), 4 (Wilson)
 inline double kernel_diag(int kind) { return kind == KERN_WIL ? 4.0 : 15.0 / 8.0; }
 
+// true when the byte ranges [a, a + na) and [b, b + nb) share a byte (argument aliasing checks)
+inline bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
 // ---------------------------------------------------------- stencil weights
 //
 // S_d = a_k + c_k sum_mu d_mu gamma_mu for a k-hop displacement d (k >= 1),

@@ -460,7 +460,13 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
         *work_bytes = need;
         return BRI_OK;
     }
-    if (*work_bytes < need || !W64 || !in || !out || in == out || ((low || lo_kernel) && !Wlo)) return BRI_EINVAL;
+    if (*work_bytes < need || !W64 || !in || !out || ((low || lo_kernel) && !Wlo)) return BRI_EINVAL;
+    {
+        const size_t vbytes = (size_t)12 * g.V * nrhs * sizeof(double2);
+        if (ranges_overlap(in, vbytes, out, vbytes) || ranges_overlap(in, vbytes, work, need) ||
+            ranges_overlap(out, vbytes, work, need))
+            return BRI_EINVAL;
+    }
 
     Cascade c;
     c.geom = geom;

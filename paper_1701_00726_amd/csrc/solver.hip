@@ -885,6 +885,12 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
         return BRI_OK;
     }
     if (*work_bytes < pl.bytes || !W64 || !in || !out || (pl.mixed && !Wlo)) return BRI_EINVAL;
+    {
+        const size_t vb = (size_t)12 * g.V * nrhs * sizeof(double2);
+        if (ranges_overlap(in, vb, out, vb) || ranges_overlap(in, vb, work, pl.bytes) ||
+            ranges_overlap(out, vb, work, pl.bytes))
+            return BRI_EINVAL;
+    }
     plan_overlap(pl, g, prm, nrhs, W64, Wlo, work);
     hipStream_t s = (hipStream_t)stream;
     const size_t nel = (size_t)12 * g.V;

@@ -135,6 +135,8 @@ static int apply_common(const bri_geom *geom, const void *W, int prec, double m0
     if (rc != BRI_OK) return rc;
     if (!W || !in || !out || nrhs < 1 || nrhs > 65535 || a.g.V % 64) return BRI_EINVAL;
     if (prec != BRI_F64 && prec != BRI_F32 && prec != BRI_F32_BF16W) return BRI_EINVAL;
+    const size_t sb = (size_t)12 * a.g.V * nrhs * (prec == BRI_F64 ? 16 : 8);
+    if (ranges_overlap(in, sb, out, sb)) return BRI_EINVAL;  // neighbours are read while out is written
     a.W = W;
     a.in = in;
     a.out = out;

@@ -351,3 +351,36 @@ def test_binding_rejects_mismatched_outputs():
     op = bri.OverlapOp(L, W, kl_n=4)
     with pytest.raises(ValueError, match="out must be"):
         op.apply(psi, out=torch.zeros((1, 4, 3, V), dtype=torch.complex64))
+
+
+def test_aliased_arguments_rejected():
+    """in / out (and the workspace) must not overlap: the stencil reads neighbours of in while it
+    writes out, and the solvers keep vectors in the workspace.  Refused before any launch."""
+    lib = bri.load()
+    g = bri._geom((4, 4, 4, 4))
+    sb = 12 * 256 * 16  # one complex-double spinor
+    base = 1 << 20
+    for off in (0, 16, sb - 16):  # identical, shifted by one entry, overlapping tails
+        assert lib.bri_apply(ctypes.byref(g), ctypes.c_void_p(base), 0, -1.0, ctypes.c_void_p(base),
+                             ctypes.c_void_p(base + off), 1, None) == bri.EINVAL, off
+        assert lib.wil_apply_dag(ctypes.byref(g), ctypes.c_void_p(base), 0, -1.0, ctypes.c_void_p(base + off),
+                                 ctypes.c_void_p(base), 1, None) == bri.EINVAL, off
+    prm = bri._OvParams(4, 1.0, 1e-12, 200, 0, 0)
+    nb = ctypes.c_size_t(0)
+    assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb),
+                        None, None) == bri.OK
+    work = base + 64 * sb
+    for inp, out in ((base, base), (base, base + sb // 2), (base, work + 256), (work, base)):
+        wb = ctypes.c_size_t(nb.value)
+        for fn in (lib.ov_apply, lib.ov_sign_apply):
+            assert fn(ctypes.byref(g), ctypes.c_void_p(base + 32 * sb), None, ctypes.byref(prm), ctypes.c_void_p(inp),
+                      ctypes.c_void_p(out), 1, ctypes.c_void_p(work), ctypes.byref(wb), None, None) == bri.EINVAL
+    mp_ = bri._MassParams(0.1, 1, 1e-10, 100)
+    sz = ctypes.c_size_t(0)
+    assert lib.ov_solve(ctypes.byref(g), None, None, ctypes.byref(prm), ctypes.byref(mp_), 0, None, None, None, 1,
+                        None, ctypes.byref(sz), None, None) == bri.OK
+    for inp, out in ((base, base + 16), (base, work + 256)):
+        wb = ctypes.c_size_t(sz.value)
+        assert lib.ov_solve(ctypes.byref(g), ctypes.c_void_p(base + 32 * sb), None, ctypes.byref(prm),
+                            ctypes.byref(mp_), 0, None, ctypes.c_void_p(inp), ctypes.c_void_p(out), 1,
+                            ctypes.c_void_p(work), ctypes.byref(wb), None, None) == bri.EINVAL
