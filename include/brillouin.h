@@ -90,7 +90,8 @@ typedef enum {
  * blocks (spins 0,1 and 2,3), 6x6 entries each, index 3*spin + colour within the block.
  *   U  : [4][3][3][V] complex double (device, read)
  *   W  : [40][3][3][V] (csw = 0) or [48][3][3][V] (csw != 0) in precision wprec (device, written)
- * Returns BRI_EINVAL for a geometry outside the limits stated at bri_geom or a null pointer,
+ * Returns BRI_EINVAL for a geometry outside the limits stated at bri_geom, a null pointer or W
+ * overlapping U,
  * BRI_EHIP on a HIP failure.  Asynchronous on `stream` for wprec = BRI_F64; for the lower
  * precisions a temporary FP64 buffer of 5760*V bytes (6912*V with the clover term) is
  * allocated, and the call synchronises `stream` before freeing it.
@@ -366,7 +367,8 @@ int bri_kl_upper_coeffs(int n, double *omega, double *sigma);
  *           (at least one of the two); both overwritten
  *   work, work_bytes: device workspace of 81 * 9 * V complex doubles; with
  *           work == NULL the call only writes the size into *work_bytes.
- * Asynchronous on `stream`.  BRI_EINVAL for bad geometry, npairs or pointers.
+ * Asynchronous on `stream`.  BRI_EINVAL for bad geometry, npairs or pointers, or when F, GU
+ * or work overlap each other or an input.
  */
 int bri_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs, const double *weights,
                   const void *u, const void *v, void *F, void *GU, void *work, size_t *work_bytes, void *stream);
@@ -399,7 +401,8 @@ int wil_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs
  *           each shift (worst of the two columns)
  * Synchronises `stream`.  Returns BRI_ENOCONV when a shift missed tol within
  * max_iter (the outputs then use the last iterates), BRI_ENAN on a non-finite
- * residual, BRI_EINVAL for bad arguments (V must be a multiple of 64).
+ * residual, BRI_EINVAL for bad arguments (V must be a multiple of 64; F, GU, gpsi and work must
+ * not overlap each other or an input).
  */
 int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const void *Wlo, const ov_params *params,
                   const void *chi, const void *psi, void *F, void *GU, void *gpsi, void *work, size_t *work_bytes,

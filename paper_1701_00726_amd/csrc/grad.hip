@@ -487,6 +487,21 @@ static int link_grad_impl(const bri_geom *geom, const void *U, const void *W, in
         return BRI_OK;
     }
     if (*work_bytes < need || !U || !W || !weights || !u || !v || (!F && !GU)) return BRI_EINVAL;
+    {
+        // the outputs and the workspace must not alias each other or any input
+        const size_t V = (size_t)g.V, sp = (size_t)npairs * 192 * V;
+        const void *ins[4] = {U, W, u, v};
+        const size_t inb[4] = {576 * V, 5760 * V, sp, sp};
+        const void *outs[3] = {F, GU, work};
+        const size_t outb[3] = {256 * V, 576 * V, need};
+        for (int i = 0; i < 3; ++i) {
+            if (!outs[i]) continue;
+            for (int k = 0; k < 4; ++k)
+                if (ranges_overlap(outs[i], outb[i], ins[k], inb[k])) return BRI_EINVAL;
+            for (int k = i + 1; k < 3; ++k)
+                if (outs[k] && ranges_overlap(outs[i], outb[i], outs[k], outb[k])) return BRI_EINVAL;
+        }
+    }
     PairTable pt;
     std::memset(&pt, 0, sizeof(pt));
     pt.n = npairs;
@@ -531,6 +546,21 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     if (*work_bytes < pl.bytes || !U || !W64 || !chi || !psi || (!F && !GU) || !gpsi ||
         (prm->inner != BRI_F64 && !Wlo))
         return BRI_EINVAL;
+    {
+        // the outputs and the workspace must not alias each other or any input
+        const size_t V = (size_t)g.V;
+        const void *ins[4] = {U, W64, chi, psi};
+        const size_t inb[4] = {576 * V, 5760 * V, 192 * V, 192 * V};
+        const void *outs[4] = {F, GU, gpsi, work};
+        const size_t outb[4] = {256 * V, 576 * V, 192 * V, pl.bytes};
+        for (int i = 0; i < 4; ++i) {
+            if (!outs[i]) continue;
+            for (int k = 0; k < 4; ++k)
+                if (ranges_overlap(outs[i], outb[i], ins[k], inb[k])) return BRI_EINVAL;
+            for (int k = i + 1; k < 4; ++k)
+                if (outs[k] && ranges_overlap(outs[i], outb[i], outs[k], outb[k])) return BRI_EINVAL;
+        }
+    }
     hipStream_t s = (hipStream_t)stream;
     const size_t nel = (size_t)12 * g.V;
     char *base = (char *)work;

@@ -293,6 +293,8 @@ extern "C" int bri_build_links(const bri_geom *geom, const void *U, void *W, int
     if (st != BRI_OK) return st;
     if (!U || !W) return BRI_EINVAL;
     if (wprec != BRI_F64 && wprec != BRI_F32 && wprec != BRI_F32_BF16W) return BRI_EINVAL;
+    const size_t wbytes = link_entries(g) * (wprec == BRI_F64 ? 16 : (wprec == BRI_F32 ? 8 : 4));
+    if (ranges_overlap(U, (size_t)576 * g.V, W, wbytes)) return BRI_EINVAL;  // W is written while U is read
     hipStream_t s = (hipStream_t)stream;
     if (wprec == BRI_F64) {
         st = build_links_f64(g, (const double2 *)U, (double2 *)W, s);

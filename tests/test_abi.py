@@ -384,3 +384,38 @@ def test_aliased_arguments_rejected():
         assert lib.ov_solve(ctypes.byref(g), ctypes.c_void_p(base + 32 * sb), None, ctypes.byref(prm),
                             ctypes.byref(mp_), 0, None, ctypes.c_void_p(inp), ctypes.c_void_p(out), 1,
                             ctypes.c_void_p(work), ctypes.byref(wb), None, None) == bri.EINVAL
+
+
+def test_aliased_link_and_gradient_arguments_rejected():
+    """The link build and the gradients refuse outputs or workspace that alias an input (or each
+    other); all refused before any launch."""
+    lib = bri.load()
+    L = (4, 4, 4, 4)
+    V = 256
+    g = bri._geom(L)
+    P = ctypes.c_void_p
+    U, Wl = 1 << 24, 1 << 26  # disjoint stand-in addresses, never dereferenced
+    # W written over U
+    assert lib.bri_build_links(ctypes.byref(g), P(U), P(U + 64), 0, None) == bri.EINVAL
+    assert lib.bri_build_links(ctypes.byref(g), P(U), P(U - 1000), 2, None) == bri.EINVAL
+    # link force: F over u, GU over W, work over v, F over GU
+    w = (ctypes.c_double * 1)(1.0)
+    nb = ctypes.c_size_t(0)
+    assert lib.bri_link_grad(ctypes.byref(g), None, None, 1, w, None, None, None, None, None, ctypes.byref(nb),
+                             None) == bri.OK
+    u, v, F, GU, work = 1 << 28, (1 << 28) + (1 << 22), 1 << 30, (1 << 30) + (1 << 22), 1 << 32
+    for args in ((u, v, u + 16, None, work), (u, v, None, Wl, work), (u, v, F, None, v), (u, v, F, F + 8, work)):
+        wb = ctypes.c_size_t(nb.value)
+        assert lib.bri_link_grad(ctypes.byref(g), P(U), P(Wl), 1, w, P(args[0]), P(args[1]),
+                                 P(args[2]) if args[2] else None, P(args[3]) if args[3] else None, P(args[4]),
+                                 ctypes.byref(wb), None) == bri.EINVAL, args
+    # overlap gradient: D_ov^dag chi written over chi, F over psi, work over U
+    prm = bri._OvParams(4, 1.0, 1e-10, 100, 0, 0)
+    nbg = ctypes.c_size_t(0)
+    assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None,
+                             None, ctypes.byref(nbg), None, None) == bri.OK
+    chi, psi, gpsi = 1 << 28, (1 << 28) + (1 << 22), (1 << 28) + (2 << 22)
+    for c, p, f, gp, wk in ((chi, psi, F, chi, work), (chi, psi, psi, gpsi, work), (chi, psi, F, gpsi, U)):
+        wb = ctypes.c_size_t(nbg.value)
+        assert lib.ov_apply_grad(ctypes.byref(g), P(U), P(Wl), None, ctypes.byref(prm), P(c), P(p), P(f), None,
+                                 P(gp), P(wk), ctypes.byref(wb), None, None) == bri.EINVAL
