@@ -86,3 +86,45 @@ def test_graph_gradient_matches_eager():
         _eager_noise()
         F, _, g, _ = op.grad(Ud, chi, psi)
         assert torch.equal(F, F0) and torch.equal(g, g0)
+
+
+def test_graph_cache_eviction_and_concurrent_threads():
+    """More solve layouts than the graph cache holds (every operator has its own workspace, so
+    its own graphs): evicted graphs are captured again and give the same bits; then two host
+    threads apply their operators at once on their own streams (graphs are looked up, captured
+    and launched under the cache lock), every result bit for bit the eager one."""
+    import threading
+
+    need_gpu()
+    L = (4, 4, 4, 4)
+    U, _ = field(L, "cfg1")
+    W = bri.build_links(L, bri.links_to_device(U), bri.F64)
+    b = bri.spinor_to_device(synth.gaussian_source(L, synth.SOURCE_SEED_BASE + 9))
+    bri.set_solver_graphs(False)
+    ref, _ = bri.OverlapOp(L, W, kl_n=8, tol=1e-12).apply(b)
+    bri.set_solver_graphs(True)
+    ops = [bri.OverlapOp(L, W, kl_n=8, tol=1e-12) for _ in range(20)]
+    for op in ops + ops[::-1]:
+        out, _ = op.apply(b)
+        assert torch.equal(out, ref)
+        _eager_noise()
+    errors = []
+
+    def work(op, stream):
+        try:
+            with torch.cuda.stream(stream):
+                for _ in range(6):
+                    out, _ = op.apply(b, stream=stream)
+                    stream.synchronize()
+                    if not torch.equal(out, ref):
+                        errors.append("mismatch")
+        except Exception as e:  # reported below, the thread must not die silently
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(ops[i], torch.cuda.Stream())) for i in (0, 17)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
