@@ -183,7 +183,10 @@ def survey(torch, bri, synth):
                 print(f"[survey] {L} {key} {us:.1f} us", file=sys.stderr, flush=True)
         b1 = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED), bri.F64)
         b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64)
-        for nm, inner, b in (("fp64_1src", bri.F64, b1), ("fp64_12src", bri.F64, b12), ("mixed_f32_1src", bri.F32, b1)):
+        # the last row keeps every (shift, source) solution in FP64 for the refinement: 16 x 12 columns,
+        # 77 GB at 32^3x64, ~210 GB of HBM with the FP32 multi-shift and the link arrays
+        for nm, inner, b in (("fp64_1src", bri.F64, b1), ("fp64_12src", bri.F64, b12), ("mixed_f32_1src", bri.F32, b1),
+                             ("mixed_f32_12src", bri.F32, b12)):
             op = bri.OverlapOp(L, W[bri.F64], kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000,
                                Wlo=None if inner == bri.F64 else W[inner], inner=inner, nrhs=b.shape[0])
             op.apply(b)
