@@ -290,7 +290,15 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  * block row with nsplit = 1, 2 or 4 waves sharing the 80 displacements;
  * rpt = 1..4: rpt right-hand sides per thread, four waves sharing the
  * displacements, nsplit ignored) and xcd = 1 to give each XCD a
- * contiguous range of tiles.
+ * contiguous range of tiles.  variant selects the kernel for one right-hand
+ * side per block row (rpt = 0; Brillouin kernel only for 1 and 2):
+ *   0  the 64-site tile kernel described above;
+ *   1  t-streaming: a block of 256 threads owns a tile_x x tile_y x tile_z tile of
+ *      the xyz volume (product 256, each dividing its extent) and walks tile_t
+ *      consecutive t-slices (dividing L_t), reading both uses of every stored
+ *      link inside one slice; col_z and nsplit are ignored;
+ *   2  x-line: as 0 with tile_x = L_x (whole x-lines in every wave), the three
+ *      x-displacements of each (dy, dz, dt) sharing one spinor load.
  */
 typedef struct {
     int tile_x, tile_y, tile_z, tile_t;
@@ -298,6 +306,7 @@ typedef struct {
     int nsplit;
     int rpt;
     int xcd;
+    int variant;
 } bri_stencil_cfg;
 
 /* bri_stencil_time -- average time of `reps` back-to-back bri_apply launches

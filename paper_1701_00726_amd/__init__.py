@@ -118,6 +118,7 @@ class StencilCfg(ctypes.Structure):
         ("nsplit", ctypes.c_int),
         ("rpt", ctypes.c_int),
         ("xcd", ctypes.c_int),
+        ("variant", ctypes.c_int),
     ]
 
     def as_dict(self):

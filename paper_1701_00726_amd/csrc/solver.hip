@@ -660,7 +660,8 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
                (uint64_t)(uintptr_t)s.r, (uint64_t)(uintptr_t)s.p, (uint64_t)(uintptr_t)s.t,
                (uint64_t)(uintptr_t)s.y, (uint64_t)(uintptr_t)s.x, (uint64_t)(uintptr_t)s.ps,
                (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1], (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3],
-               (uint64_t)cfg.colz, (uint64_t)cfg.nsplit, (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap};
+               (uint64_t)cfg.colz, (uint64_t)cfg.nsplit, (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap,
+               (uint64_t)cfg.variant};
     }
 
     int it = 0;

@@ -15,8 +15,23 @@ hipError_t launch_bf16_wil(const StencilArgs &, bool, int, const StencilConfig &
 // A 64-site tile that divides the lattice.  Column traversal: tile
 // tile[0] x tile[1] x 1 x 1 with colz | Lz.  Otherwise x first (coalescing),
 // then y, z, t.
-int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
+static int plan_tile_base(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
     if (g.V % 64) return BRI_EINVAL;
+    if (cfg.variant == VAR_TSTREAM) {
+        // t-streaming: an xyz tile of STREAM_THREADS sites and chunks of tile[3] t-slices
+        if (cfg.rpt != 0) return BRI_EINVAL;
+        int prod = 1;
+        for (int mu = 0; mu < 4; ++mu) {
+            if (cfg.tile[mu] < 1 || g.L[mu] % cfg.tile[mu]) return BRI_EINVAL;
+            if (mu < 3) prod *= cfg.tile[mu];
+        }
+        if (prod != STREAM_THREADS) return BRI_EINVAL;
+        for (int mu = 0; mu < 4; ++mu) {
+            tile[mu] = cfg.tile[mu];
+            nb[mu] = g.L[mu] / tile[mu];
+        }
+        return BRI_OK;
+    }
     if (cfg.colz > 0) {
         const int tx = cfg.tile[0], ty = cfg.tile[1];
         if (tx < 1 || ty < 1 || tx * ty != 64 || g.L[0] % tx || g.L[1] % ty || g.L[2] % cfg.colz) return BRI_EINVAL;
@@ -59,12 +74,22 @@ int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
     return BRI_OK;
 }
 
+// the tile plan, and for the x-line kernel the requirement that a tile spans whole x-lines
+int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
+    const int rc = plan_tile_base(g, cfg, tile, nb);
+    if (rc != BRI_OK) return rc;
+    if (cfg.variant == VAR_XLINE && (tile[0] != g.L[0] || cfg.rpt != 0)) return BRI_EINVAL;
+    if (cfg.variant < VAR_STANDARD || cfg.variant > VAR_XLINE) return BRI_EINVAL;
+    return BRI_OK;
+}
+
 int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilConfig &cfg, hipStream_t st) {
     if (a.ncol < 1 || a.ncol > 65535) return BRI_EINVAL;
     int rc = plan_tile(a.g, cfg, a.tile, a.nb);
     if (rc != BRI_OK) return rc;
     a.colz = cfg.colz;
     a.xcd_remap = cfg.xcd_remap;
+    a.nslots = a.g.V / 64;
     if (a.kind != KERN_BRI && a.kind != KERN_WIL) return BRI_EINVAL;
     const bool wil = a.kind == KERN_WIL;
     hipError_t e;
@@ -119,6 +144,19 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
         // large ones keeps fewer tiles (and their link lines) in flight per XCD than two waves do
         c.rpt = 0;
         c.nsplit = 4;
+        // large lattices whose x-lines fit a wave: the x-line kernel (one spinor load per three
+        // x-displacements).  At 32^3x64 it measured 4.15 / 2.08 / 1.49 ms (FP64 / FP32 /
+        // bfloat16 links) against 5.52 / 3.37 / 2.64 ms for the column traversal above, with
+        // lexicographic whole-line tiles and no XCD remap fastest; at 16^4 the two tie.
+        if (kind == KERN_BRI && g.V / 64 >= 8192 && (g.L[0] == 16 || g.L[0] == 32 || g.L[0] == 64) &&
+            g.L[1] % (64 / g.L[0]) == 0) {
+            c.variant = VAR_XLINE;
+            c.tile[0] = g.L[0];
+            c.tile[1] = 64 / g.L[0];
+            c.tile[2] = c.tile[3] = 1;
+            c.colz = 0;
+            c.xcd_remap = 0;
+        }
     }
     return c;
 }

@@ -39,11 +39,13 @@ enum EpiMode {
 
 struct StencilArgs {
     Geom g;
-    int tile[4];  // 64-site tile extents
+    int tile[4];  // 64-site tile extents (t-streaming: xyz tile of 256 sites and the t-chunk length)
     int nb[4];    // tiles per axis
     int colz;     // column traversal depth in z (0 = lexicographic tiles)
     int xcd_remap;
     int ncol;     // columns (right-hand sides); column c lives at offset c * 12 V
+    int nslots;   // partial-sum slots per column the reductions read (V / 64); a kernel with fewer
+                  // blocks zeroes the slots it does not fill
     const void *W;
     const void *in;
     void *out;
@@ -67,7 +69,18 @@ struct StencilConfig {
     int nsplit;     // 1-RHS kernel: waves per 64-site tile (1, 2, 4)
     int rpt;        // multi-RHS kernel: right-hand sides per thread (0 = use the 1-RHS kernel)
     int xcd_remap;  // 1 = give each XCD a contiguous range of tiles
+    int variant = 0;  // 1-RHS kernel variant (rpt must be 0 for 1 and 2):
+                      //   VAR_STANDARD  the 64-site tile kernel above;
+                      //   VAR_TSTREAM   t-streaming: xyz tile tile[0..2] (256 sites), chunks of
+                      //                 tile[3] t-slices;
+                      //   VAR_XLINE     64-site tiles spanning whole x-lines (tile[0] = L_x): the
+                      //                 three x-displacements of every (dy, dz, dt) share one
+                      //                 spinor load, the x-neighbours come by cross-lane moves
 };
+
+enum StencilVariant { VAR_STANDARD = 0, VAR_TSTREAM = 1, VAR_XLINE = 2 };
+
+constexpr int STREAM_THREADS = 256;  // sites (threads) per block of the t-streaming kernel
 
 // process-wide table of tuned configurations, keyed by lattice, precision and
 // number of columns; default_config consults it first

@@ -105,6 +105,25 @@ __device__ __forceinline__ void transport(typename Cx<typename LS::R>::T (&chi)[
         }
 }
 
+// chi = w p (ADJ: w^dag p) with link and spinor both in registers
+template <typename C, typename R, bool ADJ>
+__device__ __forceinline__ void transport_vals(C (&chi)[4][3], const C (&w)[3][3], const C (&p)[4][3]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C v = cmake<C>((R)0, (R)0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (ADJ)
+                    cmac_conj(v, w[b][a], p[s][b]);
+                else
+                    cmac(v, w[a][b], p[s][b]);
+            }
+            chi[s][a] = v;
+        }
+}
+
 __device__ __forceinline__ unsigned sel3(int d, unsigned m, unsigned z, unsigned p) {
     return d < 0 ? m : (d > 0 ? p : z);
 }
@@ -227,6 +246,14 @@ __device__ __forceinline__ unsigned neighbour(int j, int s, const unsigned om[4]
     const int d0 = s * (j % 3 - 1), d1 = s * ((j / 3) % 3 - 1), d2 = s * ((j / 9) % 3 - 1), d3 = s * (j / 27 - 1);
     return sel3(d0, om[0], o0[0], op[0]) + sel3(d1, om[1], o0[1], op[1]) + sel3(d2, om[2], o0[2], op[2]) +
            sel3(d3, om[3], o0[3], op[3]);
+}
+
+// xyz part of the neighbour x + s*d of a stored displacement index j (s = +1 or -1); the t step
+// is added by the caller
+__device__ __forceinline__ unsigned neighbour3(int j, int s, const unsigned om[3], const unsigned o0[3],
+                                               const unsigned op[3]) {
+    const int d0 = s * (j % 3 - 1), d1 = s * ((j / 3) % 3 - 1), d2 = s * ((j / 9) % 3 - 1);
+    return sel3(d0, om[0], o0[0], op[0]) + sel3(d1, om[1], o0[1], op[1]) + sel3(d2, om[2], o0[2], op[2]);
 }
 
 // weights of stored displacement j: a_k and c_mu = c_k d_mu (negated for the adjoint).

@@ -199,6 +199,325 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
     }
 }
 
+// ------------------------------------------------ whole x-lines, one right-hand side
+//
+// stencil_xline_kernel: as stencil_kernel, with 64-site tiles whose x extent is the lattice's
+// (every x-line of a tile lies in one wave).  The 80 displacements fall into 27 groups of equal
+// (d_y, d_z, d_t), each with d_x = -1, 0, +1; a group's three neighbour spinors psi(x + d) are the
+// one spinor loaded at x + (0, d_y, d_z, d_t), moved one lane left or right inside the x-line
+// (cross-lane moves through the LDS crossbar instead of two more loads through the vector-memory
+// address unit, and every spinor load aligned to the x-line).  A displacement d whose index
+// j(d) < 40 uses the stored link W_j(x) (own term); otherwise the stored link of -d at x + d,
+// daggered (partner term).  Wave q takes the groups q, q + NSPLIT, ...
+
+template <typename C> __device__ __forceinline__ C lane_fetch(const C &v, int src) {
+    C r;
+    r.x = __shfl(v.x, src, 64);
+    r.y = __shfl(v.y, src, 64);
+    return r;
+}
+
+// chi = w p' (ADJ: w^dag p') where p' is p as held by lane src (shift) or by this lane; each
+// component is moved right before its use, so no shifted copy of the spinor is kept
+template <typename C, typename R, bool ADJ>
+__device__ __forceinline__ void transport_shift(C (&chi)[4][3], const C (&w)[3][3], const C (&p)[4][3], bool shift,
+                                                int src) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) chi[s][a] = cmake<C>((R)0, (R)0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const C v = shift ? lane_fetch(p[s][b], src) : p[s][b];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (ADJ)
+                    cmac_conj(chi[s][a], w[b][a], v);
+                else
+                    cmac(chi[s][a], w[a][b], v);
+            }
+        }
+    }
+}
+
+template <class LS, int NSPLIT, bool DAG, int MODE>
+__global__ __launch_bounds__(64 * NSPLIT) void stencil_xline_kernel(StencilArgs a) {
+    using R = typename LS::R;
+    using C = typename Cx<R>::T;
+    using S = typename LS::store_t;
+    constexpr int NCOMP = 12 / NSPLIT;
+    const int col = blockIdx.y;
+    if (col_done<MODE>(a, col)) return;
+
+    const unsigned V = (unsigned)a.g.V;
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
+    unsigned om[4], o0[4], op[4];
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const int tx = a.tile[0];  // = L_x
+    const int lx = lane % tx;
+    const int lane_m = lane - lx + (lx == 0 ? tx - 1 : lx - 1);  // holds x - 1 (periodic in x)
+    const int lane_p = lane - lx + (lx == tx - 1 ? 0 : lx + 1);  // holds x + 1
+
+    const C *__restrict__ in = (const C *)a.in + (size_t)col * 12 * V;
+    const S *__restrict__ W = (const S *)a.W;
+
+    C acc[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[s][b] = cmake<C>((R)0, (R)0);
+    if (q == 0) {
+        const R diag = (R)a.diag;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const C v = in[(size_t)(s * 3 + b) * V + x];
+                acc[s][b] = cmake<C>(diag * v.x, diag * v.y);
+            }
+    }
+
+    for (int gi = q; gi < 27; gi += NSPLIT) {
+        const int dy = gi % 3 - 1, dz = (gi / 3) % 3 - 1, dt = gi / 9 - 1;
+        const unsigned yzt = sel3(dy, om[1], o0[1], op[1]) + sel3(dz, om[2], o0[2], op[2]) +
+                             sel3(dt, om[3], o0[3], op[3]);
+        C pc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) pc[s][b] = in[(size_t)(s * 3 + b) * V + o0[0] + yzt];
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (gi == 13 && dx == 0) continue;  // d = 0: the diagonal term
+            const int jd = (dx + 1) + 3 * gi;    // index of d = (dx, dy, dz, dt)
+            const int src = dx < 0 ? lane_m : lane_p;
+            C w[3][3], chi[4][3];
+            if (jd < 40) {  // own term: S_d W_d(x) psi(x + d)
+                const DirW<R, DAG, KERN_BRI> dw(jd);
+                load_link<LS>(w, W + (size_t)jd * 9 * V, x, V);
+                transport_shift<C, R, false>(chi, w, pc, dx != 0, src);
+                spin_accumulate(acc, chi, dw.a, dw.c0, dw.c1, dw.c2, dw.c3);
+            } else {  // partner term: S_d W_{-d}(x + d)^dag psi(x + d)
+                const int j = 80 - jd;
+                const DirW<R, DAG, KERN_BRI> dw(j);
+                load_link<LS>(w, W + (size_t)j * 9 * V, sel3(dx, om[0], o0[0], op[0]) + yzt, V);
+                transport_shift<C, R, true>(chi, w, pc, dx != 0, src);
+                spin_accumulate(acc, chi, dw.a, -dw.c0, -dw.c1, -dw.c2, -dw.c3);
+            }
+        }
+    }
+
+    __shared__ C red[NSPLIT > 1 ? NSPLIT : 1][12][64];
+    __shared__ double wsum[NSPLIT][2];
+    C res[NCOMP];
+    if constexpr (NSPLIT > 1) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) red[q][s * 3 + b][lane] = acc[s][b];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) {
+            const int comp = q * NCOMP + i;
+            C v = red[0][comp][lane];
+#pragma unroll
+            for (int w = 1; w < NSPLIT; ++w) {
+                const C u = red[w][comp][lane];
+                v.x += u.x;
+                v.y += u.y;
+            }
+            res[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) res[s * 3 + b] = acc[s][b];
+    }
+    if (a.g.csw != 0.0) {
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) clover_row<LS>(res[i], W + (size_t)LINK_SLAB_ENTRIES * V, in, q * NCOMP + i, x, V);
+    }
+    double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NCOMP; ++i) epilogue<MODE, C, R>(a, col, q * NCOMP + i, x, V, res[i], n0, n1);
+    if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
+        n0 = wave_sum(n0);
+        n1 = wave_sum(n1);
+        if (lane == 0) {
+            wsum[q][0] = n0;
+            wsum[q][1] = n1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < NSPLIT; ++w) {
+                s0 += wsum[w][0];
+                s1 += wsum[w][1];
+            }
+            const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+            a.partial[2 * pb] = s0;
+            a.partial[2 * pb + 1] = s1;
+        }
+    }
+}
+
+// ------------------------------------------------ t-streaming, one right-hand side
+//
+// stencil_stream_kernel: a block of STREAM_THREADS threads owns a tile of tile[0] x tile[1] x
+// tile[2] sites of the xyz volume (one site per thread) and walks the tile[3] t-slices of its
+// chunk.  At slice s every stored slab j (displacement d, with d_t = -1 for j < 27 and d_t = 0
+// for 27 <= j < 40) is read twice inside that slice:
+//   at the site x itself, for the own term     S_d W_j(x) psi(x + d)            of y(s);
+//   at the xyz-shifted site x - d_xyz, for the partner term S_{-d} W_j(x - d_xyz)^dag psi(x - d_xyz)
+//                                              of y(s - 1) (d_t = -1) or y(s) (d_t = 0),
+// since the partner site x - d of the output site (x, s - 1) lies in slice s.  Both reads of a
+// stored link thus happen in the same slice at nearly the same time, mostly inside the block's
+// own tile, instead of a slice apart.  Every thread keeps the two output slices it is building:
+// y(s - 1) is complete after the d_t = -1 slabs of step s and is written out then.  A chunk
+// [t0, t1) also visits slice t1 for the partner terms of y(t1 - 1) and leaves the partner terms of
+// y(t0 - 1) to the chunk before it.
+template <class LS, bool DAG, int MODE>
+__global__ __launch_bounds__(STREAM_THREADS) void stencil_stream_kernel(StencilArgs a) {
+    using R = typename LS::R;
+    using C = typename Cx<R>::T;
+    using S = typename LS::store_t;
+    const int col = blockIdx.y;
+    if (col_done<MODE>(a, col)) return;
+
+    const unsigned V = (unsigned)a.g.V;
+    const int Lt = a.g.L[3];
+    const unsigned S3 = (unsigned)a.g.L[0] * (unsigned)a.g.L[1] * (unsigned)a.g.L[2];
+    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
+    const int ntile = a.nb[0] * a.nb[1] * a.nb[2];
+    const int chunk = blk / ntile;
+    unsigned om[3], o0[3], op[3];
+    {
+        int tl = blk - chunk * ntile;
+        int l = threadIdx.x;
+        unsigned stride = 1;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            const int bm = tl % a.nb[mu];
+            tl /= a.nb[mu];
+            const int cm = bm * a.tile[mu] + l % a.tile[mu];
+            l /= a.tile[mu];
+            const int Lm = a.g.L[mu];
+            om[mu] = (unsigned)(cm == 0 ? Lm - 1 : cm - 1) * stride;
+            o0[mu] = (unsigned)cm * stride;
+            op[mu] = (unsigned)(cm == Lm - 1 ? 0 : cm + 1) * stride;
+            stride *= (unsigned)Lm;
+        }
+    }
+    const unsigned xyz = o0[0] + o0[1] + o0[2];
+    const int t0 = chunk * a.tile[3], t1 = t0 + a.tile[3];
+
+    const C *__restrict__ in = (const C *)a.in + (size_t)col * 12 * V;
+    const S *__restrict__ W = (const S *)a.W;
+    const R diag = (R)a.diag;
+
+    C accp[4][3], accc[4][3];  // y(s - 1), y(s)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            accp[s][b] = cmake<C>((R)0, (R)0);
+            accc[s][b] = cmake<C>((R)0, (R)0);
+        }
+    double n0 = 0.0, n1 = 0.0;
+
+    for (int s = t0; s <= t1; ++s) {
+        const bool first = s == t0, last = s == t1;
+        const unsigned ts = (unsigned)(s == Lt ? 0 : s) * S3;         // slice s
+        const unsigned tm = (unsigned)(s == 0 ? Lt - 1 : s - 1) * S3;  // slice s - 1
+        if (!last) {
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const C v = in[(size_t)(sp * 3 + b) * V + xyz + ts];
+                    accc[sp][b] = cmake<C>(diag * v.x, diag * v.y);
+                }
+        }
+        // d_t = -1: own terms of y(s) (spinor from slice s - 1), partner terms of y(s - 1)
+        for (int j = 0; j < 27; ++j) {
+            const DirW<R, DAG, KERN_BRI> dw(j);
+            const S *__restrict__ Wj = W + (size_t)j * 9 * V;
+            C chi[4][3];
+            if (!last) {
+                const unsigned yp = neighbour3(j, +1, om, o0, op) + tm;
+                transport<LS, false>(chi, Wj, xyz + ts, in, yp, V);
+                spin_accumulate(accc, chi, dw.a, dw.c0, dw.c1, dw.c2, dw.c3);
+            }
+            if (!first) {
+                const unsigned ym = neighbour3(j, -1, om, o0, op) + ts;
+                transport<LS, true>(chi, Wj, ym, in, ym, V);
+                spin_accumulate(accp, chi, dw.a, -dw.c0, -dw.c1, -dw.c2, -dw.c3);
+            }
+        }
+        if (!first) {  // y(s - 1) is complete
+            const unsigned x = xyz + tm;
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    C v = accp[sp][b];
+                    if (a.g.csw != 0.0) clover_row<LS>(v, W + (size_t)LINK_SLAB_ENTRIES * V, in, sp * 3 + b, x, V);
+                    epilogue<MODE, C, R>(a, col, sp * 3 + b, x, V, v, n0, n1);
+                }
+        }
+        if (last) break;
+        // d_t = 0: own and partner terms of y(s), everything in slice s
+        for (int j = 27; j < 40; ++j) {
+            const DirW<R, DAG, KERN_BRI> dw(j);
+            const S *__restrict__ Wj = W + (size_t)j * 9 * V;
+            C chi[4][3];
+            const unsigned yp = neighbour3(j, +1, om, o0, op) + ts;
+            transport<LS, false>(chi, Wj, xyz + ts, in, yp, V);
+            spin_accumulate(accc, chi, dw.a, dw.c0, dw.c1, dw.c2, dw.c3);
+            const unsigned ym = neighbour3(j, -1, om, o0, op) + ts;
+            transport<LS, true>(chi, Wj, ym, in, ym, V);
+            spin_accumulate(accc, chi, dw.a, -dw.c0, -dw.c1, -dw.c2, -dw.c3);
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) accp[sp][b] = accc[sp][b];
+    }
+
+    if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
+        // deterministic: wave sums, then the wave totals in order; blocks fill slots
+        // [0, gridDim.x) of the column and zero the rest of its nslots
+        constexpr int NW = STREAM_THREADS / 64;
+        __shared__ double wsum[NW][2];
+        const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+        n0 = wave_sum(n0);
+        n1 = wave_sum(n1);
+        if (lane == 0) {
+            wsum[q][0] = n0;
+            wsum[q][1] = n1;
+        }
+        __syncthreads();
+        double *pc = a.partial + 2 * (size_t)col * a.nslots;
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                s0 += wsum[w][0];
+                s1 += wsum[w][1];
+            }
+            pc[2 * blockIdx.x] = s0;
+            pc[2 * blockIdx.x + 1] = s1;
+        }
+        for (int i = gridDim.x + blockIdx.x * STREAM_THREADS + threadIdx.x; i < a.nslots;
+             i += gridDim.x * STREAM_THREADS) {
+            pc[2 * i] = 0.0;
+            pc[2 * i + 1] = 0.0;
+        }
+    }
+}
+
 // ------------------------------------------------------ many right-hand sides
 
 template <class LS, int R, bool DAG, int MODE, int KIND>
@@ -355,8 +674,57 @@ inline hipError_t launch_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class LS, bool DAG>
+inline hipError_t launch_stream(const StencilArgs &a, int mode, hipStream_t st) {
+    const dim3 grid((unsigned)(a.nb[0] * a.nb[1] * a.nb[2] * a.nb[3]), (unsigned)a.ncol), block(STREAM_THREADS);
+    switch (mode) {
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_stream_kernel<LS, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_stream_kernel<LS, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_stream_kernel<LS, DAG, EPI_CG_R>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_stream_kernel<LS, DAG, EPI_OV>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_stream_kernel<LS, DAG, EPI_SIGN>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_stream_kernel<LS, DAG, EPI_RESID>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class LS, int NSPLIT, bool DAG>
+inline hipError_t launch_xline(const StencilArgs &a, int mode, hipStream_t st) {
+    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)a.ncol), block(64 * NSPLIT);
+    switch (mode) {
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_CG_R>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_OV>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_SIGN>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_RESID>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <class LS, bool DAG, int KIND>
 inline hipError_t launch_cfg(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
+    if (cfg.variant == VAR_XLINE) {
+        if constexpr (KIND == KERN_BRI) {
+            if (cfg.rpt == 0) {
+                switch (cfg.nsplit) {
+                case 1: return launch_xline<LS, 1, DAG>(a, mode, st);
+                case 2: return launch_xline<LS, 2, DAG>(a, mode, st);
+                case 4: return launch_xline<LS, 4, DAG>(a, mode, st);
+                default: return hipErrorInvalidValue;
+                }
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    if (cfg.variant == VAR_TSTREAM) {
+        if constexpr (KIND == KERN_BRI) {
+            if (cfg.rpt == 0) return launch_stream<LS, DAG>(a, mode, st);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (cfg.rpt) {
     case 0:
         switch (cfg.nsplit) {

@@ -40,6 +40,7 @@ static StencilConfig from_public(const bri_stencil_cfg &c) {
     s.nsplit = c.nsplit;
     s.rpt = c.rpt;
     s.xcd_remap = c.xcd;
+    s.variant = c.variant;
     return s;
 }
 
@@ -53,6 +54,7 @@ static bri_stencil_cfg to_public(const StencilConfig &s) {
     c.nsplit = s.nsplit;
     c.rpt = s.rpt;
     c.xcd = s.xcd_remap;
+    c.variant = s.variant;
     return c;
 }
 
@@ -89,7 +91,7 @@ static int time_config(const Geom &g, const void *W, int prec, const void *in, v
 static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) {
     std::vector<StencilConfig> out;
     std::vector<std::array<int, 5>> trav;  // tile x, y, z, t, colz
-    const int tx_opts[3][2] = {{8, 8}, {16, 4}, {4, 16}};
+    const int tx_opts[5][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}, {64, 1}};
     for (const auto &t : tx_opts)
         for (int cz : {2, 4, 8, 16})
             if (g.L[0] % t[0] == 0 && g.L[1] % t[1] == 0 && g.L[2] % cz == 0) trav.push_back({t[0], t[1], 1, 1, cz});
@@ -112,7 +114,32 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
                 c.rpt = w.second;
                 c.xcd_remap = xcd;
                 out.push_back(c);
+                // the x-line kernel where the tile spans whole x-lines
+                if (w.second == 0 && t[0] == g.L[0]) {
+                    c.variant = VAR_XLINE;
+                    out.push_back(c);
+                }
             }
+    // t-streaming kernel (one right-hand side per block row): xyz tiles of 256 sites, t-chunks
+    if (ncol <= 4) {
+        const int xyz[6][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 8}, {16, 8, 2}, {32, 8, 1}, {16, 16, 1}};
+        for (const auto &t : xyz)
+            for (int ct : {4, 8, 16})
+                for (int xcd : {0, 1}) {
+                    StencilConfig c;
+                    c.tile[0] = t[0];
+                    c.tile[1] = t[1];
+                    c.tile[2] = t[2];
+                    c.tile[3] = ct;
+                    c.colz = 0;
+                    c.nsplit = 1;
+                    c.rpt = 0;
+                    c.xcd_remap = xcd;
+                    c.variant = VAR_TSTREAM;
+                    int tile[4], nb[4];
+                    if (plan_tile(g, c, tile, nb) == BRI_OK) out.push_back(c);
+                }
+    }
     return out;
 }
 
@@ -179,7 +206,10 @@ int bri_set_stencil_cfg(const bri_geom *geom, int prec, int nrhs, const bri_sten
     StencilConfig c = from_public(*cfg);
     int tile[4], nb[4];
     if (plan_tile(g, c, tile, nb) != BRI_OK) return BRI_EINVAL;
-    if (c.rpt < 0 || c.rpt > 4 || (c.rpt == 0 && c.nsplit != 1 && c.nsplit != 2 && c.nsplit != 4)) return BRI_EINVAL;
+    if (c.variant < VAR_STANDARD || c.variant > VAR_XLINE) return BRI_EINVAL;
+    if (c.rpt < 0 || c.rpt > 4 || (c.variant != VAR_TSTREAM && c.rpt == 0 && c.nsplit != 1 && c.nsplit != 2 &&
+                                   c.nsplit != 4))
+        return BRI_EINVAL;
     g_tuned[key_of(g, prec, nrhs)] = c;
     return BRI_OK;
 }
