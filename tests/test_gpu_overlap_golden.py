@@ -1,0 +1,196 @@
+"""Overlap apply at the full workload lattices against the FP64 oracle (eq. (def_over) with the
+[16/16] partial fractions of eq. (KLnn_parfrac), rho = 1), in the launch configuration the
+benchmark times (the library defaults):
+
+  * 24^3x48 and 32^3x64 against the stored oracle outputs of tests/golden/overlap_*.npz
+    (written by tests/golden/make_overlap_golden.py, oracle only): the output at the stored
+    sites, the global norm and two projections on seeded unit Gaussian spinors;
+  * 16^4 against the oracle run in the test, element by element.
+
+The result criterion is |D_ov psi - oracle| <= 1e-10 |oracle| (relative error per result).  At
+the stored sites each entry must lie within 1e-10 |oracle| of the oracle's, and so must the
+norm and each projection (|<w, e>| <= |e| for a unit w), which see an error anywhere on the
+lattice.  Paths: FP64 single source, the FP64 batch (12 spin-colour point sources side by side
+at 32^3x64), and the mixed-precision paths with FP32 and bfloat16-link inner solves.
+
+The device builds the links with the same recipe as the oracle's inputs (synth, torch variant;
+agreement with the numpy recipe to rounding is tested in test_synth.py).
+"""
+
+import glob
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1701_00726_amd as bri
+import synth
+from tests._gpu import need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden")
+TOL = 1e-10
+CASES = ["24x24x24x48_point0", "24x24x24x48_gauss", "32x32x32x64_point0", "32x32x32x64_point7",
+         "32x32x32x64_point11"]
+
+
+def _load(name):
+    path = os.path.join(GOLD, f"overlap_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle output {os.path.basename(path)} not written")
+    d = np.load(path, allow_pickle=False)
+    return {k: d[k] for k in d.files}
+
+
+def _check(got_dev, g, what):
+    """got_dev: (4, 3, V) complex128 device tensor of one result."""
+    ref_norm = float(g["norm"])
+    sites = torch.from_numpy(g["sites"]).to(got_dev.device)
+    got_s = got_dev[:, :, sites].permute(2, 0, 1).cpu().numpy()
+    err_s = np.abs(got_s - g["out_sites"]).max() / ref_norm
+    got_norm = float(torch.linalg.vector_norm(got_dev))
+    L = tuple(int(v) for v in g["L"])
+    got_host = bri.spinor_to_host(got_dev[None])[0]
+    errs_p = [abs(np.vdot(synth.gaussian_source(L, int(s))[0].ravel(), got_host.ravel()) - p) / ref_norm
+              for s, p in zip(g["proj_seeds"], g["proj"])]
+    print(f"{what}: sites {err_s:.1e}, norm {abs(got_norm - ref_norm) / ref_norm:.1e}, "
+          f"projections {max(errs_p):.1e} (of |ref| = {ref_norm:.6f})", flush=True)
+    assert err_s <= TOL, (what, err_s)
+    assert abs(got_norm - ref_norm) <= TOL * ref_norm, (what, got_norm, ref_norm)
+    assert max(errs_p) <= TOL, (what, errs_p)
+
+
+def _source(L, g):
+    if str(g["source_kind"]) == "point":
+        return synth.point_sources_12(L)[int(g["source_arg"])][None]
+    return synth.gaussian_source(L, int(g["source_arg"]))
+
+
+_fields = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _free_fields():
+    yield
+    _fields.clear()
+    if torch.cuda.is_available():
+        torch.cuda.empty_cache()
+
+
+def _field(g):
+    key = (tuple(int(v) for v in g["L"]), float(g["eps"]), int(g["link_seed"]))
+    if key not in _fields:
+        _fields.clear()
+        torch.cuda.empty_cache()
+        L, eps, seed = key
+        U = synth.smeared_links_torch(L, eps, seed, float(g["ape_alpha"]), int(g["ape_steps"]), device="cuda",
+                                      chunk=1 << 18).permute(0, 2, 3, 1).contiguous()
+        _fields[key] = (U, bri.build_links(L, U, bri.F64))
+    return key[0], _fields[key]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp64_single_source(name):
+    need_gpu()
+    g = _load(name)
+    L, (U, W) = _field(g)
+    print(f"[{name}] FP64 single source", flush=True)
+    op = bri.OverlapOp(L, W, kl_n=int(g["kl_n"]), rho=float(g["rho"]), tol=1e-12, max_iter=5000)
+    out, st = op.apply(bri.spinor_to_device(_source(L, g)))
+    _check(out[0], g, f"{name} fp64 1src ({st.iters} iterations)")
+    del op, out
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16w"])
+@pytest.mark.parametrize("name", CASES[:3])
+def test_mixed_single_source(name, inner):
+    need_gpu()
+    g = _load(name)
+    L, (U, W) = _field(g)
+    prec = {"f32": bri.F32, "bf16w": bri.F32_BF16W}[inner]
+    print(f"[{name}] mixed {inner} single source", flush=True)
+    Wlo = bri.build_links(L, U, prec)
+    op = bri.OverlapOp(L, W, kl_n=int(g["kl_n"]), rho=float(g["rho"]), tol=1e-12, max_iter=5000, Wlo=Wlo,
+                       inner=prec)
+    out, st = op.apply(bri.spinor_to_device(_source(L, g)))
+    _check(out[0], g, f"{name} mixed {inner} 1src ({st.iters} iterations, {st.refine} refinements)")
+    del op, out, Wlo
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_batched_point_sources_32_64(inner):
+    """The 12 spin-colour point sources at 32^3x64 side by side; every column with a stored
+    oracle output is checked."""
+    need_gpu()
+    have = [n for n in CASES if n.startswith("32x") and os.path.exists(os.path.join(GOLD, f"overlap_{n}.npz"))]
+    if not have:
+        pytest.skip("no stored 32^3x64 oracle output")
+    gs = {n: _load(n) for n in have}
+    g0 = gs[have[0]]
+    L, (U, W) = _field(g0)
+    prec = {"f64": bri.F64, "f32": bri.F32}[inner]
+    print(f"[32^3x64] batched 12 sources, inner {inner}", flush=True)
+    Wlo = None if prec == bri.F64 else bri.build_links(L, U, prec)
+    op = bri.OverlapOp(L, W, kl_n=16, rho=1.0, tol=1e-12, max_iter=5000, Wlo=Wlo, inner=prec, nrhs=12)
+    out, st = op.apply(bri.spinor_to_device(synth.point_sources_12(L)))
+    for n, g in gs.items():
+        _check(out[int(g["source_arg"])], g, f"{n} batched {inner} ({st.iters} iterations)")
+    del op, out, Wlo
+    torch.cuda.empty_cache()
+
+
+def test_batched_24_48():
+    """The point and Gaussian sources of 24^3x48 side by side in one FP64 batch."""
+    need_gpu()
+    gp, gg = _load("24x24x24x48_point0"), _load("24x24x24x48_gauss")
+    L, (U, W) = _field(gp)
+    b = np.concatenate([_source(L, gp), _source(L, gg)])
+    op = bri.OverlapOp(L, W, kl_n=16, rho=1.0, tol=1e-12, max_iter=5000, nrhs=2)
+    out, st = op.apply(bri.spinor_to_device(b))
+    _check(out[0], gp, f"24^3x48 point batched ({st.iters} iterations)")
+    _check(out[1], gg, f"24^3x48 gauss batched ({st.iters} iterations)")
+
+
+# ------------------------------------------------------------------- 16^4 in the test
+
+L16 = (16, 16, 16, 16)
+
+
+@pytest.fixture(scope="module")
+def cfg16():
+    U = synth.smeared_links(L16, 0.5, synth.LINK_SEED_BASE + 2, 0.6, 3)
+    return U, oracle.links(L16, U), bri.build_links(L16, bri.links_to_device(U), bri.F64)
+
+
+def test_16_4_every_path_against_oracle(cfg16):
+    """16^4, [16/16]: the Gaussian source and two point sources through the oracle (every shift by
+    its own CG), against the FP64 single-source and batched applies and the mixed paths,
+    element by element."""
+    need_gpu()
+    U, Wo, W = cfg16
+    b = np.concatenate([synth.gaussian_source(L16, synth.SOURCE_SEED_BASE + 2), synth.point_sources_12(L16)[[0, 7]]])
+    print("[16^4] oracle for 3 sources", flush=True)
+    ref = np.stack([oracle.ov_apply(L16, Wo, 1.0, 16, b[r], tol=1e-13)[0] for r in range(3)])
+    bd = bri.spinor_to_device(b)
+
+    def rel(got, r):
+        return float(np.linalg.norm((got - ref[r]).ravel()) / np.linalg.norm(ref[r].ravel()))
+
+    op1 = bri.OverlapOp(L16, W, kl_n=16, tol=1e-12, max_iter=5000)
+    for r in range(3):
+        got = bri.spinor_to_host(op1.apply(bd[r:r + 1].contiguous())[0])[0]
+        assert rel(got, r) < TOL, ("fp64 1src", r, rel(got, r))
+    opb = bri.OverlapOp(L16, W, kl_n=16, tol=1e-12, max_iter=5000, nrhs=3)
+    got = bri.spinor_to_host(opb.apply(bd)[0])
+    for r in range(3):
+        assert rel(got[r], r) < TOL, ("fp64 batched", r, rel(got[r], r))
+    for prec in (bri.F32, bri.F32_BF16W):
+        Wlo = bri.build_links(L16, bri.links_to_device(U), prec)
+        opm = bri.OverlapOp(L16, W, kl_n=16, tol=1e-12, max_iter=5000, Wlo=Wlo, inner=prec, nrhs=3)
+        got = bri.spinor_to_host(opm.apply(bd)[0])
+        for r in range(3):
+            assert rel(got[r], r) < TOL, ("mixed", prec, r, rel(got[r], r))
