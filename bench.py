@@ -1,37 +1,44 @@
 #!/usr/bin/env python3
 """Benchmark of the Brillouin-kernel overlap hot path on one MI355X.
 
-Step (the timed unit behind `value`) = one pass of the whole hot path over one
-synthetic batch: bri_build_links (U -> FP64 off-axis links) + ov_apply (FP64
-multi-shift CG for the Kenney-Laub [16/16] rational, two stencil applies per
-iteration, final apply) on a 16^4 lattice with smeared links (exp(0.5 i A),
-3 APE steps at alpha 0.6), one normalised Gaussian source, rho = 1, CG
-tolerance 1e-12 per shift.  This is the plain FP64 single-RHS GPU path.
+Workload (the metric's configuration): a 32^3x64 lattice, links exp(0.7 i A) + 3 APE steps at
+alpha 0.6 (seeded), the 12 spin-colour point sources at the origin, D_ov = rho (1 + gamma5 sign(H))
+with the Kenney-Laub [16/16] partial fractions (16 shifts), rho = 1, per-shift CG tolerance 1e-12.
 
-value        overlap applies (right-hand sides) per second of that step
-roofline     dominant kernel, the FP64 stencil bri_apply, timed live with HIP
-             events on the library's stream: algorithmic bytes per launch
-             (6144 B/site: the 40 stored links, spinor in and out) / average
-             launch time, against the 8 TB/s HBM peak; `traffic` from the
-             committed rocprofv3 counter summary when the kernel sources match
-cpu_baseline the FP64 CPU oracle on a bounded sample (see `sample`)
-extra        the same apply batched over the 12 spin-colour point sources and
-             with mixed precision (FP32 / bfloat16-link inner solve, FP64
-             refinement), each with its error against the FP64 result
+Step (the timed unit behind `value`) = one pass of the whole hot path over the 12 sources:
+bri_build_links (U -> FP64 off-axis links, and the FP32 links of the inner solve) + one batched
+mixed-precision ov_apply (FP64 multi-shift CG whose iterations switch to FP32 links and vectors
+once the residual has fallen to where their rounding no longer reaches the tolerance; FP64 final
+apply).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
-       python bench.py --stencil-only     (copy calibration + stencil launches, for counters)
-       python bench.py --stencil-only --lattice 32,32,32,64   (the same on a larger workload lattice)
-       python bench.py --stencil-only --stencil-rhs 12        (plus the multi-RHS kernel, FP64 and FP32)
-       python bench.py --batched-only --steps 5 --warmup 1    (12-source FP64 apply only, for traces)
+value        overlap applies (right-hand sides) per second of that step.  Gated: every source with
+             a stored FP64 oracle output (tests/golden/overlap_32x32x32x64_point*.npz) must match
+             it to 1e-10 of its norm (stored sites, norm, two projections), else value = 0.
+extra        the same workload through the plain FP64 single-source path (the speedup's
+             denominator) and the FP64 batched path, with the speedups; a 16^4 line.
+roofline     dominant kernel family, the FP64 stencil bri_apply at 32^3x64 (1 RHS, default launch),
+             timed live with HIP events on the stream it runs on: algorithmic bytes per launch
+             (6144 B/site: the 40 stored links, spinor in and out) / average launch time, against
+             the 8 TB/s HBM peak; `traffic` from the committed rocprofv3 counter summary while the
+             kernel sources match it.  The FP32 stencil and the multi-RHS kernels (% of peak
+             flops) are reported beside it.
+cpu_baseline the FP64 CPU oracle (every shift solved on its own) on the host: its stencil timed on
+             a 16^4 field (same per-site work), scaled to the 32^3x64 volume and to the CG
+             iterations the oracle itself needed on this workload (stored with its outputs).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
+       python bench.py --stencil-only [--stencil-rhs 12]   (copy calibration + stencil launches, for counters)
+       python bench.py --survey                             (tuned stencil and overlap timings, 3 lattices)
 """
 
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -42,16 +49,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-L_BENCH = (16, 16, 16, 16)
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+L_BENCH = (32, 32, 32, 64)
+NSRC = 12
 KL_N = 16
 RHO = 1.0
 CG_TOL = 1e-12
-MASS = 0.05  # bare quark mass of the massive solve measured beside the apply
-OUTER_TOL = 1e-10  # BiCGstab stop of that solve
-LINK_EPS, APE_ALPHA, APE_STEPS = 0.5, 0.6, 3
-LINK_SEED = 1701 + 2
-SRC_SEED = 726 + 2
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_f64_16x16x16x16_counters.txt")
+GATE_TOL = 1e-10
+LINK_EPS, APE_ALPHA, APE_STEPS = 0.7, 0.6, 3
+LINK_SEED = 1701 + 4
+L_SMALL = (16, 16, 16, 16)  # the 16^4 line: exp(0.5 i A) + 3 APE, Gaussian source
+SMALL_EPS, SMALL_SEED, SMALL_SRC_SEED = 0.5, 1701 + 2, 726 + 2
+MASS = 0.05  # bare quark mass of the massive solve (extras)
+OUTER_TOL = 1e-10
+LINK_SEED_16 = SMALL_SEED
+SRC_SEED = SMALL_SRC_SEED
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_f64_32x32x32x64_counters.txt")
+FLOP_PER_SITE_RHS = 2 * 18648  # FMA count of the kernels per site and right-hand side, x2
 
 
 def stencil_bytes_per_site(spinor_bytes_per_real: int, link_bytes_per_real: int, nrhs: int = 1) -> int:
@@ -74,9 +90,9 @@ def kernel_source_digest() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per launch of the FP64 stencil at 16^4 from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel factor), or
-    None when the kernel sources changed since the counters were taken."""
+    """HBM bytes per launch of the FP64 stencil at 32^3x64 from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel factor), or None when the kernel
+    sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -93,69 +109,142 @@ def measured_traffic():
         return None
 
 
+def golden_cases(L):
+    """Stored oracle outputs for lattice L: list of dicts (tests/golden/overlap_<L>_*.npz)."""
+    tag = "x".join(str(v) for v in L)
+    out = []
+    for path in sorted(glob.glob(os.path.join(GOLDEN, f"overlap_{tag}_*.npz"))):
+        d = np.load(path, allow_pickle=False)
+        out.append({k: d[k] for k in d.files} | {"name": os.path.basename(path)})
+    return out
+
+
+def gate(torch, bri, synth, out, cases):
+    """Compare columns of `out` (nsrc, 4, 3, V) with the stored oracle outputs of point sources:
+    the worst of (stored sites, norm, projections) relative to the oracle norm, per case."""
+    rows = []
+    for g in cases:
+        if str(g["source_kind"]) != "point":
+            continue
+        col = out[int(g["source_arg"])]
+        ref_norm = float(g["norm"])
+        sites = torch.from_numpy(g["sites"]).to(col.device)
+        es = float(np.abs(col[:, :, sites].permute(2, 0, 1).cpu().numpy() - g["out_sites"]).max()) / ref_norm
+        en = abs(float(torch.linalg.vector_norm(col)) - ref_norm) / ref_norm
+        L = tuple(int(v) for v in g["L"])
+        host = bri.spinor_to_host(col[None])[0].ravel()
+        ep = max(abs(np.vdot(synth.gaussian_source(L, int(s))[0].ravel(), host) - p) / ref_norm
+                 for s, p in zip(g["proj_seeds"], g["proj"]))
+        rows.append({"case": g["name"], "source": int(g["source_arg"]), "err_sites": es, "err_norm": en,
+                     "err_proj": float(ep), "pass": max(es, en, ep) <= GATE_TOL})
+    return rows
+
+
+def cpu_info():
+    model, phys = None, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cur = {}
+            for ln in f:
+                if ":" in ln:
+                    k, v = (t.strip() for t in ln.split(":", 1))
+                    cur[k] = v
+                    if k == "model name" and model is None:
+                        model = v
+                elif cur:
+                    phys.add((cur.get("physical id"), cur.get("core id")))
+                    cur = {}
+            if cur:
+                phys.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    return {"model": model, "physical_cores": len(phys) or None, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+_ONE_CORE = r"""
+import sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle, synth
+L = (8, 8, 8, 8)
+W = oracle.links(L, synth.random_links(L, 0.5, 1))
+b = synth.gaussian_source(L, 2)[0]
+oracle.dirac(L, W, -1.0, b)
+t0 = time.perf_counter(); n = 0
+while time.perf_counter() - t0 < 2.0:
+    oracle.dirac(L, W, -1.0, b); n += 1
+print((time.perf_counter() - t0) / n / 4096, oracle.num_threads())
+"""
+
+
+def cpu_baseline(shift_iters_per_source, iters_note, budget_s):
+    """The oracle's stencil timed on a 16^4 field (per-site cost identical at every volume: the
+    same 81 terms), scaled to one 12-source overlap apply at 32^3x64 with the per-shift CG
+    iterations the oracle needs there (each CG iteration = 2 stencils, plus 2 per restart and
+    final residual check, plus the final X y)."""
+    import oracle
+    import synth
+
+    V16, V32 = int(np.prod(L_SMALL)), int(np.prod(L_BENCH))
+    U = synth.random_links(L_SMALL, SMALL_EPS, SMALL_SEED)
+    t0 = time.perf_counter()
+    Wo = oracle.links(L_SMALL, U)
+    t_links = time.perf_counter() - t0
+    b = synth.gaussian_source(L_SMALL, SMALL_SRC_SEED)[0]
+    oracle.dirac(L_SMALL, Wo, -RHO, b)
+    n, t0 = 0, time.perf_counter()
+    while n < 3 or (time.perf_counter() - t0 < budget_s / 2 and n < 50):
+        oracle.dirac(L_SMALL, Wo, -RHO, b)
+        n += 1
+    t_site = (time.perf_counter() - t0) / n / V16
+    applies = [sum(2 * (int(i) + 2) for i in its) + 1 for its in shift_iters_per_source]
+    per_src = float(np.mean(applies)) * V32 * t_site
+    t_total = t_links / V16 * V32 + NSRC * per_src
+    one = None
+    try:
+        r = subprocess.run([sys.executable, "-c", _ONE_CORE, ROOT], capture_output=True, text=True, timeout=120,
+                           env=dict(os.environ, OMP_NUM_THREADS="1"))
+        one = float(r.stdout.split()[0])
+    except Exception:  # noqa: BLE001 - the one-core figure is informative only
+        pass
+    info = cpu_info()
+    return {
+        "value": NSRC / t_total,
+        "unit": "overlap applies/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (
+            f"oracle stencil (direct 81-term sum, stored 81 links per site) timed {n}x on a 16^4 field: "
+            f"{t_site * 1e9:.0f} ns/site ({oracle.num_threads()} threads); oracle links {t_links:.2f} s at 16^4. "
+            f"Scaled to 32^3x64 and to {np.mean(applies):.0f} stencil applies per source ({iters_note}; every "
+            f"shift solved by its own CG): {per_src:.0f} s per source, {t_total:.0f} s for the 12 sources"
+        ),
+        "cpu": info,
+        "one_thread_ns_per_site": None if one is None else one * 1e9,
+        "one_thread_applies_per_s": None if one is None else NSRC / (t_links / V16 * V32 * oracle.num_threads() +
+                                                                       NSRC * float(np.mean(applies)) * V32 * one),
+    }
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--stencil-reps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--stencil-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and mixed-precision measurements")
-    ap.add_argument("--tune", action="store_true", help="autotune the stencil launch before timing")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP64 comparison paths and kernel extras")
+    ap.add_argument("--extras", action="store_true",
+                    help="also the 16^4 gradient, kernel and rational variants, massive solve, cascade and Sec. 7 tables")
+    ap.add_argument("--tune", action="store_true", help="autotune the stencil launches before timing")
     ap.add_argument("--survey", action="store_true",
                     help="stencil (tuned, FP64/FP32/BF16-link, 1 and 12 RHS) and overlap timings at 16^4, 24^3x48, 32^3x64")
     ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
     ap.add_argument("--stencil-rhs", type=int, default=1,
                     help="with --stencil-only: also launch the multi-RHS kernel on this many RHS (FP64 and FP32)")
-    ap.add_argument("--batched-only", action="store_true",
-                    help="only the 12-source FP64 overlap apply, --steps times (for kernel traces)")
-    ap.add_argument("--lattice", default=None,
-                    help="with --stencil-only: another lattice, e.g. 32,32,32,64 (links exp(0.7iA) + 3 APE "
-                         "built on the device)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
+    ap.add_argument("--inner", default="f32", choices=["f32", "bf16w"], help="inner precision of the timed path")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     return ap.parse_args()
-
-
-def cpu_baseline(L, U_np, shift_iters, budget_s):
-    """Time the FP64 oracle on a bounded sample of the same workload and scale it
-    to one overlap apply: oracle links + sum over shifts of (per-shift CG iterations
-    x measured time per CG iteration) + the final stencil apply."""
-    import oracle
-    import synth
-    from oracle import kl
-
-    t0 = time.perf_counter()
-    Wo = oracle.links(L, U_np)
-    t_links = time.perf_counter() - t0
-    b = synth.gaussian_source(L, SRC_SEED)[0]
-    _, _, sg = kl.kl_diag_coeffs_f64(KL_N)
-    its = 2
-    while True:
-        t0 = time.perf_counter()
-        oracle.cg(L, Wo, -RHO, sg[0], b, tol=1e-30, maxit=its)
-        dt = time.perf_counter() - t0
-        # one restart residual + `its` iterations + the final true residual = its + 2 normal-op applies
-        t_iter = dt / (its + 2)
-        if dt * 2.5 > budget_s or its >= 64:
-            break
-        its *= 2
-    t0 = time.perf_counter()
-    oracle.dirac(L, Wo, -RHO, b)
-    t_apply = time.perf_counter() - t0
-    total_iters = int(sum(shift_iters))
-    t_est = t_links + total_iters * t_iter + t_apply
-    return {
-        "value": 1.0 / t_est,
-        "unit": "overlap applies/s",
-        "cores": oracle.num_threads(),
-        "kind": "oracle",
-        "sample": (
-            f"oracle links ({t_links:.2f} s) + {its} CG iterations of the smallest shift "
-            f"({t_iter:.3f} s each) + one stencil apply ({t_apply:.2f} s) timed on {L[0]}x{L[1]}x{L[2]}x{L[3]}; "
-            f"scaled to the {total_iters} per-shift CG iterations ({KL_N} shifts solved one by one) "
-            f"that one apply needs: {t_est:.1f} s per apply"
-        ),
-    }
 
 
 def survey(torch, bri, synth):
@@ -205,28 +294,6 @@ def survey(torch, bri, synth):
         torch.cuda.empty_cache()
 
 
-def stencil_only_large(torch, bri, synth, L, reps):
-    """Counter runs on a workload lattice other than the bench's: a 1 GiB calibration copy, the
-    links of that lattice's recipe (exp(0.7 i A) + 3 APE(0.6)) built on the device, and `reps`
-    FP64 stencil launches in the default configuration."""
-    V = int(np.prod(L))
-    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-    c = torch.empty_like(a)
-    c.copy_(a)
-    del a, c
-    U = synth.smeared_links_torch(L, 0.7, LINK_SEED, APE_ALPHA, APE_STEPS, device="cuda", chunk=1 << 18)
-    W = bri.build_links(L, U.permute(0, 2, 3, 1).contiguous(), bri.F64)
-    del U
-    x = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED), bri.F64)
-    y = torch.empty_like(x)
-    for _ in range(reps):
-        bri.apply(L, W, bri.F64, -RHO, x, out=y)
-    torch.cuda.synchronize()
-    print(json.dumps({"stencil_only": True, "lattice": list(L), "launches": reps,
-                      "alg_bytes_per_launch": stencil_bytes_per_site(8, 8) * V,
-                      "config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict()}), flush=True)
-
-
 # the cascaded-preconditioning measurement: the 16^3x32 volume of the paper's timing table,
 # links exp(0.5 iA) + 7 APE(0.6) steps, am = 0.03, rho = 1, exit |r|/|b| <= 1e-9
 CASCADE_L = (16, 16, 16, 32)
@@ -266,7 +333,7 @@ def quality_table(dev):
     rows = []
     eta = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED + 40, nrhs=4), bri.F64, dev)
     for ape in (1, 3):
-        U = synth.smeared_links_torch(L, LINK_EPS, LINK_SEED + 40, QUALITY_APE_ALPHA, ape, device=dev, chunk=1 << 18)
+        U = synth.smeared_links_torch(L, SMALL_EPS, SMALL_SEED + 40, QUALITY_APE_ALPHA, ape, device=dev, chunk=1 << 18)
         U = U.permute(0, 2, 3, 1).contiguous()
         for csw in (0.0, 1.0):
             W = bri.build_links(L, U, bri.F64, csw=csw)
@@ -299,7 +366,7 @@ def cascade_table(dev):
     import synth
 
     L = CASCADE_L
-    U = synth.smeared_links_torch(L, LINK_EPS, LINK_SEED + 30, APE_ALPHA, CASCADE_APE, device=dev, chunk=1 << 18)
+    U = synth.smeared_links_torch(L, SMALL_EPS, SMALL_SEED + 30, APE_ALPHA, CASCADE_APE, device=dev, chunk=1 << 18)
     U = U.permute(0, 2, 3, 1).contiguous()
     W = bri.build_links(L, U, bri.F64)
     W32 = bri.build_links(L, U, bri.F32)
@@ -330,6 +397,88 @@ def cascade_table(dev):
     return {"lattice": list(L), "mass": CASCADE_MASS, "tol": CASCADE_TOL, "ape_steps": CASCADE_APE, "rows": rows}
 
 
+
+
+def small_line(torch, bri, synth, dev, timed):
+    """The former headline: 16^4 FP64 overlap apply of one Gaussian source and of the 12 point
+    sources (links exp(0.5 i A) + 3 APE), HIP-event timed."""
+    L = L_SMALL
+    U = bri.links_to_device(synth.smeared_links(L, SMALL_EPS, SMALL_SEED, APE_ALPHA, APE_STEPS), dev)
+    W = bri.build_links(L, U, bri.F64)
+    b = bri.spinor_to_device(synth.gaussian_source(L, SMALL_SRC_SEED), bri.F64, dev)
+    op = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+    o = torch.empty_like(b)
+    _, st = op.apply(b, out=o)
+    ms = timed(lambda: op.apply(b, out=o), 10)
+    b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
+    op12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, nrhs=12)
+    o12 = torch.empty_like(b12)
+    op12.apply(b12, out=o12)
+    ms12 = timed(lambda: op12.apply(b12, out=o12), 3)
+    return {"fp64_1src_applies_per_s": 1e3 / ms, "fp64_12src_applies_per_s": 12e3 / ms12,
+            "cg_iterations": st.iters, "stencil_config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict()}
+
+
+def extras_16(torch, bri, synth, dev, timed, stencil_reps):
+    """Gradient, Wilson kernel, relaxed stopping, upper diagonal, clover, massive solves, cascade and
+    Sec. 7 quality tables on the 16^4 field (the NEXT rows and the differentiation growth)."""
+    L = L_SMALL
+    V = int(np.prod(L))
+    U = bri.links_to_device(synth.smeared_links(L, SMALL_EPS, SMALL_SEED, APE_ALPHA, APE_STEPS), dev)
+    W = bri.build_links(L, U, bri.F64)
+    b = bri.spinor_to_device(synth.gaussian_source(L, SMALL_SRC_SEED), bri.F64, dev)
+    op = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+    ref64 = op.apply(b)[0].clone()
+    ms_ov = timed(lambda: op.apply(b), 5)
+    t_in, t_out = b.clone(), torch.empty_like(b)
+    bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
+    us_st = timed(lambda: bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out), stencil_reps) * 1e3
+    ex = {}
+    chi = bri.spinor_to_device(synth.gaussian_source(L, SMALL_SRC_SEED + 1), bri.F64, dev)
+    op.grad(U, chi[0], b[0])
+    ms_g = timed(lambda: op.grad(U, chi[0], b[0]), 2)
+    ex["grad_fp64_1src"] = {"ms_per_call": ms_g, "ratio_to_apply": ms_g / ms_ov}
+    for _ in range(3):
+        bri.wilson_apply(L, W, bri.F64, -RHO, t_in, out=t_out)
+    ms_w = timed(lambda: bri.wilson_apply(L, W, bri.F64, -RHO, t_in, out=t_out), stencil_reps)
+    opw = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=20000, kernel=bri.KERNEL_WILSON)
+    _, stw = opw.apply(b)
+    ms_ow = timed(lambda: opw.apply(b), 3)
+    ex["wilson_kernel_fp64_1src"] = {"stencil_us": ms_w * 1e3, "stencil_GBps_alg": 960 * V / (ms_w * 1e-3) / 1e9,
+                                     "overlap_applies_per_s": 1e3 / ms_ow, "cg_iterations": stw.iters,
+                                     "brillouin_stencil_us": us_st}
+    del opw
+    opr = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, relax=True)
+    orl, str_ = opr.apply(b)
+    ms_r = timed(lambda: opr.apply(b), 5)
+    ex["relaxed_fp64_1src"] = {"applies_per_s": 1e3 / ms_r, "cg_iterations": str_.iters,
+                               "rel_diff_vs_strict": float(torch.linalg.vector_norm(orl - ref64) /
+                                                           torch.linalg.vector_norm(ref64))}
+    opu = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, kind=bri.KL_UPPER)
+    ou, stu = opu.apply(b)
+    ms_u = timed(lambda: opu.apply(b), 5)
+    ex["upper_diagonal_fp64_1src"] = {"applies_per_s": 1e3 / ms_u, "cg_iterations": stu.iters,
+                                      "rel_diff_vs_diagonal": float(torch.linalg.vector_norm(ou - ref64) /
+                                                                    torch.linalg.vector_norm(ref64))}
+    Wc = bri.build_links(L, U, bri.F64, csw=1.0)
+    bri.apply(L, Wc, bri.F64, -RHO, t_in, out=t_out)
+    ms_c = timed(lambda: bri.apply(L, Wc, bri.F64, -RHO, t_in, out=t_out), stencil_reps)
+    opc = bri.OverlapOp(L, Wc, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+    _, stc = opc.apply(b)
+    ms_oc = timed(lambda: opc.apply(b), 5)
+    ex["clover_fp64_1src"] = {"csw": 1.0, "stencil_us": ms_c * 1e3, "stencil_GBps_alg": 7296 * V / (ms_c * 1e-3) / 1e9,
+                              "overlap_applies_per_s": 1e3 / ms_oc, "cg_iterations": stc.iters}
+    del Wc, opc
+    _, sts = op.solve(b, MASS, complete=True, tol=OUTER_TOL)
+    ms_s = timed(lambda: op.solve(b, MASS, complete=True, tol=OUTER_TOL), 1)
+    ex["massive_solve_fp64_1src"] = {"mass": MASS, "outer_tol": OUTER_TOL, "outer_iters": sts.iters,
+                                     "ov_applies": sts.applies, "ms_per_solve": ms_s,
+                                     "ms_per_ov_apply": ms_s / sts.applies, "true_rel_resid": sts.rel_resid}
+    ex["cascaded_16x16x16x32"] = cascade_table(dev)
+    ex["kernel_quality_16x16x16x32"] = quality_table(dev)
+    return ex
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -351,14 +500,12 @@ def main():
     if args.survey:
         survey(torch, bri, synth)
         return
-    if args.stencil_only and args.lattice:
-        stencil_only_large(torch, bri, synth, tuple(int(v) for v in args.lattice.split(",")), args.stencil_reps)
-        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     L = L_BENCH
     V = int(np.prod(L))
+    inner = {"f32": bri.F32, "bf16w": bri.F32_BF16W}[args.inner]
 
     def timed(fn, reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -369,94 +516,86 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps  # ms
 
-    print(f"[bench] generating links {L} eps={LINK_EPS} APE {APE_STEPS}x{APE_ALPHA}", file=sys.stderr, flush=True)
-    U_np = synth.smeared_links(L, LINK_EPS, LINK_SEED, APE_ALPHA, APE_STEPS)
-    U = bri.links_to_device(U_np, dev)
-    b = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED), bri.F64, dev)
+    print(f"[bench] links {L} exp({LINK_EPS} i A) + {APE_STEPS} APE({APE_ALPHA}) on the device", file=sys.stderr,
+          flush=True)
+    U = synth.smeared_links_torch(L, LINK_EPS, LINK_SEED, APE_ALPHA, APE_STEPS, device=dev, chunk=1 << 18)
+    U = U.permute(0, 2, 3, 1).contiguous()
     W = torch.empty((40, 3, 3, V), dtype=torch.complex128, device=dev)
-    out = torch.empty_like(b)
+    Wlo = torch.empty((40, 3, 3, V), dtype=bri.link_dtype(inner), device=dev)
     bri.build_links(L, U, bri.F64, out=W)
+    bri.build_links(L, U, inner, out=Wlo)
+    b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
     if args.tune:
-        cfg, us = bri.autotune(L, W, bri.F64, b, reps=5)
-        print(f"[bench] tuned FP64 stencil: {us:.1f} us {cfg.as_dict()}", file=sys.stderr, flush=True)
-    tuned = bri.get_stencil_cfg(L, bri.F64, 1).as_dict()
+        for p, Wp in ((bri.F64, W), (inner, Wlo)):
+            x = b12[:1].to(bri.spinor_dtype(p)).contiguous()
+            cfg, us = bri.autotune(L, Wp, p, x, reps=3)
+            print(f"[bench] tuned stencil prec {p}: {us:.1f} us {cfg.as_dict()}", file=sys.stderr, flush=True)
 
     if args.stencil_only:
         # calibration copy of 1 GiB (beyond the 256 MB Infinity Cache), then the stencil
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         c = torch.empty_like(a)
         c.copy_(a)
+        del a, c
         torch.cuda.synchronize()
-        t_in, t_out = b.clone(), torch.empty_like(b)
+        t_in = b12[:1].clone()
+        t_out = torch.empty_like(t_in)
         for _ in range(args.stencil_reps):
             bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
         torch.cuda.synchronize()
-        rec = {"stencil_only": True, "launches": args.stencil_reps, "copy_bytes": 1 << 30,
-               "kernel_src_sha": kernel_source_digest(), "config": tuned}
+        rec = {"stencil_only": True, "lattice": list(L), "launches": args.stencil_reps, "copy_bytes": 1 << 30,
+               "alg_bytes_per_launch": stencil_bytes_per_site(8, 8) * V, "kernel_src_sha": kernel_source_digest(),
+               "config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict()}
         if args.stencil_rhs > 1:
-            # the multi-RHS kernel in its default configuration, FP64 and FP32 links and vectors
             nr = args.stencil_rhs
-            src = synth.gaussian_source(L, SRC_SEED, nrhs=nr)
-            for prec, name in ((bri.F64, "f64"), (bri.F32, "f32")):
-                Wp = W if prec == bri.F64 else bri.build_links(L, U, prec)
-                xm = bri.spinor_to_device(src, prec, dev)
+            for prec, Wp, name in ((bri.F64, W, "f64"), (bri.F32, bri.build_links(L, U, bri.F32), "f32")):
+                xm = torch.randn((nr, 4, 3, V), dtype=bri.spinor_dtype(prec), device=dev)
                 ym = torch.empty_like(xm)
-                bri.apply(L, Wp, prec, -RHO, xm, out=ym)  # first launch loads the kernel's code object
-                ms = timed(lambda: bri.apply(L, Wp, prec, -RHO, xm, out=ym), args.stencil_reps)
+                bri.apply(L, Wp, prec, -RHO, xm, out=ym)
+                ms = timed(lambda: bri.apply(L, Wp, prec, -RHO, xm, out=ym), 5)
                 rec[f"mrhs_{name}_{nr}rhs"] = {"us": ms * 1e3, "config": bri.get_stencil_cfg(L, prec, nr).as_dict()}
-                del Wp, xm, ym
+                del xm, ym
         print(json.dumps(rec), flush=True)
         return
 
-    if args.batched_only:
-        # the 12 spin-colour point sources side by side, one multi-shift with per-column scalars
-        b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
-        o12 = torch.empty_like(b12)
-        op12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, nrhs=12)
-        for _ in range(args.warmup):
-            op12.apply(b12, out=o12)
-        ms = timed(lambda: op12.apply(b12, out=o12), args.steps)
-        _, st12 = op12.apply(b12, out=o12)
-        print(json.dumps({"batched_only": True, "sources": 12, "calls": args.steps, "ms_per_call": ms,
-                          "applies_per_s": 12 / (ms / 1e3), "cg_iterations": st12.iters,
-                          "config": bri.get_stencil_cfg(L, bri.F64, 12).as_dict()}), flush=True)
-        return
-
-    op = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+    cases = golden_cases(L)
+    o12 = torch.empty_like(b12)
+    opm = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, Wlo=Wlo, inner=inner, nrhs=NSRC)
 
     def step():
         bri.build_links(L, U, bri.F64, out=W)
-        _, st = op.apply(b, out=out)
+        bri.build_links(L, U, inner, out=Wlo)
+        _, st = opm.apply(b12, out=o12)
         return st
 
     for _ in range(args.warmup):
         st = step()
     torch.cuda.synchronize()
-    print(f"[bench] warmup done, {st.iters} CG iterations per apply", file=sys.stderr, flush=True)
-
+    print(f"[bench] warmup done, {st.iters} CG iterations ({st.refine} in low precision)", file=sys.stderr,
+          flush=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    iters = []
+    stats = []
     for _ in range(args.steps):
-        st = step()
-        iters.append(st.iters)
+        stats.append(step())
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
-    value = b.shape[0] / (ms_step / 1e3)
-    ref64 = out.clone()
-    print(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step (host wall {wall:.3f} s)", file=sys.stderr, flush=True)
+    print(f"[bench] {args.steps} steps, {ms_step:.1f} ms/step (host wall {wall:.2f} s)", file=sys.stderr, flush=True)
+    gate_rows = gate(torch, bri, synth, o12, cases)
+    gate_ok = bool(gate_rows) and all(r["pass"] for r in gate_rows)
+    rate = NSRC / (ms_step / 1e3)
+    print(f"[bench] gate against stored oracle outputs: {gate_rows}", file=sys.stderr, flush=True)
+    last = stats[-1]
 
-    # dominant kernel: the FP64 stencil, timed live with events on the same stream
-    t_in, t_out = b.clone(), torch.empty_like(b)
-    for _ in range(5):
+    # dominant kernel family: the FP64 stencil at 32^3x64, timed live on the stream it runs on
+    t_in, t_out = b12[:1].clone(), torch.empty_like(b12[:1])
+    for _ in range(3):
         bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out)
-    torch.cuda.synchronize()
-    ms_launch = timed(lambda: bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps)
-    us_launch = ms_launch * 1e3
+    us_launch = timed(lambda: bri.apply(L, W, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps) * 1e3
     alg_bytes = stencil_bytes_per_site(8, 8) * V
     achieved = alg_bytes / (us_launch * 1e-6) / 1e9
     traffic = measured_traffic()
@@ -464,7 +603,7 @@ def main():
 
     result = {
         "metric": "D_bri apply GB/s (% HBM peak); overlap applies/s at 1e-10, mixed vs FP64",
-        "value": value,
+        "value": rate if gate_ok else 0.0,
         "unit": "overlap applies/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -473,27 +612,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if inner == bri.F32 else "f64+f32/bf16",
         "data": "synthetic",
         "config": {
-            "workload": "16^4 FP64 single-RHS overlap apply, Kenney-Laub [16/16], rho=1, CG tol 1e-12, "
-            "links exp(0.5iA) + 3 APE(0.6), Gaussian source; step = bri_build_links + ov_apply",
+            "workload": f"32^3x64, 12 spin-colour point sources x Kenney-Laub [16/16] (16 shifts), rho=1, per-shift "
+            f"CG tol 1e-12, links exp(0.7iA) + 3 APE(0.6); mixed-precision batched ov_apply (FP64 multi-shift, "
+            f"{args.inner} links and vectors once the residual allows, FP64 final apply); "
+            f"step = bri_build_links (FP64 + {args.inner}) + ov_apply over the 12 sources",
             "lattice": list(L),
             "kl_n": KL_N,
-            "nrhs": int(b.shape[0]),
-            "precision": "fp64",
-            "cg_iterations": int(np.median(iters)),
-            "stencil_config": tuned,
+            "nrhs": NSRC,
+            "inner": args.inner,
+            "cg_iterations": int(last.iters),
+            "low_precision_iterations": int(last.refine),
+            "stencil_config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict(),
         },
+        "gate": {"tol": GATE_TOL, "checked": gate_rows, "pass": gate_ok, "applies_per_s_measured": rate},
         "roofline": {
             "bound": "hbm",
-            "kernel": "bri_apply FP64 1-RHS (stencil_kernel<LinkF64,nsplit,false,EPI_PLAIN>)",
+            "kernel": "bri_apply FP64 1-RHS at 32^3x64 (default launch: stencil_xline_kernel<LinkF64, 4, false, EPI_PLAIN>)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": None if traffic is None else traffic / (us_launch * 1e-6) / 1e9,
             "traffic_bytes_per_launch": traffic,
+            "traffic_ratio": None if traffic is None else traffic / alg_bytes,
             "us_per_launch": us_launch,
             "alg_bytes_per_launch": alg_bytes,
         },
@@ -501,137 +645,69 @@ def main():
 
     if not args.no_extra:
         extra = {}
-        # 12 spin-colour point sources, batched FP64
-        b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
-        o12 = torch.empty_like(b12)
-        if args.tune:
-            bri.autotune(L, W, bri.F64, b12, reps=3)
-        op12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, nrhs=12)
-        op12.apply(b12, out=o12)
-        ms = timed(lambda: op12.apply(b12, out=o12), 3)
-        extra["batched_fp64_12src"] = {"applies_per_s": 12 / (ms / 1e3), "ms_per_call": ms}
-        ref12 = o12.clone()
-        # single-source FP64 on the point source 0 for the per-solve error of the mixed runs
-        for name, inner in (("mixed_f32", bri.F32), ("mixed_bf16w", bri.F32_BF16W)):
-            Wlo = bri.build_links(L, U, inner)
-            opm = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, Wlo=Wlo, inner=inner)
-            om = torch.empty_like(b)
-            _, stm = opm.apply(b, out=om)
-            ms = timed(lambda: opm.apply(b, out=om), 2)
-            err = float(torch.linalg.vector_norm(om - ref64) / torch.linalg.vector_norm(ref64))
-            extra[name + "_1src"] = {"applies_per_s": 1 / (ms / 1e3), "ms_per_call": ms, "refine_passes": stm.refine,
-                                     "rel_err_vs_fp64": err}
-            opm12 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, Wlo=Wlo, inner=inner, nrhs=12)
-            om12 = torch.empty_like(b12)
-            opm12.apply(b12, out=om12)
-            ms = timed(lambda: opm12.apply(b12, out=om12), 1)
-            errs = [float(torch.linalg.vector_norm(om12[r] - ref12[r]) / torch.linalg.vector_norm(ref12[r]))
-                    for r in range(12)]
-            extra[name + "_12src"] = {"applies_per_s": 12 / (ms / 1e3), "ms_per_call": ms,
-                                      "max_rel_err_vs_fp64": max(errs)}
-            del opm, opm12, Wlo
-            torch.cuda.empty_cache()
-        # HIP-graph replay of the CG loop against plain launches, here and on a small lattice
-        graphs = {}
-        for Lg in (L, (8, 8, 8, 8)):
-            if Lg == L:
-                opg, bg = op, b
-            else:
-                Ug = bri.links_to_device(synth.smeared_links(Lg, LINK_EPS, LINK_SEED, APE_ALPHA, APE_STEPS), dev)
-                Wg = bri.build_links(Lg, Ug, bri.F64)
-                opg = bri.OverlapOp(Lg, Wg, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
-                bg = bri.spinor_to_device(synth.gaussian_source(Lg, SRC_SEED), bri.F64, dev)
-            og = torch.empty_like(bg)
-            row = {}
-            for on in (False, True):
-                bri.set_solver_graphs(on)
-                opg.apply(bg, out=og)
-                row["ms_graphs_on" if on else "ms_graphs_off"] = timed(lambda: opg.apply(bg, out=og), 10)
-            graphs["x".join(str(v) for v in Lg)] = row
-        extra["cg_graph_replay"] = graphs
-        # gradient of Re chi^dag D_ov psi (force on the links and D_ov^dag chi), FP64
-        chi = bri.spinor_to_device(synth.gaussian_source(L, SRC_SEED + 1), bri.F64, dev)
-        op.grad(U, chi[0], b[0])
-        ms_g = timed(lambda: op.grad(U, chi[0], b[0]), 2)
-        pairs = [(1.0, chi[0], b[0])] * (2 * KL_N + 1)
-        bri.link_grad(L, U, W, pairs)
-        ms_f = timed(lambda: bri.link_grad(L, U, W, pairs), 3)
-        extra["grad_fp64_1src"] = {"ms_per_call": ms_g, "ratio_to_step": ms_g / ms_step,
-                                   "link_force_ms_%d_pairs" % (2 * KL_N + 1): ms_f}
-        # the Wilson kernel (eq. (def_wils)) on the same links: its 9-point stencil (four link
-        # matrices, one spinor in and out per site: 960 B/site in FP64) and its overlap apply
-        for _ in range(5):
-            bri.wilson_apply(L, W, bri.F64, -RHO, t_in, out=t_out)
-        ms_w = timed(lambda: bri.wilson_apply(L, W, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps)
-        opw = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=20000, kernel=bri.KERNEL_WILSON)
-        ow = torch.empty_like(b)
-        _, stw = opw.apply(b, out=ow)
-        ms_ow = timed(lambda: opw.apply(b, out=ow), 3)
-        extra["wilson_kernel_fp64_1src"] = {
-            "stencil_us": ms_w * 1e3, "stencil_GBps_alg": 960 * V / (ms_w * 1e-3) / 1e9,
-            "overlap_applies_per_s": 1 / (ms_ow / 1e3), "overlap_ms_per_call": ms_ow, "cg_iterations": stw.iters,
-            "brillouin_cg_iterations": int(np.median(iters)), "brillouin_stencil_us": us_launch}
-        del opw, ow
-        # relaxed per-shift stopping (tol * omega_max / omega_i) against the strict apply
-        opr = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, relax=True)
-        orl = torch.empty_like(b)
-        _, str_ = opr.apply(b, out=orl)
-        ms_r = timed(lambda: opr.apply(b, out=orl), 10)
-        extra["relaxed_fp64_1src"] = {
-            "applies_per_s": 1 / (ms_r / 1e3), "ms_per_call": ms_r, "cg_iterations": str_.iters,
-            "rel_diff_vs_strict": float(torch.linalg.vector_norm(orl - ref64) / torch.linalg.vector_norm(ref64))}
-        del opr, orl
-        # the first upper-diagonal rational g_{2n} (Sec. 3.3; no constant term), n = KL_N shifts
-        opu = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, kind=bri.KL_UPPER)
-        ou = torch.empty_like(b)
-        _, stu = opu.apply(b, out=ou)
-        ms_u = timed(lambda: opu.apply(b, out=ou), 10)
-        extra["upper_diagonal_fp64_1src"] = {
-            "applies_per_s": 1 / (ms_u / 1e3), "ms_per_call": ms_u, "cg_iterations": stu.iters,
-            "rel_diff_vs_diagonal": float(torch.linalg.vector_norm(ou - ref64) / torch.linalg.vector_norm(ref64))}
-        del opu, ou
-        # the clover-improved Brillouin kernel, c_SW = 1: 72 clover entries per site after the 40
-        # link slabs (7296 B/site algorithmic in FP64), and its overlap apply
-        Wc = bri.build_links(L, U, bri.F64, csw=1.0)
-        for _ in range(5):
-            bri.apply(L, Wc, bri.F64, -RHO, t_in, out=t_out)
-        ms_c = timed(lambda: bri.apply(L, Wc, bri.F64, -RHO, t_in, out=t_out), args.stencil_reps)
-        opc = bri.OverlapOp(L, Wc, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
-        oc = torch.empty_like(b)
-        _, stc = opc.apply(b, out=oc)
-        ms_oc = timed(lambda: opc.apply(b, out=oc), 10)
-        extra["clover_fp64_1src"] = {
-            "csw": 1.0, "stencil_us": ms_c * 1e3, "stencil_GBps_alg": 7296 * V / (ms_c * 1e-3) / 1e9,
-            "overlap_applies_per_s": 1 / (ms_oc / 1e3), "overlap_ms_per_call": ms_oc, "cg_iterations": stc.iters}
-        del Wc, opc, oc
-        # massive overlap solve, complete form of Sec. 4 with the BiCGstab outer solver, am = 0.05
-        xs, sts = op.solve(b, MASS, complete=True, tol=OUTER_TOL)
-        ms_s = timed(lambda: op.solve(b, MASS, complete=True, tol=OUTER_TOL), 1)
-        extra["massive_solve_fp64_1src"] = {
-            "mass": MASS, "outer_tol": OUTER_TOL, "outer_iters": sts.iters, "ov_applies": sts.applies,
-            "inner_cg_iters": sts.inner_iters, "ms_per_solve": ms_s, "ms_per_ov_apply": ms_s / sts.applies,
-            "true_rel_resid": sts.rel_resid}
-        del xs
-        # the same solve for the 12 spin-colour point sources side by side (the paper's batch)
-        x12, st12 = op12.solve(b12, MASS, complete=True, tol=OUTER_TOL)
-        ms_s12 = timed(lambda: op12.solve(b12, MASS, complete=True, tol=OUTER_TOL), 1)
-        extra["massive_solve_fp64_12src"] = {
-            "mass": MASS, "outer_tol": OUTER_TOL, "outer_iters": st12.iters, "ms_per_solve": ms_s12,
-            "ms_per_rhs": ms_s12 / 12, "speedup_per_rhs_vs_1src": ms_s / (ms_s12 / 12),
-            "true_rel_resid_worst": st12.rel_resid}
-        del x12
-        extra["cascaded_16x16x16x32"] = cascade_table(dev)
-        extra["kernel_quality_16x16x16x32"] = quality_table(dev)
-        best_mixed = max(extra[k]["applies_per_s"] for k in extra if k.startswith("mixed"))
-        extra["fp64_1src_applies_per_s"] = value
-        extra["speedup_batched_fp64_vs_fp64_1src"] = extra["batched_fp64_12src"]["applies_per_s"] / value
-        extra["speedup_best_mixed_vs_fp64_1src"] = best_mixed / value
+        # FP64 single source (the speedup's denominator) and the FP64 batch, same workload
+        op1 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000)
+        o1 = torch.empty_like(b12[:1])
+        srcs = [b12[r:r + 1].contiguous() for r in (0, 7, 11)]
+        op1.apply(srcs[0], out=o1)
+        ms1 = timed(lambda: [op1.apply(s, out=o1) for s in srcs], 1) / len(srcs)
+        _, st1 = op1.apply(srcs[0], out=o1)
+        del op1, o1
+        op64 = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, tol=CG_TOL, max_iter=5000, nrhs=NSRC)
+        o64 = torch.empty_like(b12)
+        op64.apply(b12, out=o64)
+        ms64 = timed(lambda: op64.apply(b12, out=o64), 2)
+        gate64 = gate(torch, bri, synth, o64, cases)
+        _, st64 = op64.apply(b12, out=o64)
+        diff = float(torch.linalg.vector_norm(o12 - o64) / torch.linalg.vector_norm(o64))
+        del op64, o64
+        torch.cuda.empty_cache()
+        r1 = 1e3 / ms1
+        r64 = NSRC * 1e3 / ms64
+        extra["fp64_1src"] = {"applies_per_s": r1, "ms_per_apply": ms1, "cg_iterations": st1.iters}
+        extra["fp64_12src"] = {"applies_per_s": r64, "ms_per_call": ms64, "cg_iterations": st64.iters,
+                               "gate": gate64}
+        extra["mixed_12src"] = {"applies_per_s": rate, "ms_per_step": ms_step, "rel_diff_vs_fp64_batch": diff,
+                                "shift_rel_resid_max": max(last.rel_resid)}
+        extra["speedup_mixed_12src_vs_fp64_1src"] = rate / r1
+        extra["speedup_mixed_12src_vs_fp64_12src"] = rate / r64
+        extra["speedup_fp64_12src_vs_fp64_1src"] = r64 / r1
+        # the FP32 stencil beside the FP64 roofline, and the multi-RHS kernels in flops
+        W32 = Wlo if inner == bri.F32 else bri.build_links(L, U, bri.F32)
+        x32 = t_in.to(torch.complex64)
+        y32 = torch.empty_like(x32)
+        bri.apply(L, W32, bri.F32, -RHO, x32, out=y32)
+        us32 = timed(lambda: bri.apply(L, W32, bri.F32, -RHO, x32, out=y32), args.stencil_reps) * 1e3
+        a32 = stencil_bytes_per_site(4, 4) * V
+        extra["stencil_f32_1rhs"] = {"us_per_launch": us32, "achieved_GBps": a32 / (us32 * 1e-6) / 1e9,
+                                     "frac": a32 / (us32 * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+                                     "config": bri.get_stencil_cfg(L, bri.F32, 1).as_dict()}
+        for prec, Wp, name, peak in ((bri.F64, W, "f64", FP64_PEAK_TFLOPS), (bri.F32, W32, "f32", FP32_PEAK_TFLOPS)):
+            xm = b12.to(bri.spinor_dtype(prec))
+            ym = torch.empty_like(xm)
+            bri.apply(L, Wp, prec, -RHO, xm, out=ym)
+            us = timed(lambda: bri.apply(L, Wp, prec, -RHO, xm, out=ym), 5) * 1e3
+            tf = FLOP_PER_SITE_RHS * V * NSRC / (us * 1e-6) / 1e12
+            extra[f"stencil_{name}_12rhs"] = {"us_per_launch": us, "TFLOPs": tf, "peak_TFLOPs": peak,
+                                              "frac_of_peak": tf / peak,
+                                              "config": bri.get_stencil_cfg(L, prec, NSRC).as_dict()}
+            del xm, ym
+        del W32, x32, y32
+        torch.cuda.empty_cache()
+        extra["16x16x16x16"] = small_line(torch, bri, synth, dev, timed)
+        if args.extras:
+            extra.update(extras_16(torch, bri, synth, dev, timed, args.stencil_reps))
         result["extra"] = extra
         print(f"[bench] extra: {json.dumps(extra)}", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         print("[bench] CPU oracle sample ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(L, U_np, st.shift_iters, args.cpu_seconds)
+        its = [c["shift_iters"] for c in cases if str(c["source_kind"]) == "point"]
+        note = "per-shift CG iterations of the oracle's own runs on this field"
+        if not its:
+            its = [last.shift_iters]
+            note = "per-shift iterations of the GPU multi-shift on this field (no stored oracle run)"
+        result["cpu_baseline"] = cpu_baseline(its, note, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -154,10 +154,11 @@ typedef struct {
     int kl_n;       /* Kenney-Laub order n: f_{n,n} = g_{2n+1}, 1..BRI_MAX_SHIFTS */
     double rho;     /* 0 < rho < 2; kernel mass m0 = -rho                        */
     double tol;     /* per-shift stop: |b - (A + sigma) x_sigma| <= tol |psi|    */
-    int max_iter;   /* CG iteration cap of each (multi-shift or correction) solve */
-    int inner;      /* bri_prec of the multi-shift: BRI_F64, or BRI_F32 /
-                       BRI_F32_BF16W with FP64 defect correction of every shift */
-    int max_refine; /* mixed precision: FP64 residual + correction passes, 0..100 */
+    int max_iter;   /* multi-shift CG iteration cap                              */
+    int inner;      /* bri_prec of the late iterations: BRI_F64 (all FP64), or
+                       BRI_F32 / BRI_F32_BF16W (FP32 vectors on Wlo once the base
+                       residual has fallen to tol / u_lo |psi|, see ov_apply)   */
+    int max_refine; /* unused (0..100 accepted)                                 */
     int kind;       /* bri_kl_kind; BRI_KL_DIAG unless stated                   */
     int relax;      /* 1: shift i stops at tol * omega_max / omega_i (App. B: the
                        weights grow with the shift, so small shifts may stop at a
@@ -166,12 +167,13 @@ typedef struct {
                        stated                                                  */
 } ov_params;
 
-/* Statistics of one overlap apply (the last right-hand side for nrhs > 1). */
+/* Statistics of one overlap apply; for nrhs > 1 each figure is the worst column's. */
 typedef struct {
     int iters;                          /* multi-shift CG iterations            */
-    int refine;                         /* defect-correction passes             */
+    int refine;                         /* of those, run in the low-precision phase */
     int shift_iters[BRI_MAX_SHIFTS];    /* iteration at which each shift stopped */
-    double rel_resid[BRI_MAX_SHIFTS];   /* |zeta_sigma r| / |psi| at that point  */
+    double rel_resid[BRI_MAX_SHIFTS];   /* |zeta_sigma r| / |psi| at that point (the
+                                           recursively updated residual)        */
     double seconds;                     /* host wall time of the call            */
 } ov_stats;
 
@@ -183,9 +185,14 @@ typedef struct {
  * shifts at once (Sec. 3.3), with the coefficients of eq. (KLnn_parfrac) (or of the
  * first upper diagonal, params->kind); the
  * nrhs right-hand sides run side by side, each with its own Krylov space.
- * With a low-precision inner solve the multi-shift runs on Wlo, every shift
- * solution is kept, and each (shift, source) column is corrected against its
- * FP64 residual (formed with W64) until it meets tol.
+ * Mixed precision (inner = BRI_F32 or BRI_F32_BF16W): the multi-shift runs in FP64
+ * until the base residual of every right-hand side is at most (tol / u_lo) |psi|,
+ * u_lo = 2^-24 (BRI_F32) or 2^-8 (BRI_F32_BF16W); from there (at once if that
+ * bound exceeds 1) its vectors r, p, p_sigma are FP32 and its stencils read Wlo,
+ * while y = c0 psi + sum omega_sigma x_sigma keeps accumulating in FP64 and every
+ * scalar stays FP64.  A low-precision product then perturbs the result by about
+ * tol |psi| (the relaxation rule of inexact Krylov methods), so no shift needs a
+ * separate correction.  The final X y uses W64.
  *   W64 : [40][3][3][V] complex double off-axis links ([48]... with the clover term)
  *   Wlo : links in precision `inner` (from bri_build_links); NULL when inner = BRI_F64
  *   in, out : [nrhs][4][3][V] complex double (device); must not overlap each other or the
@@ -398,16 +405,15 @@ int wil_link_grad(const bri_geom *geom, const void *U, const void *W, int npairs
  *   gpsi = D_ov^dag chi = rho (chi + c0 X^dag chi + sum_i omega_i b_i)
  *        (= dS/dRe psi + i dS/dIm psi).
  * The a_i and b_i come from one two-column multi-shift solve that keeps every
- * shift solution: in FP64 (params->inner = BRI_F64), or in low precision on Wlo
- * with every (shift, column) refined against its FP64 residual to params->tol,
- * as ov_apply does (at most max_refine passes).
+ * shift solution (x_sigma accumulated in FP64): all FP64 (params->inner = BRI_F64), or
+ * with the late iterations on FP32 vectors and the links Wlo, as ov_apply does.
  *   U, W64  as bri_link_grad (W64 built from U with geom->tbc)
  *   Wlo     links in precision params->inner; NULL when inner = BRI_F64
  *   chi, psi, gpsi  [4][3][V] complex double
  *   F, GU   as bri_link_grad (at least one non-NULL)
  *   work, work_bytes  device workspace (query with work == NULL)
- *   stats   may be NULL: iterations, refinement passes and the final residual of
- *           each shift (worst of the two columns)
+ *   stats   may be NULL: iterations (of them in low precision) and the final residual
+ *           of each shift (worst of the two columns)
  * Synchronises `stream`.  Returns BRI_ENOCONV when a shift missed tol within
  * max_iter (the outputs then use the last iterates), BRI_ENAN on a non-finite
  * residual, BRI_EINVAL for bad arguments (V must be a multiple of 64; F, GU, gpsi and work must

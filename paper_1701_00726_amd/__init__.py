@@ -399,8 +399,9 @@ class OverlapOp:
     def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0,
                  max_refine=None, nrhs=1, kind=KL_DIAG, relax=False, kernel=KERNEL_BRILLOUIN):
         """Workspace for up to `nrhs` right-hand sides per call.  inner = F32 or
-        F32_BF16W runs the multi-shift with the low-precision links `Wlo` and refines
-        every shift in FP64 (at most max_refine passes, default 10).  kind = KL_UPPER
+        F32_BF16W runs the late multi-shift iterations (once the residual has fallen to
+        tol / unit roundoff) on FP32 vectors with the low-precision links `Wlo`,
+        accumulating the result in FP64 (max_refine is unused).  kind = KL_UPPER
         uses the first upper diagonal g_{2n} instead of g_{2n+1}; relax stops shift i
         at tol * omega_max / omega_i; kernel = KERNEL_WILSON builds the overlap on the
         Wilson operator (the one-hop slabs of W64) instead of the Brillouin one."""
@@ -413,7 +414,7 @@ class OverlapOp:
         if inner != F64 and Wlo is None:
             raise ValueError("a low-precision inner solve needs Wlo")
         if max_refine is None:
-            max_refine = 0 if inner == F64 else 10
+            max_refine = 0
         self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine),
                                 int(kind), 1 if relax else 0, int(kernel))
         self.nrhs = int(nrhs)
@@ -463,7 +464,7 @@ class OverlapOp:
 
         U is the (4, 3, 3, V) complex128 field W64 was built from (with this
         operator's tbc).  The shift solves run in this operator's inner precision
-        (low-precision inner solves are refined to tol in FP64).  Returns (F or None, GU or None, grad_psi, OvStats) with
+        (low-precision late iterations as in apply).  Returns (F or None, GU or None, grad_psi, OvStats) with
         F (4, 8, V) the force, GU (4, 3, 3, V) = dS/dRe U + i dS/dIm U and
         grad_psi = D_ov^dag chi of the shape of psi."""
         torch = _torch()

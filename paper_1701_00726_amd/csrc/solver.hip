@@ -21,12 +21,19 @@
 // direction is p itself.  When only y = c0 b + sum_sigma omega_sigma x^sigma is
 // needed the x^sigma are never stored: y accumulates omega_sigma alpha^sigma p^sigma.
 //
-// Mixed precision (inner = BRI_F32 or BRI_F32_BF16W): the multi-shift runs with
-// low-precision links and vectors, keeping every x^sigma.  Then, repeatedly, the
-// residual r^sigma = b - (A + sigma) x^sigma of every (shift, source) column is
-// formed in FP64 with the FP64 links, and the corrections (A + sigma) e = r^sigma
-// are solved in low precision as a batch of single-shift CGs (one shift per
-// column); x^sigma += e in FP64.  Finally y and the output are formed in FP64.
+// Mixed precision (inner = BRI_F32 or BRI_F32_BF16W): the same multi-shift recurrences, with the
+// precision of the operator and of the Krylov vectors relaxed as the residual falls.  A matrix-
+// vector product whose relative error is u perturbs the recursively updated residual, and with
+// it every shifted solution, by about u |r_k| (inexact Krylov methods: van den Eshof and Sleijpen,
+// SIAM J. Matrix Anal. Appl. 26 (2004) 125; Simoncini and Szyld, SIAM J. Sci. Comput. 25 (2003)
+// 454).  So the iterations run in FP64 until the base residual of every column has fallen to
+// |r| <= (tol / u_lo) |b|, u_lo the unit roundoff of the low precision (2^-24 for FP32 links
+// and vectors, 2^-8 for bfloat16 links); then r, p and the p^sigma are rounded to FP32 once and
+// the remaining iterations apply the stencil with the low-precision links on FP32 vectors,
+// while y (or every x^sigma) keeps accumulating in FP64 and all scalars stay FP64.  Each late
+// iteration's rounding is then of order tol |b|, the level the shifts stop at; no shift needs
+// a separate correction solve, so the multi-shift structure (one Krylov space for all shifts)
+// is kept to the end.  The output is formed from the FP64 y with the FP64 links.
 //
 // All solver scalars live on the device (ColState) and are updated by small
 // kernels; the host only polls a done flag every few iterations, and every
@@ -247,10 +254,10 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
 // before any store, so the independent streams overlap in flight.
 constexpr int UPD_BATCH = 8;
 
-template <typename C>
+template <typename C, typename Y>
 __global__ __launch_bounds__(256) void ms_update_kernel(const ColState *__restrict__ states, size_t n, int ncol,
                                                         const C *__restrict__ r, C *__restrict__ p,
-                                                        C *__restrict__ y, C *__restrict__ x, C *__restrict__ ps) {
+                                                        Y *__restrict__ y, Y *__restrict__ x, C *__restrict__ ps) {
     const int col = blockIdx.y;
     const ColState *st = states + col;
     const int done = st->done;
@@ -261,10 +268,11 @@ __global__ __launch_bounds__(256) void ms_update_kernel(const ColState *__restri
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const C ri = r[off + i];
         C pi = p[off + i];
-        C yi;
+        Y yi;
         if (y) yi = y[off + i];
         for (int k0 = 0; k0 < ns; k0 += UPD_BATCH) {
-            C v[UPD_BATCH], xv[UPD_BATCH];
+            C v[UPD_BATCH];
+            Y xv[UPD_BATCH];
 #pragma unroll
             for (int b = 0; b < UPD_BATCH; ++b) {
                 const int k = k0 + b;
@@ -310,48 +318,34 @@ static inline int update_blocks(size_t n) {
     return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
-// done 2 -> 1 for every column; *alldone = 1 once every column is done
-__global__ void ms_finish_kernel(ColState *states, int ncol, int *alldone) {
-    __shared__ int cnt[256];
-    int mine = 0;
+// done 2 -> 1 for every column; *alldone = 1 once every column is done, else 2 when sw2 > 0 and
+// every column still iterating has |r|^2 <= sw2 |b|^2 (time for the low-precision phase), else 0
+__global__ void ms_finish_kernel(ColState *states, int ncol, int *alldone, double sw2) {
+    __shared__ int cnt[256], low[256];
+    int mine = 0, below = 0;
     for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
         if (states[c].done == 2) states[c].done = 1;
         mine += states[c].done != 0;
+        below += states[c].done != 0 || states[c].rr <= sw2 * states[c].bnorm2;
     }
     cnt[threadIdx.x] = mine;
+    low[threadIdx.x] = below;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        if ((int)threadIdx.x < w) {
+            cnt[threadIdx.x] += cnt[threadIdx.x + w];
+            low[threadIdx.x] += low[threadIdx.x + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *alldone = (cnt[0] == ncol) ? 1 : 0;
+    if (threadIdx.x == 0) *alldone = (cnt[0] == ncol) ? 1 : ((sw2 > 0.0 && low[0] == ncol) ? 2 : 0);
 }
 
-// y = c0 b + sum_k omega_k x_k (FP64), column c = blockIdx.y
-__global__ void combine_kernel(size_t n, int ncol, int nshift, double c0, const double *__restrict__ omega,
-                               const double2 *__restrict__ b, const double2 *__restrict__ x, double2 *__restrict__ y) {
-    const int col = blockIdx.y;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const double2 bv = b[(size_t)col * n + i];
-        double2 v = make_double2(c0 * bv.x, c0 * bv.y);
-        for (int k = 0; k < nshift; ++k) {
-            const double2 xv = x[((size_t)k * ncol + col) * n + i];
-            v.x += omega[k] * xv.x;
-            v.y += omega[k] * xv.y;
-        }
-        y[(size_t)col * n + i] = v;
-    }
-}
-
-// dst = src (widened to FP64), or dst += src with accumulate
-template <typename S>
-__global__ void widen_kernel(size_t count, const S *__restrict__ src, double2 *__restrict__ dst, int accumulate) {
+// dst = src rounded to FP32 (the Krylov vectors entering the low-precision phase)
+__global__ void narrow_kernel(size_t count, const double2 *__restrict__ src, float2 *__restrict__ dst) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
-        const S v = src[i];
-        double2 d = accumulate ? dst[i] : make_double2(0.0, 0.0);
-        d.x += (double)v.x;
-        d.y += (double)v.y;
-        dst[i] = d;
+        const double2 v = src[i];
+        dst[i] = make_float2((float)v.x, (float)v.y);
     }
 }
 
@@ -441,11 +435,20 @@ struct Arena {
     }
 };
 
+// unit roundoff of the low-precision operator: FP32 links and vectors, or bfloat16 links
+inline double unit_roundoff(int prec) { return prec == BRI_F32_BF16W ? 0x1p-8 : 0x1p-24; }
+
 // One batched multi-shift solve: ncol columns, nshift shifts each.
 struct MsSolve {
     Geom g;
-    int prec = BRI_F64;  // vector / stencil precision
+    int prec = BRI_F64;  // vectors and stencil of the first phase (FP64)
     const void *W = nullptr;
+    // low-precision phase: once every column has |r| <= lo_switch |b| the
+    // iterations continue on FP32 vectors with the links Wlo of precision prec_lo; y / x stay FP64
+    int prec_lo = -1;
+    const void *Wlo = nullptr;
+    double lo_switch = 0.0;
+    void *r_lo = nullptr, *p_lo = nullptr, *t_lo = nullptr, *ps_lo = nullptr;
     double m0 = 0.0;
     int kind = KERN_BRI;  // kernel operator X = D_kind(m0)
     int ncol = 1, nshift = 1;
@@ -463,7 +466,6 @@ struct MsSolve {
     void *r = nullptr, *p = nullptr, *t = nullptr, *y = nullptr, *x = nullptr, *ps = nullptr;
     int nblk_st = 0;
 
-    size_t csize() const { return prec == BRI_F64 ? sizeof(double2) : sizeof(float2); }
 
     void carve(Arena &ar) {
         nblk_st = stencil_blocks(g);
@@ -471,7 +473,7 @@ struct MsSolve {
         st = (ColState *)ar.take(sizeof(ColState) * ncol);
         partial = (double *)ar.take(sizeof(double) * 2 * (size_t)nb * ncol);
         alldone = (int *)ar.take(sizeof(int));
-        const size_t vb = (size_t)12 * g.V * csize() * ncol;
+        const size_t vb = (size_t)12 * g.V * sizeof(double2) * ncol;
         r = ar.take(vb);
         p = ar.take(vb);
         t = ar.take(vb);
@@ -480,11 +482,19 @@ struct MsSolve {
         else
             y = ar.take(vb);
         if (nshift > 1) ps = ar.take(vb * (nshift - 1));
+        if (prec_lo >= 0) {
+            const size_t vl = (size_t)12 * g.V * sizeof(float2) * ncol;
+            r_lo = ar.take(vl);
+            p_lo = ar.take(vl);
+            t_lo = ar.take(vl);
+            if (nshift > 1) ps_lo = ar.take(vl * (nshift - 1));
+        }
     }
 };
 
 struct RunStats {
     int iters = 0;
+    int lo_iters = 0;  // iterations of the low-precision phase (launched; columns done earlier return)
     int status = BRI_OK;
     std::vector<ColState> fin;
 };
@@ -570,10 +580,10 @@ static bool graphs_enabled() {
     return g_graphs_on;
 }
 
-// Runs one batched multi-shift solve; b is [ncol][12 V] complex double (or
-// complex float when b_is_f64 is false).  Returns a HIP / argument status;
-// convergence and NaN status land in rs.
-static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, int *hflag, RunStats &rs) {
+// Runs one batched multi-shift solve; b is [ncol][12 V] complex double.  Returns a HIP /
+// argument status; convergence and NaN status land in rs.
+static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunStats &rs) {
+    if (s.prec != BRI_F64) return BRI_EINVAL;  // FP64 vectors; the low-precision phase has its own
     const size_t n = (size_t)12 * s.g.V;
     std::vector<ColState> h(s.ncol);
     for (int c = 0; c < s.ncol; ++c) {
@@ -592,102 +602,155 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
     BRI_HIP_CHECK(hipMemcpyAsync(s.st, h.data(), sizeof(ColState) * s.ncol, hipMemcpyHostToDevice, strm));
     const dim3 vgrid(INIT_BLOCKS, s.ncol);
     const dim3 ugrid(update_blocks(n), s.ncol);
-    if (s.prec == BRI_F64) {
-        hipLaunchKernelGGL((ms_init_kernel<double2, double2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
-                           (double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x, (double2 *)s.ps, s.ncol,
-                           s.nshift, s.c0, s.partial);
-    } else if (b_is_f64) {
-        hipLaunchKernelGGL((ms_init_kernel<double2, float2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
-                           (float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps, s.ncol,
-                           s.nshift, s.c0, s.partial);
-    } else {
-        hipLaunchKernelGGL((ms_init_kernel<float2, float2>), vgrid, dim3(256), 0, strm, n, (const float2 *)b,
-                           (float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps, s.ncol,
-                           s.nshift, s.c0, s.partial);
-    }
+    hipLaunchKernelGGL((ms_init_kernel<double2, double2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
+                       (double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x, (double2 *)s.ps, s.ncol,
+                       s.nshift, s.c0, s.partial);
     hipLaunchKernelGGL(ms_scalar_init_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, INIT_BLOCKS,
                        s.tol);
     BRI_HIP_CHECK(hipGetLastError());
 
-    const StencilConfig cfg = default_config(s.g, s.prec, s.ncol, s.kind);
-    StencilArgs a1{};
-    a1.g = s.g;
-    a1.W = s.W;
-    a1.ncol = s.ncol;
-    a1.in = s.p;
-    a1.out = s.t;
-    a1.kind = s.kind;
-    a1.diag = kernel_diag(s.kind) + s.m0;
-    a1.partial = s.partial;
-    a1.st = s.st;
-    StencilArgs a2 = a1;
-    a2.in = s.t;
-    a2.out = nullptr;
-    a2.p = s.p;
-    a2.r = s.r;
+    // phase 0 runs at s.prec on (r, p, t, ps); phase 1 (FP64 solves with a low-precision phase)
+    // on the FP32 vectors (r_lo, p_lo, t_lo, ps_lo) with the links Wlo, accumulating into the
+    // FP64 y / x
+    struct Phase {
+        int prec;
+        StencilConfig cfg;
+        StencilArgs a1, a2;
+        void *r, *p, *ps;
+    };
+    auto make_phase = [&](int prec, const void *W, void *r, void *p, void *t, void *ps) {
+        Phase ph;
+        ph.prec = prec;
+        ph.cfg = default_config(s.g, prec, s.ncol, s.kind);
+        ph.a1 = StencilArgs{};
+        ph.a1.g = s.g;
+        ph.a1.W = W;
+        ph.a1.ncol = s.ncol;
+        ph.a1.in = p;
+        ph.a1.out = t;
+        ph.a1.kind = s.kind;
+        ph.a1.diag = kernel_diag(s.kind) + s.m0;
+        ph.a1.partial = s.partial;
+        ph.a1.st = s.st;
+        ph.a2 = ph.a1;
+        ph.a2.in = t;
+        ph.a2.out = nullptr;
+        ph.a2.p = p;
+        ph.a2.r = r;
+        ph.r = r;
+        ph.p = p;
+        ph.ps = ps;
+        return ph;
+    };
+    const bool has_lo = s.prec == BRI_F64 && s.prec_lo >= 0;
+    Phase phases[2] = {make_phase(s.prec, s.W, s.r, s.p, s.t, s.ps),
+                       has_lo ? make_phase(s.prec_lo, s.Wlo, s.r_lo, s.p_lo, s.t_lo, s.ps_lo) : Phase{}};
+    const double sw2 = has_lo ? s.lo_switch * s.lo_switch : 0.0;
 
     // one CG iteration for every column: t = X p, alpha, r update, beta, vector updates, done flags
-    auto iteration = [&](hipStream_t q) -> int {
-        const int e1 = stencil_launch(a1, s.prec, false, EPI_NORMS, cfg, q);
+    auto iteration = [&](const Phase &ph, bool lo, hipStream_t q) -> int {
+        const int e1 = stencil_launch(ph.a1, ph.prec, false, EPI_NORMS, ph.cfg, q);
         hipLaunchKernelGGL(ms_alpha_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
-        const int e2 = stencil_launch(a2, s.prec, true, EPI_CG_R, cfg, q);
+        const int e2 = stencil_launch(ph.a2, ph.prec, true, EPI_CG_R, ph.cfg, q);
         hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
-        if (s.prec == BRI_F64)
-            hipLaunchKernelGGL(ms_update_kernel<double2>, ugrid, dim3(256), 0, q, s.st, n, s.ncol,
-                               (const double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x,
-                               (double2 *)s.ps);
+        if (!lo)
+            hipLaunchKernelGGL((ms_update_kernel<double2, double2>), ugrid, dim3(256), 0, q, s.st, n, s.ncol,
+                               (const double2 *)ph.r, (double2 *)ph.p, (double2 *)s.y, (double2 *)s.x,
+                               (double2 *)ph.ps);
         else
-            hipLaunchKernelGGL(ms_update_kernel<float2>, ugrid, dim3(256), 0, q, s.st, n, s.ncol,
-                               (const float2 *)s.r, (float2 *)s.p, (float2 *)s.y, (float2 *)s.x, (float2 *)s.ps);
-        hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(256), 0, q, s.st, s.ncol, s.alldone);
+            hipLaunchKernelGGL((ms_update_kernel<float2, double2>), ugrid, dim3(256), 0, q, s.st, n, s.ncol,
+                               (const float2 *)ph.r, (float2 *)ph.p, (double2 *)s.y, (double2 *)s.x,
+                               (float2 *)ph.ps);
+        hipLaunchKernelGGL(ms_finish_kernel, dim3(1), dim3(256), 0, q, s.st, s.ncol, s.alldone, lo ? 0.0 : sw2);
         if (e1 != BRI_OK || e2 != BRI_OK) return e1 != BRI_OK ? e1 : e2;
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     };
+    // rounds phase 0's r, p, p^sigma into phase 1's FP32 vectors
+    auto narrow = [&]() -> int {
+        const size_t cnt = n * s.ncol;
+        hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt, (const double2 *)s.r, (float2 *)s.r_lo);
+        hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt, (const double2 *)s.p, (float2 *)s.p_lo);
+        if (s.nshift > 1)
+            hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt * (s.nshift - 1),
+                               (const double2 *)s.ps, (float2 *)s.ps_lo);
+        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+    };
     const bool use_graph = graphs_enabled();
-    std::vector<uint64_t> key;
+    std::vector<uint64_t> key0;
     if (use_graph) {
         int dev = 0;
         BRI_HIP_CHECK(hipGetDevice(&dev));
         // everything the captured launches bake in: geometry (with the clover switch), precision,
         // kernel, mass, every buffer address and the launch configuration
-        uint64_t m0bits, cswbits;
+        uint64_t m0bits, cswbits, swbits;
         std::memcpy(&m0bits, &s.m0, sizeof(m0bits));
         std::memcpy(&cswbits, &s.g.csw, sizeof(cswbits));
-        key = {(uint64_t)dev, (uint64_t)s.g.L[0], (uint64_t)s.g.L[1], (uint64_t)s.g.L[2], (uint64_t)s.g.L[3],
-               (uint64_t)s.g.tbc, cswbits, (uint64_t)s.prec, (uint64_t)s.kind, (uint64_t)s.ncol, m0bits,
-               (uint64_t)(uintptr_t)s.W,
-               (uint64_t)(uintptr_t)s.st, (uint64_t)(uintptr_t)s.partial, (uint64_t)(uintptr_t)s.alldone,
-               (uint64_t)(uintptr_t)s.r, (uint64_t)(uintptr_t)s.p, (uint64_t)(uintptr_t)s.t,
-               (uint64_t)(uintptr_t)s.y, (uint64_t)(uintptr_t)s.x, (uint64_t)(uintptr_t)s.ps,
-               (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1], (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3],
-               (uint64_t)cfg.colz, (uint64_t)cfg.nsplit, (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap,
-               (uint64_t)cfg.variant};
+        std::memcpy(&swbits, &sw2, sizeof(swbits));
+        key0 = {(uint64_t)dev, (uint64_t)s.g.L[0], (uint64_t)s.g.L[1], (uint64_t)s.g.L[2], (uint64_t)s.g.L[3],
+                (uint64_t)s.g.tbc, cswbits, (uint64_t)s.prec, (uint64_t)s.kind, (uint64_t)s.ncol, m0bits,
+                (uint64_t)(uintptr_t)s.W, (uint64_t)(uintptr_t)s.st, (uint64_t)(uintptr_t)s.partial,
+                (uint64_t)(uintptr_t)s.alldone, (uint64_t)(uintptr_t)s.r, (uint64_t)(uintptr_t)s.p,
+                (uint64_t)(uintptr_t)s.t, (uint64_t)(uintptr_t)s.y, (uint64_t)(uintptr_t)s.x,
+                (uint64_t)(uintptr_t)s.ps, (uint64_t)(int64_t)s.prec_lo, (uint64_t)(uintptr_t)s.Wlo,
+                (uint64_t)(uintptr_t)s.r_lo, (uint64_t)(uintptr_t)s.p_lo, (uint64_t)(uintptr_t)s.t_lo,
+                (uint64_t)(uintptr_t)s.ps_lo, swbits};
     }
+    auto key_of = [&](int phase, int nblock) {
+        std::vector<uint64_t> k = key0;
+        const StencilConfig &cfg = phases[phase].cfg;
+        for (uint64_t v : {(uint64_t)phase, (uint64_t)nblock, (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1],
+                           (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3], (uint64_t)cfg.colz, (uint64_t)cfg.nsplit,
+                           (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap, (uint64_t)cfg.variant})
+            k.push_back(v);
+        return k;
+    };
 
-    int it = 0;
+    // a solve whose tolerance is already within the low precision's reach starts in phase 1
+    int phase = 0;
+    if (has_lo && s.lo_switch >= 1.0) {
+        const int e = narrow();
+        if (e != BRI_OK) return e;
+        phase = 1;
+    }
+    int it = 0, it_switch = 0;
+    rs.lo_iters = 0;
     for (;;) {
-        if (use_graph && it + CHECK_EVERY <= s.max_iter) {
+        // shorter polling blocks while the switch to the low-precision phase is pending
+        const int blk = (phase == 0 && has_lo) ? CHECK_EVERY / 2 : CHECK_EVERY;
+        const Phase &ph = phases[phase];
+        const bool lo = phase == 1;
+        if (use_graph && it + blk <= s.max_iter) {
             const int rc = graph_launch(
-                key,
+                key_of(phase, blk),
                 [&](hipStream_t q) -> int {
-                    for (int k = 0; k < CHECK_EVERY; ++k) {
-                        const int e = iteration(q);
+                    for (int k = 0; k < blk; ++k) {
+                        const int e = iteration(ph, lo, q);
                         if (e != BRI_OK) return e;
                     }
                     return BRI_OK;
                 },
                 strm);
             if (rc != BRI_OK) return rc;
-            it += CHECK_EVERY;
+            it += blk;
         } else {
-            for (int k = 0; k < CHECK_EVERY && it < s.max_iter; ++k, ++it) {
-                const int e = iteration(strm);
+            for (int k = 0; k < blk && it < s.max_iter; ++k, ++it) {
+                const int e = iteration(ph, lo, strm);
                 if (e != BRI_OK) return e;
             }
         }
         BRI_HIP_CHECK(hipMemcpyAsync(hflag, s.alldone, sizeof(int), hipMemcpyDeviceToHost, strm));
         BRI_HIP_CHECK(hipStreamSynchronize(strm));
-        if (*hflag || it >= s.max_iter) break;
+        if (*hflag == 1 || it >= s.max_iter) break;
+        if (*hflag == 2 && phase == 0 && has_lo) {
+            // iterations done so far (the last of a polling block may find a column done)
+            std::vector<ColState> cur(s.ncol);
+            BRI_HIP_CHECK(hipMemcpyAsync(cur.data(), s.st, sizeof(ColState) * s.ncol, hipMemcpyDeviceToHost, strm));
+            BRI_HIP_CHECK(hipStreamSynchronize(strm));
+            for (const ColState &c : cur) it_switch = c.iter > it_switch ? c.iter : it_switch;
+            const int e = narrow();
+            if (e != BRI_OK) return e;
+            phase = 1;
+        }
     }
     rs.fin.resize(s.ncol);
     BRI_HIP_CHECK(hipMemcpyAsync(rs.fin.data(), s.st, sizeof(ColState) * s.ncol, hipMemcpyDeviceToHost, strm));
@@ -696,6 +759,7 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
     rs.status = BRI_OK;
     for (const ColState &c : rs.fin) {
         if (c.iter > rs.iters) rs.iters = c.iter;
+        if (phase == 1 && c.iter - it_switch > rs.lo_iters) rs.lo_iters = c.iter - it_switch;
         if (c.status == BRI_ENAN)
             rs.status = BRI_ENAN;
         else if (c.done == 0 && rs.status == BRI_OK)
@@ -706,165 +770,53 @@ static int ms_run(MsSolve &s, const void *b, bool b_is_f64, hipStream_t strm, in
 
 // ---------------------------------------------------------------- overlap
 
-constexpr int REFINE_CHUNK = 32;  // (shift, source) columns per refinement batch
-
-struct OvPlan {
-    int n = 0, nrhs = 0, chunk = 0;
-    bool mixed = false;
-    double c0 = 0.0, om[MAXS], sg[MAXS], tolf[MAXS];
-    MsSolve main;                 // FP64: y accumulated; mixed: every x^sigma kept
-    MsSolve corr;                 // mixed: batched single-shift corrections
-    double2 *x64 = nullptr;       // mixed: [n][nrhs][12V] FP64 shift solutions
-    double2 *res64 = nullptr;     // mixed: residual columns of one chunk
-    double2 *t64 = nullptr;       // mixed: X x for one chunk
-    double2 *y64 = nullptr;       // mixed: combined y [nrhs][12V]
-    double *sig_dev = nullptr;    // mixed: shift per residual column
-    double *omega_dev = nullptr;  // mixed: omega [n]
-    double *partial = nullptr;    // mixed: residual norms [chunk][nblk][2]
-    size_t bytes = 0;
-};
-
-static void plan_overlap(OvPlan &pl, const Geom &g, const ov_params *prm, int nrhs, const void *W64, const void *Wlo,
-                         void *work) {
-    pl.n = prm->kl_n;
-    pl.nrhs = nrhs;
-    pl.mixed = prm->inner != BRI_F64;
-    shift_coeffs(prm, &pl.c0, pl.om, pl.sg, pl.tolf);
-    Arena ar(work);
-    MsSolve &m = pl.main;
+// The multi-shift solve behind an overlap apply or the gradient: FP64, or FP64 with a low-
+// precision phase for inner = BRI_F32 / BRI_F32_BF16W, entered once the base residual has
+// fallen to tol / u_lo (u_lo the inner precision's unit roundoff; at once when that exceeds 1).
+static void plan_shifts(MsSolve &m, const Geom &g, const ov_params *prm, int ncol, const void *W64, const void *Wlo,
+                        bool store_x) {
+    const int n = prm->kl_n;
+    double om[MAXS], sg[MAXS], tf[MAXS];
+    shift_coeffs(prm, &m.c0, om, sg, tf);
     m.g = g;
-    m.prec = pl.mixed ? prm->inner : BRI_F64;
-    m.W = pl.mixed ? Wlo : W64;
+    m.prec = BRI_F64;
+    m.W = W64;
     m.m0 = -prm->rho;
     m.kind = prm->kernel;
-    m.ncol = nrhs;
-    m.nshift = pl.n;
-    m.store_x = pl.mixed;
-    m.c0 = pl.c0;
-    m.omega.assign(pl.om, pl.om + pl.n);
-    m.tolf.assign(pl.tolf, pl.tolf + pl.n);
-    m.sigma.resize((size_t)nrhs * pl.n);
-    for (int c = 0; c < nrhs; ++c)
-        for (int i = 0; i < pl.n; ++i) m.sigma[(size_t)c * pl.n + i] = pl.sg[i];
-    // the low-precision stage stops near its rounding floor; refinement delivers tol
-    m.tol = pl.mixed ? (prm->tol > 1e-5 ? prm->tol : 1e-5) : prm->tol;
+    m.ncol = ncol;
+    m.nshift = n;
+    m.store_x = store_x;
+    m.omega.assign(om, om + n);
+    m.tolf.assign(tf, tf + n);
+    m.sigma.resize((size_t)ncol * n);
+    for (int c = 0; c < ncol; ++c)
+        for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];
+    m.tol = prm->tol;
     m.max_iter = prm->max_iter;
-    m.carve(ar);
-    if (pl.mixed) {
-        // a chunk is a whole number of sources, so chunk column k reads source k % nrhs
-        const int per = REFINE_CHUNK / nrhs > 0 ? REFINE_CHUNK / nrhs : 1;
-        pl.chunk = nrhs * (per < pl.n ? per : pl.n);
-        const size_t vb = (size_t)12 * g.V * sizeof(double2);
-        pl.x64 = (double2 *)ar.take(vb * nrhs * pl.n);
-        pl.res64 = (double2 *)ar.take(vb * pl.chunk);
-        pl.t64 = (double2 *)ar.take(vb * pl.chunk);
-        pl.y64 = (double2 *)ar.take(vb * nrhs);
-        pl.sig_dev = (double *)ar.take(sizeof(double) * pl.chunk);
-        pl.omega_dev = (double *)ar.take(sizeof(double) * pl.n);
-        pl.partial = (double *)ar.take(sizeof(double) * 2 * (size_t)stencil_blocks(g) * pl.chunk);
-        MsSolve &e = pl.corr;
-        e.g = g;
-        e.prec = prm->inner;
-        e.W = Wlo;
-        e.m0 = -prm->rho;
-        e.kind = prm->kernel;
-        e.ncol = pl.chunk;
-        e.nshift = 1;
-        e.store_x = true;
-        e.c0 = 0.0;
-        e.omega.assign(1, 1.0);
-        e.sigma.assign(pl.chunk, 0.0);
-        e.tol = 1e-5;  // the corrections only need a few digits
-        e.max_iter = prm->max_iter;
-        e.carve(ar);
+    if (prm->inner != BRI_F64) {
+        m.prec_lo = prm->inner;
+        m.Wlo = Wlo;
+        const double sw = prm->tol / unit_roundoff(prm->inner);
+        m.lo_switch = sw < 1.0 ? sw : 1.0;
     }
-    pl.bytes = ar.used;
 }
 
-// Mixed precision: refine every (shift, source) column of x64 until its FP64
-// residual is below tol.  shift_res receives the worst residual per shift of
-// the last check.
-static int refine(OvPlan &pl, const Geom &g, const ov_params *prm, const void *W64, const void *in, hipStream_t s,
-                  int *hflag, int &passes, std::vector<double> &shift_res) {
-    const int n = pl.n, nrhs = pl.nrhs, total = n * nrhs, chunk = pl.chunk;
-    const size_t nel = (size_t)12 * g.V;
-    const int nblk = stencil_blocks(g);
-    std::vector<double> part, hsig(chunk), b2(nrhs, 0.0);
-    // |b|^2 per source from the main solve's states
-    {
-        std::vector<ColState> st(nrhs);
-        BRI_HIP_CHECK(hipMemcpyAsync(st.data(), pl.main.st, sizeof(ColState) * nrhs, hipMemcpyDeviceToHost, s));
-        BRI_HIP_CHECK(hipStreamSynchronize(s));
-        for (int c = 0; c < nrhs; ++c) b2[c] = st[c].bnorm2;
-    }
-    passes = 0;
-    for (int pass = 0;; ++pass) {
-        bool all_ok = true;
-        for (int i = 0; i < n; ++i) shift_res[i] = 0.0;
-        for (int c0i = 0; c0i < total; c0i += chunk) {
-            const int nc = total - c0i < chunk ? total - c0i : chunk;
-            for (int k = 0; k < nc; ++k) hsig[k] = pl.sg[(c0i + k) / nrhs];
-            BRI_HIP_CHECK(hipMemcpyAsync(pl.sig_dev, hsig.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
-            double2 *xc = pl.x64 + (size_t)c0i * nel;
-            // t = X x ; res = b - (X^dag t + sigma x), all FP64
-            StencilArgs a{};
-            a.g = g;
-            a.W = W64;
-            a.ncol = nc;
-            a.in = xc;
-            a.out = pl.t64;
-            a.kind = prm->kernel;
-            a.diag = kernel_diag(prm->kernel) - prm->rho;
-            const StencilConfig cfg = default_config(g, BRI_F64, nc, prm->kernel);
-            int rc = stencil_launch(a, BRI_F64, false, EPI_PLAIN, cfg, s);
-            if (rc != BRI_OK) return rc;
-            StencilArgs a2 = a;
-            a2.in = pl.t64;
-            a2.out = pl.res64;
-            a2.b = in;
-            a2.b_mod = nrhs;
-            a2.xs = xc;
-            a2.sig = pl.sig_dev;
-            a2.partial = pl.partial;
-            rc = stencil_launch(a2, BRI_F64, true, EPI_RESID, cfg, s);
-            if (rc != BRI_OK) return rc;
-            part.resize((size_t)2 * nblk * nc);
-            BRI_HIP_CHECK(
-                hipMemcpyAsync(part.data(), pl.partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
-            BRI_HIP_CHECK(hipStreamSynchronize(s));
-            bool chunk_ok = true;
-            for (int k = 0; k < nc; ++k) {
-                double r2 = 0.0;
-                for (int bk = 0; bk < nblk; ++bk) r2 += part[2 * ((size_t)k * nblk + bk)];
-                const int col = c0i + k;
-                const double bb = b2[col % nrhs];
-                const double rel = bb > 0 ? sqrt(r2 / bb) : 0.0;
-                if (!isfinite(rel)) return BRI_ENAN;
-                const int sh = col / nrhs;
-                if (rel > shift_res[sh]) shift_res[sh] = rel;
-                if (rel > prm->tol * pl.tolf[sh]) chunk_ok = false;
-            }
-            if (chunk_ok || pass >= prm->max_refine) {
-                all_ok = all_ok && chunk_ok;
-                continue;
-            }
-            all_ok = false;
-            // corrections (A + sigma_k) e_k = res_k in low precision; x64 += e
-            MsSolve &e = pl.corr;
-            e.ncol = nc;
-            for (int k = 0; k < nc; ++k) e.sigma[k] = hsig[k];
-            RunStats rs;
-            rc = ms_run(e, pl.res64, true, s, hflag, rs);
-            e.ncol = chunk;
-            if (rc != BRI_OK) return rc;
-            if (rs.status == BRI_ENAN) return BRI_ENAN;
-            hipLaunchKernelGGL(widen_kernel<float2>, dim3(4096), dim3(256), 0, s, nel * nc, (const float2 *)e.x, xc,
-                               1);
-            BRI_HIP_CHECK(hipGetLastError());
+// iterations and residual per shift, the worst column of the solve
+static void fill_stats(const RunStats &rs, int n, ov_stats *st) {
+    st->iters = rs.iters;
+    st->refine = rs.lo_iters;
+    for (int i = 0; i < n; ++i) {
+        int it = 0;
+        double res = 0.0;
+        for (const ColState &c : rs.fin) {
+            const int ci = c.conv_iter[i] ? c.conv_iter[i] : c.iter;
+            const double cr =
+                c.conv_iter[i] ? c.conv_res[i] : fabs(c.zeta[i]) * sqrt(c.rr / (c.bnorm2 > 0 ? c.bnorm2 : 1));
+            if (ci > it) it = ci;
+            if (cr > res) res = cr;
         }
-        if (all_ok) return BRI_OK;
-        if (pass >= prm->max_refine) return BRI_ENOCONV;
-        ++passes;
+        st->shift_iters[i] = it;
+        st->rel_resid[i] = res;
     }
 }
 
@@ -879,60 +831,38 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     const int n = prm->kl_n;
     if (!params_ok(prm)) return BRI_EINVAL;
     if (g.V % 64 || nrhs < 1 || nrhs > 4096) return BRI_EINVAL;
-    OvPlan pl;
-    plan_overlap(pl, g, prm, nrhs, W64, Wlo, nullptr);
-    if (!work) {
-        *work_bytes = pl.bytes;
-        return BRI_OK;
-    }
-    if (*work_bytes < pl.bytes || !W64 || !in || !out || (pl.mixed && !Wlo)) return BRI_EINVAL;
+    const bool mixed = prm->inner != BRI_F64;
+    MsSolve m;
+    plan_shifts(m, g, prm, nrhs, W64, Wlo, false);
     {
+        Arena ar(nullptr);
+        m.carve(ar);
+        if (!work) {
+            *work_bytes = ar.used;
+            return BRI_OK;
+        }
+        if (*work_bytes < ar.used || !W64 || !in || !out || (mixed && !Wlo)) return BRI_EINVAL;
         const size_t vb = (size_t)12 * g.V * nrhs * sizeof(double2);
-        if (ranges_overlap(in, vb, out, vb) || ranges_overlap(in, vb, work, pl.bytes) ||
-            ranges_overlap(out, vb, work, pl.bytes))
+        if (ranges_overlap(in, vb, out, vb) || ranges_overlap(in, vb, work, ar.used) ||
+            ranges_overlap(out, vb, work, ar.used))
             return BRI_EINVAL;
     }
-    plan_overlap(pl, g, prm, nrhs, W64, Wlo, work);
+    Arena ar(work);
+    m.carve(ar);
     hipStream_t s = (hipStream_t)stream;
-    const size_t nel = (size_t)12 * g.V;
 
     int *hflag = nullptr;
     if (pinned_flag(&hflag) != BRI_OK) return BRI_EHIP;
-    int result = BRI_OK;
     RunStats rs;
-    int passes = 0;
-    std::vector<double> shift_res((size_t)n, 0.0);
-    const void *yfinal = nullptr;
-
-    rc = ms_run(pl.main, in, true, s, hflag, rs);
-    result = rc != BRI_OK ? rc : rs.status;
-    if (result == BRI_OK && !pl.mixed) {
-        yfinal = pl.main.y;
-    } else if ((result == BRI_OK || result == BRI_ENOCONV) && pl.mixed) {
-        hipLaunchKernelGGL(widen_kernel<float2>, dim3(4096), dim3(256), 0, s, nel * nrhs * n,
-                           (const float2 *)pl.main.x, pl.x64, 0);
-        if (hipMemcpyAsync(pl.omega_dev, pl.om, sizeof(double) * n, hipMemcpyHostToDevice, s) != hipSuccess)
-            result = BRI_EHIP;
-        else {
-            rc = refine(pl, g, prm, W64, in, s, hflag, passes, shift_res);
-            if (rc != BRI_OK) result = rc;
-        }
-        if (result == BRI_OK || result == BRI_ENOCONV) {
-            hipLaunchKernelGGL(combine_kernel, dim3(INIT_BLOCKS, nrhs), dim3(256), 0, s, nel, nrhs, n, pl.c0,
-                               (const double *)pl.omega_dev, (const double2 *)in, (const double2 *)pl.x64, pl.y64);
-            yfinal = pl.y64;
-        }
-    } else if (result == BRI_ENOCONV) {
-        yfinal = pl.main.y;  // best iterate
-    }
-
-    if (yfinal) {
+    rc = ms_run(m, in, s, hflag, rs);
+    int result = rc != BRI_OK ? rc : rs.status;
+    if (result == BRI_OK || result == BRI_ENOCONV) {  // (the best iterate on ENOCONV)
         // out = rho (b + X y)  or  gamma5 X y, in FP64
         StencilArgs a3{};
         a3.g = g;
         a3.W = W64;
         a3.ncol = nrhs;
-        a3.in = yfinal;
+        a3.in = m.y;
         a3.out = out;
         a3.kind = prm->kernel;
         a3.diag = kernel_diag(prm->kernel) - prm->rho;
@@ -945,18 +875,7 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     if (hipStreamSynchronize(s) != hipSuccess) result = BRI_EHIP;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->iters = rs.iters;
-        stats->refine = passes;
-        if (!rs.fin.empty()) {
-            const ColState &fin = rs.fin.back();
-            for (int i = 0; i < n; ++i) {
-                stats->shift_iters[i] = fin.conv_iter[i] ? fin.conv_iter[i] : fin.iter;
-                stats->rel_resid[i] =
-                    pl.mixed ? shift_res[i]
-                             : (fin.conv_iter[i] ? fin.conv_res[i]
-                                                 : fabs(fin.zeta[i]) * sqrt(fin.rr / (fin.bnorm2 > 0 ? fin.bnorm2 : 1)));
-            }
-        }
+        if (!rs.fin.empty()) fill_stats(rs, n, stats);
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return result;
@@ -964,84 +883,33 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
 
 // Multi-shift solve of (A + sigma_i) x_i = b over the Kenney-Laub shifts with every x_i kept
 // in FP64, [shift][ncol][12 V] inside the workspace (the gradient needs the individual shift
-// solutions).  inner = BRI_F64 runs the FP64 multi-shift; a low-precision inner runs it on
-// Wlo and refines every (shift, column) in FP64 as the overlap apply does.  With
-// work == NULL only *need is set.  st (may be NULL) receives iterations and the final
-// residual of each shift (the worst column).
+// solutions).  inner = BRI_F64 runs it in FP64; a low-precision inner relaxes the precision
+// of the late iterations as the overlap apply does.  With work == NULL only *need is set.
+// st (may be NULL) receives iterations and the final residual of each shift (the worst column).
 int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_params *prm, const void *b, int ncol,
                     void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st) {
     const int n = prm->kl_n;
     if (n < 1 || n > MAXS || ncol < 1) return BRI_EINVAL;
     const bool mixed = prm->inner != BRI_F64;
-    OvPlan pl;
     MsSolve m;
-    if (mixed) {
-        plan_overlap(pl, g, prm, ncol, W64, Wlo, nullptr);
-        if (!work) {
-            if (need) *need = pl.bytes;
-            return BRI_OK;
-        }
-        if (work_bytes < pl.bytes || !W64 || !Wlo || !b || !x_out) return BRI_EINVAL;
-        plan_overlap(pl, g, prm, ncol, W64, Wlo, work);
-    } else {
-        m.g = g;
-        m.prec = BRI_F64;
-        m.W = W64;
-        m.m0 = -prm->rho;
-        m.kind = prm->kernel;
-        m.ncol = ncol;
-        m.nshift = n;
-        m.store_x = true;
-        double om[MAXS], sg[MAXS], tf[MAXS];
-        shift_coeffs(prm, &m.c0, om, sg, tf);
-        m.omega.assign(om, om + n);
-        m.tolf.assign(tf, tf + n);
-        m.sigma.resize((size_t)ncol * n);
-        for (int c = 0; c < ncol; ++c)
-            for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];
-        m.tol = prm->tol;
-        m.max_iter = prm->max_iter;
-        Arena ar(work);
-        m.carve(ar);
-        if (!work) {
-            if (need) *need = ar.used;
-            return BRI_OK;
-        }
-        if (work_bytes < ar.used || !W64 || !b || !x_out) return BRI_EINVAL;
+    plan_shifts(m, g, prm, ncol, W64, Wlo, true);
+    Arena ar(work);
+    m.carve(ar);
+    if (!work) {
+        if (need) *need = ar.used;
+        return BRI_OK;
     }
+    if (work_bytes < ar.used || !W64 || !b || !x_out || (mixed && !Wlo)) return BRI_EINVAL;
     int *hflag = nullptr;
     if (pinned_flag(&hflag) != BRI_OK) return BRI_EHIP;
     RunStats rs;
-    int passes = 0;
-    std::vector<double> shift_res((size_t)n, 0.0);
-    int rc = ms_run(mixed ? pl.main : m, b, true, s, hflag, rs);
-    int result = rc != BRI_OK ? rc : rs.status;
-    if (mixed && (result == BRI_OK || result == BRI_ENOCONV)) {
-        const size_t nel = (size_t)12 * g.V;
-        hipLaunchKernelGGL(widen_kernel<float2>, dim3(4096), dim3(256), 0, s, nel * ncol * n,
-                           (const float2 *)pl.main.x, pl.x64, 0);
-        rc = refine(pl, g, prm, W64, b, s, hflag, passes, shift_res);
-        result = rc;
-    }
+    const int rc = ms_run(m, b, s, hflag, rs);
+    const int result = rc != BRI_OK ? rc : rs.status;
     if (result != BRI_OK && result != BRI_ENOCONV) return result;
-    *x_out = mixed ? (void *)pl.x64 : m.x;
+    *x_out = m.x;
     if (st) {
         std::memset(st, 0, sizeof(*st));
-        st->iters = rs.iters;
-        st->refine = passes;
-        for (int i = 0; i < n; ++i) {
-            int it = 0;
-            double res = 0.0;
-            for (const ColState &c : rs.fin) {
-                const int ci = c.conv_iter[i] ? c.conv_iter[i] : c.iter;
-                const double cr = c.conv_iter[i] ? c.conv_res[i]
-                                                 : fabs(c.zeta[i]) * sqrt(c.rr / (c.bnorm2 > 0 ? c.bnorm2 : 1));
-                if (ci > it) it = ci;
-                if (cr > res) res = cr;
-            }
-            st->shift_iters[i] = it;
-            st->rel_resid[i] = mixed ? shift_res[i] : res;
-        }
+        fill_stats(rs, n, st);
     }
     return result;
 }

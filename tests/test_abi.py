@@ -123,7 +123,7 @@ def test_gradient_workspace_and_invalid_arguments():
                 bri._OvParams(8, 2.0, 1e-10, 100, 0, 0), bri._OvParams(8, 1.0, 1e-10, 100, 1, 101)):
         assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(bad), None, None, None, None, None,
                                  None, ctypes.byref(nb), None, None) == bri.EINVAL
-    # a low-precision inner solve keeps FP64 shift solutions and refinement buffers: larger
+    # a low-precision inner solve adds the FP32 vectors of its late iterations: larger
     lo = bri._OvParams(8, 1.0, 1e-10, 100, 1, 10)
     nb_lo = ctypes.c_size_t(0)
     assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(lo), None, None, None, None, None, None,

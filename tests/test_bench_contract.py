@@ -26,10 +26,24 @@ def test_algorithmic_bytes_per_site():
 def test_counter_traffic_is_tied_to_the_stencil_sources():
     # the committed counter summary is used only while the stencil sources hash to its digest
     traffic = bench.measured_traffic()
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        assert traffic is None
+        return
     with open(bench.TRAFFIC_FILE) as f:
         txt = f.read()
     sha = [ln.split("=", 1)[1].strip() for ln in txt.splitlines() if ln.startswith("kernel_src_sha")][0]
     if sha == bench.kernel_source_digest():
-        assert traffic is not None and traffic > bench.stencil_bytes_per_site(8, 8) * 16**4
+        V = 1
+        for v in bench.L_BENCH:
+            V *= v
+        assert traffic is not None and traffic > bench.stencil_bytes_per_site(8, 8) * V
     else:
         assert traffic is None
+
+
+def test_gate_reads_the_stored_oracle_outputs():
+    # every stored 32^3x64 oracle output is a point source of the benchmark's batch
+    for c in bench.golden_cases(bench.L_BENCH):
+        assert str(c["source_kind"]) == "point" and 0 <= int(c["source_arg"]) < bench.NSRC
+        assert float(c["tol"]) <= 1e-13 and int(c["kl_n"]) == bench.KL_N
+        assert tuple(int(v) for v in c["L"]) == bench.L_BENCH

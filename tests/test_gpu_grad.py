@@ -191,7 +191,8 @@ def test_overlap_autograd():
 
 @pytest.mark.parametrize("inner", [bri.F32, bri.F32_BF16W])
 def test_overlap_grad_low_precision_inner(inner):
-    """Low-precision shift solves refined in FP64 give the FP64 gradient to the solver tolerance."""
+    """Shift solves whose late iterations run in low precision give the FP64 gradient to the
+    solver tolerance."""
     need_gpu()
     U, _ = field(L4, "cfg1", 1)
     rng = np.random.default_rng(17)
@@ -204,7 +205,7 @@ def test_overlap_grad_low_precision_inner(inner):
     F, _, g, st = op.grad(Ud, chi, psi)
     assert float((F - F64_).abs().max()) <= 1e-9 * float(F64_.abs().max())
     assert float(torch.linalg.vector_norm(g - g64) / torch.linalg.vector_norm(g64)) < 1e-10
-    assert st.refine >= 1 and max(st.rel_resid) <= 1e-12
+    assert st.refine >= (1 if inner == bri.F32 else 0) and max(st.rel_resid) <= 1e-12
 
 
 def test_grad_error_paths():

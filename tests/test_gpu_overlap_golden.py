@@ -116,7 +116,7 @@ def test_mixed_single_source(name, inner):
     op = bri.OverlapOp(L, W, kl_n=int(g["kl_n"]), rho=float(g["rho"]), tol=1e-12, max_iter=5000, Wlo=Wlo,
                        inner=prec)
     out, st = op.apply(bri.spinor_to_device(_source(L, g)))
-    _check(out[0], g, f"{name} mixed {inner} 1src ({st.iters} iterations, {st.refine} refinements)")
+    _check(out[0], g, f"{name} mixed {inner} 1src ({st.iters} iterations, {st.refine} in low precision)")
     del op, out, Wlo
     torch.cuda.empty_cache()
 

@@ -109,7 +109,7 @@ def test_wilson_overlap_4_4(n):
 
 
 def test_wilson_overlap_variants_non_cubic():
-    """Antiperiodic non-cubic lattice: FP32 inner solves with FP64 refinement, and the upper-diagonal
+    """Antiperiodic non-cubic lattice: FP32 late iterations of the inner solves, and the upper-diagonal
     rational, each against the oracle."""
     need_gpu()
     L = (4, 4, 4, 8)
