@@ -71,7 +71,9 @@ typedef enum {
     BRI_EINVAL = -1,  /* bad geometry, pointer, precision, size or workspace  */
     BRI_ENOCONV = -2, /* solver hit max_iter; out holds the last iterate      */
     BRI_ENAN = -3,    /* non-finite value met in a reduction                  */
-    BRI_EHIP = -4     /* a HIP runtime call failed                            */
+    BRI_EHIP = -4,    /* a HIP runtime call failed                            */
+    BRI_ESCRATCH = -5 /* ov_apply_noalloc: the problem's workspace exceeds the
+                         library's static scratch (ov_noalloc_max_bytes)       */
 } bri_status;
 
 /* Largest supported Kenney-Laub order n (number of shifts). */
@@ -208,6 +210,23 @@ int ov_sign_apply(const bri_geom *geom, const void *W64, const void *Wlo, const 
                   void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream);
 int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params, const void *in,
              void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream);
+
+/*
+ * ov_apply_noalloc -- ov_apply for callers that cannot allocate (no hipMalloc, hipFree, pinned
+ * host memory or HIP-graph instantiation on their path): the same computation and kernels, with
+ * the workspace taken from a static device array of ov_noalloc_max_bytes() = 256 MiB that the
+ * library holds on each GPU it runs on until the process ends (enough for a 16^4 FP64 apply of
+ * one right-hand side with 16 shifts).  The caller passes inputs and outputs as for ov_apply;
+ * stats may be NULL.  Returns BRI_ESCRATCH, before launching anything, when the workspace
+ * ov_apply would ask for exceeds that size.  The array's address is resolved on the first call
+ * on each device.  Every call on a GPU uses that GPU's one array and nothing in it needs to be
+ * cleared between calls (each call initialises what it reads); calls that overlap in time on
+ * one GPU (other streams or host threads) race on it and must be serialised by the caller.
+ * Synchronises `stream` (it polls the solver's convergence flag, as ov_apply does).
+ */
+int ov_apply_noalloc(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params, const void *in,
+                     void *out, int nrhs, ov_stats *stats, void *stream);
+size_t ov_noalloc_max_bytes(void);
 
 /*
  * Outer solve of the massive overlap equation (Sec. 4; BiCGstab outer solver of Sec. 7):

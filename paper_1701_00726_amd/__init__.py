@@ -31,9 +31,10 @@ LIB_PATH = os.path.join(_HERE, "libbrillouin.so")
 F64, F32, F32_BF16W = 0, 1, 2
 KL_DIAG, KL_UPPER = 0, 1
 KERNEL_BRILLOUIN, KERNEL_WILSON = 0, 1
-OK, EINVAL, ENOCONV, ENAN, EHIP = 0, -1, -2, -3, -4
+OK, EINVAL, ENOCONV, ENAN, EHIP, ESCRATCH = 0, -1, -2, -3, -4, -5
 MAX_SHIFTS = 32
-STATUS_NAMES = {OK: "BRI_OK", EINVAL: "BRI_EINVAL", ENOCONV: "BRI_ENOCONV", ENAN: "BRI_ENAN", EHIP: "BRI_EHIP"}
+STATUS_NAMES = {OK: "BRI_OK", EINVAL: "BRI_EINVAL", ENOCONV: "BRI_ENOCONV", ENAN: "BRI_ENAN", EHIP: "BRI_EHIP",
+                ESCRATCH: "BRI_ESCRATCH"}
 
 
 class BriError(RuntimeError):
@@ -185,6 +186,8 @@ def load():
                       ctypes.POINTER(_OvStats), P]
             lib.ov_sign_apply.argtypes = ovargs
             lib.ov_apply.argtypes = ovargs
+            lib.ov_apply_noalloc.argtypes = [G, P, P, ctypes.POINTER(_OvParams), P, P, I, ctypes.POINTER(_OvStats), P]
+            lib.ov_noalloc_max_bytes.argtypes = []
             lib.bri_kl_coeffs.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
             SC = ctypes.POINTER(StencilCfg)
             lib.bri_stencil_time.argtypes = [G, P, I, P, P, I, SC, I, ctypes.POINTER(D), P]
@@ -202,6 +205,7 @@ def load():
                                           ctypes.POINTER(_OvStats), P]
             for fn in EXPORTS:
                 getattr(lib, fn).restype = I
+            lib.ov_noalloc_max_bytes.restype = ctypes.c_size_t
             _lib = lib
     return _lib
 
@@ -225,6 +229,8 @@ EXPORTS = (
     "ov_solve",
     "bri_kl_upper_coeffs",
     "bri_set_solver_graphs",
+    "ov_apply_noalloc",
+    "ov_noalloc_max_bytes",
 )
 MAX_PAIRS = 2 * MAX_SHIFTS + 1
 

@@ -582,7 +582,7 @@ static bool graphs_enabled() {
 
 // Runs one batched multi-shift solve; b is [ncol][12 V] complex double.  Returns a HIP /
 // argument status; convergence and NaN status land in rs.
-static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunStats &rs) {
+static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunStats &rs, bool allow_graphs = true) {
     if (s.prec != BRI_F64) return BRI_EINVAL;  // FP64 vectors; the low-precision phase has its own
     const size_t n = (size_t)12 * s.g.V;
     std::vector<ColState> h(s.ncol);
@@ -675,7 +675,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                                (const double2 *)s.ps, (float2 *)s.ps_lo);
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     };
-    const bool use_graph = graphs_enabled();
+    const bool use_graph = allow_graphs && graphs_enabled();
     std::vector<uint64_t> key0;
     if (use_graph) {
         int dev = 0;
@@ -820,20 +820,56 @@ static void fill_stats(const RunStats &rs, int n, ov_stats *st) {
     }
 }
 
+// Static workspace of the entry point that allocates nothing (ov_apply_noalloc): one per GPU,
+// held until the process ends, resolved once per device with hipGetSymbolAddress (the array's
+// name is only a host-side stand-in).  Every call on a GPU shares it.
+constexpr size_t SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+// device address of the current device's scratch array (resolved on the first call per device)
+static int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BRI_EHIP;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return BRI_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BRI_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BRI_OK;
+}
+
+// noalloc: the workspace is the static scratch (work / work_bytes ignored), the polling word a
+// host variable, and the CG loop is launched without HIP graphs (instantiating one allocates)
 static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *prm, const void *in,
                    void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream,
-                   bool overlap) {
+                   bool overlap, bool noalloc = false) {
     const auto t0 = std::chrono::steady_clock::now();
     Geom g;
     int rc = geom_check(geom, &g);
     if (rc != BRI_OK) return rc;
-    if (!prm || !work_bytes) return BRI_EINVAL;
+    if (!prm || (!work_bytes && !noalloc)) return BRI_EINVAL;
     const int n = prm->kl_n;
     if (!params_ok(prm)) return BRI_EINVAL;
     if (g.V % 64 || nrhs < 1 || nrhs > 4096) return BRI_EINVAL;
     const bool mixed = prm->inner != BRI_F64;
     MsSolve m;
     plan_shifts(m, g, prm, nrhs, W64, Wlo, false);
+    size_t scratch_bytes = 0;
+    if (noalloc) {
+        Arena ar(nullptr);
+        m.carve(ar);
+        if (ar.used > SCRATCH_BYTES) return BRI_ESCRATCH;
+        rc = scratch_address(&work);
+        if (rc != BRI_OK) return rc;
+        scratch_bytes = SCRATCH_BYTES;
+        work_bytes = &scratch_bytes;
+    }
     {
         Arena ar(nullptr);
         m.carve(ar);
@@ -851,10 +887,13 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     m.carve(ar);
     hipStream_t s = (hipStream_t)stream;
 
-    int *hflag = nullptr;
-    if (pinned_flag(&hflag) != BRI_OK) return BRI_EHIP;
+    int *hflag = nullptr, host_flag = 0;
+    if (noalloc)
+        hflag = &host_flag;
+    else if (pinned_flag(&hflag) != BRI_OK)
+        return BRI_EHIP;
     RunStats rs;
-    rc = ms_run(m, in, s, hflag, rs);
+    rc = ms_run(m, in, s, hflag, rs, !noalloc);
     int result = rc != BRI_OK ? rc : rs.status;
     if (result == BRI_OK || result == BRI_ENOCONV) {  // (the best iterate on ENOCONV)
         // out = rho (b + X y)  or  gamma5 X y, in FP64
@@ -947,5 +986,12 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
              void *out, int nrhs, void *work, size_t *work_bytes, ov_stats *stats, void *stream) {
     return bri::ov_impl(geom, W64, Wlo, params, in, out, nrhs, work, work_bytes, stats, stream, true);
 }
+
+int ov_apply_noalloc(const bri_geom *geom, const void *W64, const void *Wlo, const ov_params *params, const void *in,
+                     void *out, int nrhs, ov_stats *stats, void *stream) {
+    return bri::ov_impl(geom, W64, Wlo, params, in, out, nrhs, nullptr, nullptr, stats, stream, true, true);
+}
+
+size_t ov_noalloc_max_bytes(void) { return bri::SCRATCH_BYTES; }
 
 }  // extern "C"

@@ -18,7 +18,7 @@ from tests.conftest import ROOT
 def _declared():
     txt = open(os.path.join(ROOT, "include", "brillouin.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*int\s+(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t)\s+(\w+)\s*\(", txt, flags=re.M)))
 
 
 def test_exports_every_declared_symbol():
