@@ -324,7 +324,8 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  *      consecutive t-slices (dividing L_t), reading both uses of every stored
  *      link inside one slice; col_z and nsplit are ignored;
  *   2  x-line: as 0 with tile_x = L_x (whole x-lines in every wave), the three
- *      x-displacements of each (dy, dz, dt) sharing one spinor load.
+ *      x-displacements of each (dy, dz, dt) sharing one spinor load; with
+ *      rpt = 2, 3 or 4 right-hand sides per thread as the multi-RHS kernel.
  */
 typedef struct {
     int tile_x, tile_y, tile_z, tile_t;

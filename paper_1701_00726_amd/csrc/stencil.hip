@@ -78,7 +78,7 @@ static int plan_tile_base(const Geom &g, const StencilConfig &cfg, int tile[4], 
 int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
     const int rc = plan_tile_base(g, cfg, tile, nb);
     if (rc != BRI_OK) return rc;
-    if (cfg.variant == VAR_XLINE && (tile[0] != g.L[0] || cfg.rpt != 0)) return BRI_EINVAL;
+    if (cfg.variant == VAR_XLINE && (tile[0] != g.L[0] || cfg.rpt == 1 || cfg.rpt > 4)) return BRI_EINVAL;
     if (cfg.variant < VAR_STANDARD || cfg.variant > VAR_XLINE) return BRI_EINVAL;
     return BRI_OK;
 }
@@ -120,6 +120,11 @@ static void default_traversal(const Geom &g, StencilConfig &c) {
     }
 }
 
+// a large lattice whose x-lines fill whole rows of a 64-lane wave (the x-line kernels' default)
+static bool xline_fits(const Geom &g) {
+    return g.V / 64 >= 8192 && (g.L[0] == 16 || g.L[0] == 32 || g.L[0] == 64) && g.L[1] % (64 / g.L[0]) == 0;
+}
+
 StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
     StencilConfig c;
     // the tuned table holds Brillouin launches; the Wilson stencil keeps the defaults
@@ -139,6 +144,19 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.rpt = (prec == BRI_F64 || ncol <= 8) ? 2 : 3;
         else
             c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
+        // low-precision batches on large lattices whose x-lines fit a wave: the x-line kernel with
+        // three right-hand sides per thread (12 RHS at 32^3x64: 19.9 / 18.7 ms for FP32 / bfloat16
+        // links against 24.7 / 22.7 ms; in FP64 it only ties, its registers limit it to one wave
+        // per SIMD)
+        if (kind == KERN_BRI && prec != BRI_F64 && ncol >= 3 && xline_fits(g)) {
+            c.variant = VAR_XLINE;
+            c.tile[0] = g.L[0];
+            c.tile[1] = 64 / g.L[0];
+            c.tile[2] = c.tile[3] = 1;
+            c.colz = g.L[2] % 4 == 0 ? 4 : 0;
+            c.rpt = 3;
+            c.xcd_remap = 1;
+        }
     } else {
         // four waves split each tile's directions: fills the 1024 SIMDs on small lattices, and on
         // large ones keeps fewer tiles (and their link lines) in flight per XCD than two waves do
@@ -148,8 +166,7 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
         // x-displacements).  At 32^3x64 it measured 4.15 / 2.08 / 1.49 ms (FP64 / FP32 /
         // bfloat16 links) against 5.52 / 3.37 / 2.64 ms for the column traversal above, with
         // lexicographic whole-line tiles and no XCD remap fastest; at 16^4 the two tie.
-        if (kind == KERN_BRI && g.V / 64 >= 8192 && (g.L[0] == 16 || g.L[0] == 32 || g.L[0] == 64) &&
-            g.L[1] % (64 / g.L[0]) == 0) {
+        if (kind == KERN_BRI && xline_fits(g)) {
             c.variant = VAR_XLINE;
             c.tile[0] = g.L[0];
             c.tile[1] = 64 / g.L[0];

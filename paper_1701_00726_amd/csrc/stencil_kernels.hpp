@@ -364,6 +364,140 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_xline_kernel(StencilArgs 
     }
 }
 
+// stencil_xline_mrhs_kernel: the x-line grouping with R right-hand sides per thread, as
+// stencil_mrhs_kernel: MRHS_SPLIT waves split a whole-x-line tile's 27 groups, each group's R
+// neighbour spinors are loaded once and shifted across lanes, and each link is loaded once for
+// the R right-hand sides.  The partial sums meet in LDS one column at a time.
+template <class LS, int R, bool DAG, int MODE>
+__global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_xline_mrhs_kernel(StencilArgs a) {
+    using RT = typename LS::R;
+    using C = typename Cx<RT>::T;
+    using S = typename LS::store_t;
+    constexpr int NSPLIT = MRHS_SPLIT;
+    constexpr int NCOMP = 12 / NSPLIT;
+    const unsigned V = (unsigned)a.g.V;
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col0 = blockIdx.y * R;
+    bool live[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        live[r] = (col0 + r < a.ncol) && !col_done<MODE>(a, col0 + r);
+        any |= live[r];
+    }
+    if (!any) return;
+
+    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
+    unsigned om[4], o0[4], op[4];
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const int tx = a.tile[0];  // = L_x
+    const int lx = lane % tx;
+    const int lane_m = lane - lx + (lx == 0 ? tx - 1 : lx - 1);
+    const int lane_p = lane - lx + (lx == tx - 1 ? 0 : lx + 1);
+    const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
+    const S *__restrict__ W = (const S *)a.W;
+
+    C acc[R][4][3];
+    const RT diag = (RT)a.diag;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                C v = cmake<C>((RT)0, (RT)0);
+                if (q == 0 && live[r]) {
+                    const C u = in[((size_t)r * 12 + s * 3 + b) * V + x];
+                    v = cmake<C>(diag * u.x, diag * u.y);
+                }
+                acc[r][s][b] = v;
+            }
+
+    for (int gi = q; gi < 27; gi += NSPLIT) {
+        const int dy = gi % 3 - 1, dz = (gi / 3) % 3 - 1, dt = gi / 9 - 1;
+        const unsigned yzt = sel3(dy, om[1], o0[1], op[1]) + sel3(dz, om[2], o0[2], op[2]) +
+                             sel3(dt, om[3], o0[3], op[3]);
+        C pc[R][4][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    pc[r][s][b] = live[r] ? in[((size_t)r * 12 + s * 3 + b) * V + o0[0] + yzt] : cmake<C>((RT)0, (RT)0);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (gi == 13 && dx == 0) continue;  // d = 0: the diagonal term
+            const int jd = (dx + 1) + 3 * gi;
+            const int src = dx < 0 ? lane_m : lane_p;
+            const bool own = jd < 40;
+            const int j = own ? jd : 80 - jd;
+            const DirW<RT, DAG, KERN_BRI> dw(j);
+            C w[3][3], chi[4][3];
+            load_link<LS>(w, W + (size_t)j * 9 * V, own ? x : sel3(dx, om[0], o0[0], op[0]) + yzt, V);
+            const RT sg = own ? (RT)1 : (RT)-1;  // the partner term has S_{-d}: derivative weights negated
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!live[r]) continue;
+                if (own)
+                    transport_shift<C, RT, false>(chi, w, pc[r], dx != 0, src);
+                else
+                    transport_shift<C, RT, true>(chi, w, pc[r], dx != 0, src);
+                spin_accumulate(acc[r], chi, dw.a, sg * dw.c0, sg * dw.c1, sg * dw.c2, sg * dw.c3);
+            }
+        }
+    }
+
+    __shared__ C red[NSPLIT][12][64];
+    __shared__ double wsum[NSPLIT][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!live[r]) continue;
+        const int col = col0 + r;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) red[q][s * 3 + b][lane] = acc[r][s][b];
+        __syncthreads();
+        double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NCOMP; ++i) {
+            const int comp = q * NCOMP + i;
+            C v = red[0][comp][lane];
+#pragma unroll
+            for (int w = 1; w < NSPLIT; ++w) {
+                const C u = red[w][comp][lane];
+                v.x += u.x;
+                v.y += u.y;
+            }
+            if (a.g.csw != 0.0)
+                clover_row<LS>(v, W + (size_t)LINK_SLAB_ENTRIES * V, in + (size_t)r * 12 * V, comp, x, V);
+            epilogue<MODE, C, RT>(a, col, comp, x, V, v, n0, n1);
+        }
+        if constexpr (MODE == EPI_NORMS || MODE == EPI_CG_R || MODE == EPI_RESID) {
+            n0 = wave_sum(n0);
+            n1 = wave_sum(n1);
+            if (lane == 0) {
+                wsum[q][0] = n0;
+                wsum[q][1] = n1;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s0 = 0.0, s1 = 0.0;
+                for (int w = 0; w < NSPLIT; ++w) {
+                    s0 += wsum[w][0];
+                    s1 += wsum[w][1];
+                }
+                const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+                a.partial[2 * pb] = s0;
+                a.partial[2 * pb + 1] = s1;
+            }
+        }
+        __syncthreads();  // red and wsum are reused by the next column
+    }
+}
+
 // ------------------------------------------------ t-streaming, one right-hand side
 //
 // stencil_stream_kernel: a block of STREAM_THREADS threads owns a tile of tile[0] x tile[1] x
@@ -704,10 +838,33 @@ inline hipError_t launch_xline(const StencilArgs &a, int mode, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class LS, int R, bool DAG>
+inline hipError_t launch_xline_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
+    const int groups = (a.ncol + R - 1) / R;
+    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(64 * MRHS_SPLIT);
+    switch (mode) {
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_CG_R>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_OV>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_SIGN>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_RESID>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <class LS, bool DAG, int KIND>
 inline hipError_t launch_cfg(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
     if (cfg.variant == VAR_XLINE) {
         if constexpr (KIND == KERN_BRI) {
+            switch (cfg.rpt) {
+            case 0: break;
+            case 2: return launch_xline_mrhs<LS, 2, DAG>(a, mode, st);
+            case 3: return launch_xline_mrhs<LS, 3, DAG>(a, mode, st);
+            case 4: return launch_xline_mrhs<LS, 4, DAG>(a, mode, st);
+            default: return hipErrorInvalidValue;
+            }
             if (cfg.rpt == 0) {
                 switch (cfg.nsplit) {
                 case 1: return launch_xline<LS, 1, DAG>(a, mode, st);

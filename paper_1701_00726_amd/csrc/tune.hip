@@ -114,8 +114,8 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
                 c.rpt = w.second;
                 c.xcd_remap = xcd;
                 out.push_back(c);
-                // the x-line kernel where the tile spans whole x-lines
-                if (w.second == 0 && t[0] == g.L[0]) {
+                // the x-line kernels where the tile spans whole x-lines
+                if (w.second != 1 && t[0] == g.L[0]) {
                     c.variant = VAR_XLINE;
                     out.push_back(c);
                 }

@@ -158,6 +158,8 @@ def _xline_cfgs(L):
                     out += [((tx, ty, 1, 1), cz) for cz in (2, 4) if L[2] % cz == 0]
     for (t, cz), ns, xcd in itertools.product(out, (1, 2, 4), (0, 1)):
         yield bri.StencilCfg(t[0], t[1], t[2], t[3], cz, ns, 0, xcd, 2)
+    for (t, cz), rpt in itertools.product(out[:3], (2, 3, 4)):  # R right-hand sides per thread
+        yield bri.StencilCfg(t[0], t[1], t[2], t[3], cz, 4, rpt, 1, 2)
 
 
 @pytest.mark.parametrize("Lx", [(16, 8, 8, 6), (32, 4, 4, 4), (64, 2, 2, 4), (8, 8, 4, 4), (2, 8, 4, 4),
@@ -167,22 +169,23 @@ def test_xline_configs_match_oracle(Lx):
     U = synth.random_links(Lx, 0.6, 4246)
     Wo = oracle.links(Lx, U)
     W = bri.build_links(Lx, bri.links_to_device(U), bri.F64)
-    psi = synth.gaussian_source(Lx, 69, nrhs=2)
+    nrhs = 5  # a partial last group of columns for 2, 3 and 4 per thread
+    psi = synth.gaussian_source(Lx, 69, nrhs=nrhs)
     ref = oracle.dirac(Lx, Wo, -0.9, psi)
     refd = oracle.dirac_adj(Lx, Wo, -0.9, psi)
     x = bri.spinor_to_device(psi)
     n = 0
     try:
         for cfg in _xline_cfgs(Lx):
-            bri.set_stencil_cfg(Lx, bri.F64, 2, cfg)
+            bri.set_stencil_cfg(Lx, bri.F64, nrhs, cfg)
             got = bri.spinor_to_host(bri.apply(Lx, W, bri.F64, -0.9, x))
             gotd = bri.spinor_to_host(bri.apply_dag(Lx, W, bri.F64, -0.9, x))
-            for r in range(2):
+            for r in range(nrhs):
                 assert rel_l2(got[r], ref[r]) < 1e-14, cfg.as_dict()
                 assert rel_l2(gotd[r], refd[r]) < 1e-14, cfg.as_dict()
             n += 1
     finally:
-        bri.set_stencil_cfg(Lx, bri.F64, 2, None)
+        bri.set_stencil_cfg(Lx, bri.F64, nrhs, None)
     assert n >= 6
 
 
@@ -243,4 +246,44 @@ def test_xline_solver_epilogues(field, nrhs):
         refs, _, _ = oracle.sign_apply(L, Wo, 1.0, 8, b[r], tol=1e-13)
         assert rel_l2(got[r], ref) < 1e-10
         assert rel_l2(gots[r], refs) < 1e-10
+    assert max(st.rel_resid) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(bri.F32, 2e-6), (bri.F32_BF16W, 2e-2)])
+@pytest.mark.parametrize("rpt", [2, 3, 4])
+def test_xline_mrhs_low_precision(field, prec, tol, rpt):
+    need_gpu()
+    U, Wo, _ = field
+    W = bri.build_links(L, bri.links_to_device(U), prec)
+    psi = synth.gaussian_source(L, 73, nrhs=7)
+    x = bri.spinor_to_device(psi, prec)
+    ref = oracle.dirac(L, Wo, -0.9, psi)
+    refd = oracle.dirac_adj(L, Wo, -0.9, psi)
+    try:
+        bri.set_stencil_cfg(L, prec, 7, bri.StencilCfg(16, 4, 1, 1, 4, 4, rpt, 1, 2))
+        got = bri.spinor_to_host(bri.apply(L, W, prec, -0.9, x))
+        gotd = bri.spinor_to_host(bri.apply_dag(L, W, prec, -0.9, x))
+    finally:
+        bri.set_stencil_cfg(L, prec, 7, None)
+    for r in range(7):
+        assert rel_l2(got[r], ref[r]) < tol
+        assert rel_l2(gotd[r], refd[r]) < tol
+
+
+def test_xline_mrhs_solver_epilogues(field):
+    """Batched overlap apply and sign function with the x-line multi-RHS kernel (3 per thread,
+    a partial group) installed for the solve's 5 columns."""
+    need_gpu()
+    _, Wo, W = field
+    b = synth.gaussian_source(L, 74, nrhs=5)
+    try:
+        bri.set_stencil_cfg(L, bri.F64, 5, bri.StencilCfg(16, 4, 1, 1, 2, 4, 3, 1, 2))
+        op = bri.OverlapOp(L, W, kl_n=8, tol=1e-12, nrhs=5)
+        out, st = op.apply(bri.spinor_to_device(b))
+    finally:
+        bri.set_stencil_cfg(L, bri.F64, 5, None)
+    got = bri.spinor_to_host(out)
+    for r in (0, 4):
+        ref, _, _ = oracle.ov_apply(L, Wo, 1.0, 8, b[r], tol=1e-13)
+        assert rel_l2(got[r], ref) < 1e-10
     assert max(st.rel_resid) <= 1e-12
