@@ -46,8 +46,17 @@ _lock = threading.Lock()
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+def build(force: bool = False, sanitize_to: str | None = None) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP).  sanitize_to: instead build a copy
+    instrumented with AddressSanitizer and UndefinedBehaviorSanitizer (ROCm's clang, so that it
+    shares the sanitizer runtime of the library's sanitized host code) at that path."""
+    if sanitize_to:
+        subprocess.check_call(
+            ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+             "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+             "-shared-libsan", "-o", sanitize_to, _SRC, "-lm"]
+        )
+        return sanitize_to
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(
@@ -61,8 +70,12 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            lib = ctypes.CDLL(_SO)
+            alt = os.environ.get("ORACLE_LIB")  # a separately built copy (the sanitizer job)
+            if alt:
+                lib = ctypes.CDLL(alt)
+            else:
+                build()
+                lib = ctypes.CDLL(_SO)
             P = ctypes.c_void_p
             I = ctypes.c_int
             D = ctypes.c_double

@@ -26,7 +26,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbrillouin.so")
+# BRI_LIB selects another build of the library (the CPU sanitizer job's instrumented copy)
+LIB_PATH = os.environ.get("BRI_LIB") or os.path.join(_HERE, "libbrillouin.so")
 
 F64, F32, F32_BF16W = 0, 1, 2
 KL_DIAG, KL_UPPER = 0, 1

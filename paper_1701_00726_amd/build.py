@@ -36,14 +36,26 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+# host code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer (CPU checks of the
+# argument validation, planning and host bookkeeping); -Xarch_host keeps the sanitizer off the
+# device pass (the CPU job launches no kernel)
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize_to: str | None = None) -> str:
+    """Compile every csrc/*.hip for gfx950 and link libbrillouin.so next to this file; with
+    sanitize_to, link a copy whose host code is sanitized at that path instead."""
     srcs = sources()
+    flags = [f for f in FLAGS if f != "-O3"] + SANITIZE_FLAGS if sanitize_to else FLAGS
+    out_lib = sanitize_to or LIB
     tmpdir = tempfile.mkdtemp(prefix="bri_build_")
     try:
         objs, procs = [], []
         for src in srcs:
             obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
-            cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+            cmd = [HIPCC, *flags, "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -66,12 +78,15 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
                 sys.stderr.write(f"--- hipcc failed on {src}\n{text}\n")
             raise RuntimeError("HIP build failed")
         tmp_lib = os.path.join(tmpdir, "libbrillouin.so")
-        subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs])
-        shutil.copyfile(tmp_lib, LIB + ".tmp")
-        os.replace(LIB + ".tmp", LIB)
+        link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs]
+        if sanitize_to:
+            link += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
+        subprocess.check_call(link)
+        shutil.copyfile(tmp_lib, out_lib + ".tmp")
+        os.replace(out_lib + ".tmp", out_lib)
     finally:
         shutil.rmtree(tmpdir, ignore_errors=True)
-    return LIB
+    return out_lib
 
 
 if __name__ == "__main__":

@@ -13,6 +13,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library through its C ABI)")
     config.addinivalue_line("markers", "slow: long-running CPU check")
+    config.addinivalue_line("markers", "sanitize: opt-in CPU sanitizer job (BRI_SANITIZE=1)")
 
 
 @pytest.fixture(scope="session")
