@@ -167,6 +167,10 @@ typedef struct {
                        larger residual); 0: every shift at tol                  */
     int kernel;     /* bri_kernel: X = D_kernel(-rho); BRI_KERNEL_BRILLOUIN unless
                        stated                                                  */
+    int recompute;  /* ov_apply_grad only: 0 keeps all 2n shift solutions of one
+                       multi-shift solve; m in 1..kl_n solves the shifts m at a
+                       time and keeps only those (workspace for 4m instead of
+                       ~6n vectors, at the cost of a solve per group)           */
 } ov_params;
 
 /* Statistics of one overlap apply; for nrhs > 1 each figure is the worst column's. */
@@ -363,7 +367,10 @@ int bri_get_stencil_cfg(const bri_geom *geom, int prec, int nrhs, bri_stencil_cf
  * configuration) on a library-owned stream and
  * replayed on the caller's stream; up to 16 instantiated graphs are cached per process and
  * disabling clears them.  Results are identical either way (same kernels, same order).
- * Not thread-safe against solves running concurrently in other threads.  BRI_EINVAL for
+ * Cached graphs are looked up and launched under a lock, and an evicted or cleared graph is
+ * destroyed only after its last launch has completed, so solves in several host threads may
+ * share the cache; switching graphs off while other threads solve is not supported (their
+ * solves keep launching graphs).  BRI_EINVAL for
  * other values. */
 int bri_set_solver_graphs(int enable);
 

@@ -59,6 +59,7 @@ class _OvParams(ctypes.Structure):
         ("kind", ctypes.c_int),
         ("relax", ctypes.c_int),
         ("kernel", ctypes.c_int),
+        ("recompute", ctypes.c_int),
     ]
 
 
@@ -404,14 +405,16 @@ class OverlapOp:
     """Holds the workspace of ov_apply / ov_sign_apply for one lattice and parameter set."""
 
     def __init__(self, L, W64, kl_n=16, rho=1.0, tol=1e-12, max_iter=2000, Wlo=None, inner=F64, tbc=0,
-                 max_refine=None, nrhs=1, kind=KL_DIAG, relax=False, kernel=KERNEL_BRILLOUIN):
+                 max_refine=None, nrhs=1, kind=KL_DIAG, relax=False, kernel=KERNEL_BRILLOUIN, recompute=0):
         """Workspace for up to `nrhs` right-hand sides per call.  inner = F32 or
         F32_BF16W runs the late multi-shift iterations (once the residual has fallen to
         tol / unit roundoff) on FP32 vectors with the low-precision links `Wlo`,
         accumulating the result in FP64 (max_refine is unused).  kind = KL_UPPER
         uses the first upper diagonal g_{2n} instead of g_{2n+1}; relax stops shift i
         at tol * omega_max / omega_i; kernel = KERNEL_WILSON builds the overlap on the
-        Wilson operator (the one-hop slabs of W64) instead of the Brillouin one."""
+        Wilson operator (the one-hop slabs of W64) instead of the Brillouin one.  recompute = m > 0
+        makes grad solve the shifts m at a time, keeping only those solutions (less memory,
+        more solver iterations); 0 keeps all of one multi-shift solve."""
         self.L = tuple(int(v) for v in L)
         if Wlo is not None and Wlo.shape[0] != W64.shape[0]:
             raise ValueError("W64 and Wlo must both carry the clover term or both not")
@@ -423,7 +426,7 @@ class OverlapOp:
         if max_refine is None:
             max_refine = 0
         self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine),
-                                int(kind), 1 if relax else 0, int(kernel))
+                                int(kind), 1 if relax else 0, int(kernel), int(recompute))
         self.nrhs = int(nrhs)
         nbytes = ctypes.c_size_t(0)
         _check(

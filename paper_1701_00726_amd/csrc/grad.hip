@@ -35,7 +35,8 @@ namespace bri {
 // Multi-shift solve of (A + sigma_i) x = b over the Kenney-Laub shifts, every x kept in FP64
 // ([shift][ncol][12 V] in the workspace); with work == NULL only *need is set (solver.hip).
 int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_params *prm, const void *b, int ncol,
-                    void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st);
+                    void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st,
+                    int i0 = -1, int i1 = -1);
 // the rational of `prm` (diagonal or upper-diagonal coefficients, per-shift tolerance factors) and
 // the validity check of its fields (solver.hip)
 void shift_coeffs(const ov_params *prm, double *c0, double *omega, double *sigma, double *tolf);
@@ -109,6 +110,7 @@ struct PairTable {
     const double2 *v[BRI_MAX_PAIRS];
     double w[BRI_MAX_PAIRS];
     int n;
+    int accumulate;  // add to G instead of overwriting it
 };
 
 // G[j][a][b](x) = sum_p w_p sum_t conj((S_d u_p(x))_{t,a}) v_p(x+d)_{t,b}, all d != 0.
@@ -213,7 +215,15 @@ __global__ __launch_bounds__(64 * OUTER_WAVES) void grad_outer_kernel(Geom g, Pa
 #pragma unroll
         for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) G[((size_t)j * 9 + aa * 3 + bb) * V + x] = acc[i][aa][bb];
+            for (int bb = 0; bb < 3; ++bb) {
+                double2 *gp = G + ((size_t)j * 9 + aa * 3 + bb) * V + x;
+                if (pt.accumulate) {
+                    const double2 o = *gp;
+                    *gp = make_double2(o.x + acc[i][aa][bb].x, o.y + acc[i][aa][bb].y);
+                } else {
+                    *gp = acc[i][aa][bb];
+                }
+            }
     }
 }
 
@@ -409,20 +419,27 @@ static inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 // G buffer [81][9][V] complex double
 static size_t grad_g_bytes(const Geom &g) { return al256((size_t)81 * 9 * g.V * sizeof(double2)); }
 
-static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, const PairTable &pt, double2 *G,
-                            double *F, double2 *GU, hipStream_t s, int kind) {
-    const int threads = 128;
-    const int blocks = (g.V + threads - 1) / threads;
+// G (=, or += with pt.accumulate) the outer products of the pairs of pt
+static void outer_pairs(const Geom &g, const PairTable &pt, double2 *G, hipStream_t s, int kind) {
     const int tiles = (g.V + 63) / 64;
-    if (kind == KERN_WIL) {
-        // one-hop displacements only: no pull-back through the path average
+    if (kind == KERN_WIL)
         hipLaunchKernelGGL(grad_outer_kernel<KERN_WIL>, dim3(OuterDisp<KERN_WIL>::groups * tiles),
                            dim3(64 * OUTER_WAVES), 0, s, g, pt, G);
+    else
+        hipLaunchKernelGGL(grad_outer_kernel<KERN_BRI>, dim3(OuterDisp<KERN_BRI>::groups * tiles),
+                           dim3(64 * OUTER_WAVES), 0, s, g, pt, G);
+}
+
+// pull-back of the accumulated G through the path average (Brillouin kernel) and the force
+static int force_from_outer(const Geom &g, const double2 *U, const double2 *W, double2 *G, double *F, double2 *GU,
+                            hipStream_t s, int kind) {
+    const int threads = 128;
+    const int blocks = (g.V + threads - 1) / threads;
+    if (kind == KERN_WIL) {
+        // one-hop displacements only: no pull-back through the path average
         hipLaunchKernelGGL(grad_force_kernel, dim3(4 * blocks), dim3(threads), 0, s, g, U, W, G, F, GU, kind);
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     }
-    hipLaunchKernelGGL(grad_outer_kernel<KERN_BRI>, dim3(OuterDisp<KERN_BRI>::groups * tiles), dim3(64 * OUTER_WAVES),
-                       0, s, g, pt, G);
     for (int k = 4; k >= 2; --k) {
         HopDirs lower{};
         for (int j = 0; j < 81; ++j) {
@@ -436,25 +453,36 @@ static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, c
     return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
 }
 
+static int force_from_pairs(const Geom &g, const double2 *U, const double2 *W, const PairTable &pt, double2 *G,
+                            double *F, double2 *GU, hipStream_t s, int kind) {
+    outer_pairs(g, pt, G, s, kind);
+    return force_from_outer(g, U, W, G, F, GU, s, kind);
+}
+
 // workspace of ov_apply_grad, carved in this order
 struct GradPlan {
     size_t g_off, xab_off, bin_off, y_off, om_off, solver_off, bytes, solver_bytes;
 };
 
+// shifts per solve of the gradient: all of them, or recompute at a time
+static int grad_chunk(const ov_params *prm) {
+    return prm->recompute > 0 && prm->recompute < prm->kl_n ? prm->recompute : prm->kl_n;
+}
+
 static int plan_grad(const Geom &g, const ov_params *prm, GradPlan &pl) {
     const size_t nel = (size_t)12 * g.V;
     const size_t vb = al256(nel * sizeof(double2));
-    const int n = prm->kl_n;
+    const int m = grad_chunk(prm);
     size_t solver_need = 0;
     void *xdummy = nullptr;
-    const int rc =
-        ov_solve_shifts(g, nullptr, nullptr, prm, nullptr, 2, nullptr, 0, &solver_need, nullptr, &xdummy, nullptr);
+    const int rc = ov_solve_shifts(g, nullptr, nullptr, prm, nullptr, 2, nullptr, 0, &solver_need, nullptr, &xdummy,
+                                   nullptr, 0, m);
     if (rc != BRI_OK) return rc;
     size_t off = 0;
     pl.g_off = off;
     off += grad_g_bytes(g);
-    pl.xab_off = off;  // X applied to the 2n shift solutions
-    off += vb * 2 * n;
+    pl.xab_off = off;  // X applied to the 2m shift solutions of one solve
+    off += vb * 2 * m;
     pl.bin_off = off;  // [psi | X^dag chi]
     off += vb * 2;
     pl.y_off = off;
@@ -584,47 +612,74 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     a.diag = kernel_diag(prm->kernel) + m0;
     rc = stencil_launch(a, BRI_F64, true, EPI_PLAIN, default_config(g, BRI_F64, 1, prm->kernel), s);
     if (rc != BRI_OK) return rc;
-    // a_i = (A + sigma_i)^{-1} psi and b_i = (A + sigma_i)^{-1} X^dag chi in one two-column multi-shift
-    // solve; X holds them as [i][2][12 V], i.e. a_i = X[2 i], b_i = X[2 i + 1]
-    void *xs = nullptr;
-    ov_stats sst;
-    int rcs = ov_solve_shifts(g, W64, Wlo, prm, BIN, 2, swork, pl.solver_bytes, nullptr, s, &xs, &sst);
-    if (rcs != BRI_OK && rcs != BRI_ENOCONV) return rcs;
-    const double2 *X = (const double2 *)xs;
+    // a_i = (A + sigma_i)^{-1} psi and b_i = (A + sigma_i)^{-1} X^dag chi by two-column multi-shift
+    // solves over the shifts, m at a time (m = n: one solve keeping every solution); a solve's X
+    // holds them as [i][2][12 V], i.e. a_i = X[2 i], b_i = X[2 i + 1].  Per solve the pairs
+    // (X a_i, b_i), (X b_i, a_i) (weight -rho omega_i) are added to the outer products G, and
+    // y = c0 psi + sum omega_i a_i, gpsi = rho (chi + c0 X^dag chi + sum omega_i b_i) accumulate;
+    // the pair (chi, y) (weight rho) joins the last solve's.
     double c0, om[MAXS], sg[MAXS], tf[MAXS];
     shift_coeffs(prm, &c0, om, sg, tf);
     BRI_HIP_CHECK(hipMemcpyAsync(om_dev, om, sizeof(double) * n, hipMemcpyHostToDevice, s));
-    // y = c0 psi + sum omega_i a_i ; gpsi = rho (chi + c0 X^dag chi + sum omega_i b_i)
     hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, c0, (const double2 *)psi, 0.0,
-                       (const double2 *)nullptr, 1.0, n, (const double *)om_dev, X, 2 * nel, Y);
+                       (const double2 *)nullptr, 0.0, 0, (const double *)om_dev, (const double2 *)nullptr, 0, Y);
     hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, prm->rho, (const double2 *)chi,
-                       prm->rho * c0, (const double2 *)(BIN + nel), prm->rho, n, (const double *)om_dev, X + nel,
-                       2 * nel, (double2 *)gpsi);
+                       prm->rho * c0, (const double2 *)(BIN + nel), 0.0, 0, (const double *)om_dev,
+                       (const double2 *)nullptr, 0, (double2 *)gpsi);
     BRI_HIP_CHECK(hipGetLastError());
-    // X applied to all 2n shift solutions
-    StencilArgs ax = a;
-    ax.ncol = 2 * n;
-    ax.in = X;
-    ax.out = XAB;
-    rc = stencil_launch(ax, BRI_F64, false, EPI_PLAIN, default_config(g, BRI_F64, 2 * n, prm->kernel), s);
-    if (rc != BRI_OK) return rc;
-    PairTable pt;
-    std::memset(&pt, 0, sizeof(pt));
-    pt.n = 1 + 2 * n;
-    pt.u[0] = (const double2 *)chi;
-    pt.v[0] = Y;
-    pt.w[0] = prm->rho;
-    for (int i = 0; i < n; ++i) {
-        // (X a_i, b_i) and (X b_i, a_i), weight -rho omega_i
-        pt.u[1 + 2 * i] = XAB + (size_t)(2 * i) * nel;
-        pt.v[1 + 2 * i] = X + (size_t)(2 * i + 1) * nel;
-        pt.w[1 + 2 * i] = -prm->rho * om[i];
-        pt.u[2 + 2 * i] = XAB + (size_t)(2 * i + 1) * nel;
-        pt.v[2 + 2 * i] = X + (size_t)(2 * i) * nel;
-        pt.w[2 + 2 * i] = -prm->rho * om[i];
+    const int m = grad_chunk(prm);
+    int rcs = BRI_OK;
+    ov_stats sst;
+    std::memset(&sst, 0, sizeof(sst));
+    for (int i0 = 0; i0 < n; i0 += m) {
+        const int i1 = i0 + m < n ? i0 + m : n, mc = i1 - i0;
+        const bool last = i1 == n;
+        void *xs = nullptr;
+        ov_stats cst;
+        const int r = ov_solve_shifts(g, W64, Wlo, prm, BIN, 2, swork, pl.solver_bytes, nullptr, s, &xs, &cst, i0, i1);
+        if (r != BRI_OK && r != BRI_ENOCONV) return r;
+        if (r == BRI_ENOCONV) rcs = r;
+        sst.iters += cst.iters;
+        sst.refine += cst.refine;
+        for (int k = 0; k < mc; ++k) {
+            sst.shift_iters[i0 + k] = cst.shift_iters[k];
+            sst.rel_resid[i0 + k] = cst.rel_resid[k];
+        }
+        const double2 *X = (const double2 *)xs;
+        hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, 1.0, (const double2 *)Y, 0.0,
+                           (const double2 *)nullptr, 1.0, mc, (const double *)(om_dev + i0), X, 2 * nel, Y);
+        hipLaunchKernelGGL(grad_combine_kernel, dim3(1024), dim3(256), 0, s, nel, 1.0, (const double2 *)gpsi, 0.0,
+                           (const double2 *)nullptr, prm->rho, mc, (const double *)(om_dev + i0), X + nel, 2 * nel,
+                           (double2 *)gpsi);
+        BRI_HIP_CHECK(hipGetLastError());
+        // X applied to this solve's 2 mc shift solutions
+        StencilArgs ax = a;
+        ax.ncol = 2 * mc;
+        ax.in = X;
+        ax.out = XAB;
+        rc = stencil_launch(ax, BRI_F64, false, EPI_PLAIN, default_config(g, BRI_F64, 2 * mc, prm->kernel), s);
+        if (rc != BRI_OK) return rc;
+        PairTable pt;
+        std::memset(&pt, 0, sizeof(pt));
+        pt.accumulate = i0 > 0;
+        for (int k = 0; k < mc; ++k) {
+            const double w = -prm->rho * om[i0 + k];
+            pt.u[pt.n] = XAB + (size_t)(2 * k) * nel;
+            pt.v[pt.n] = X + (size_t)(2 * k + 1) * nel;
+            pt.w[pt.n++] = w;
+            pt.u[pt.n] = XAB + (size_t)(2 * k + 1) * nel;
+            pt.v[pt.n] = X + (size_t)(2 * k) * nel;
+            pt.w[pt.n++] = w;
+        }
+        if (last) {
+            pt.u[pt.n] = (const double2 *)chi;
+            pt.v[pt.n] = Y;
+            pt.w[pt.n++] = prm->rho;
+        }
+        outer_pairs(g, pt, G, s, prm->kernel);
+        BRI_HIP_CHECK(hipGetLastError());
     }
-    rc = force_from_pairs(g, (const double2 *)U, (const double2 *)W64, pt, G, (double *)F, (double2 *)GU, s,
-                          prm->kernel);
+    rc = force_from_outer(g, (const double2 *)U, (const double2 *)W64, G, (double *)F, (double2 *)GU, s, prm->kernel);
     if (rc != BRI_OK) return rc;
     if (hipStreamSynchronize(s) != hipSuccess) return BRI_EHIP;
     if (stats) {

@@ -418,6 +418,7 @@ bool params_ok(const ov_params *prm) {
     if (prm->max_refine < 0 || prm->max_refine > 100) return false;
     if (prm->kind != BRI_KL_DIAG && prm->kind != BRI_KL_UPPER) return false;
     if (prm->kernel != BRI_KERNEL_BRILLOUIN && prm->kernel != BRI_KERNEL_WILSON) return false;
+    if (prm->recompute < 0 || prm->recompute > MAXS) return false;
     return prm->relax == 0 || prm->relax == 1;
 }
 
@@ -501,20 +502,36 @@ struct RunStats {
 
 // ------------------------------------------------------------ graph cache
 
-// Instantiated graphs of CHECK_EVERY solver iterations, keyed by everything their launches
+// Instantiated graphs of a block of solver iterations, keyed by everything their launches
 // depend on (device, geometry, precision, buffers, launch configuration).  Bounded; the
 // oldest entry is destroyed first.  Capture runs on a library stream per device (capture
 // is not possible on the null stream); the graph is then launched on the caller's stream.
+// Each entry carries an event recorded after every launch of it, and an entry is destroyed
+// only after that event has completed, so a graph another host thread launched on its own
+// stream is never destroyed while it runs.
 namespace {
 constexpr size_t GRAPH_CACHE_MAX = 16;
+struct CachedGraph {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each launch
+};
 std::mutex g_graph_mu;
 bool g_graphs_on = true;
-std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
+std::map<std::vector<uint64_t>, CachedGraph> g_graphs;
 std::deque<std::vector<uint64_t>> g_graph_order;
 std::map<int, hipStream_t> g_capture_streams;
 
+void graph_release(CachedGraph &c) {
+    if (c.done) {
+        (void)hipEventSynchronize(c.done);  // the last launch has finished
+        (void)hipEventDestroy(c.done);
+    }
+    if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    c = CachedGraph{};
+}
+
 void graph_cache_clear_locked() {
-    for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : g_graphs) graph_release(kv.second);
     g_graphs.clear();
     g_graph_order.clear();
 }
@@ -527,7 +544,10 @@ template <typename F>
 static int graph_launch(const std::vector<uint64_t> &key, F enqueue, hipStream_t strm) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) return hipGraphLaunch(it->second, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
+    if (it != g_graphs.end()) {
+        if (hipGraphLaunch(it->second.exec, strm) != hipSuccess) return BRI_EHIP;
+        return hipEventRecord(it->second.done, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
+    }
     int dev = 0;
     BRI_HIP_CHECK(hipGetDevice(&dev));
     hipStream_t cs = g_capture_streams[dev];
@@ -543,19 +563,25 @@ static int graph_launch(const std::vector<uint64_t> &key, F enqueue, hipStream_t
         if (graph) (void)hipGraphDestroy(graph);
         return rc != BRI_OK ? rc : BRI_EHIP;
     }
-    hipGraphExec_t ex = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    CachedGraph c;
+    const hipError_t ei = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return BRI_EHIP;
+    if (hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess) {
+        c.done = nullptr;
+        graph_release(c);
+        return BRI_EHIP;
+    }
     if (g_graphs.size() >= GRAPH_CACHE_MAX) {
         auto old = g_graph_order.front();
         g_graph_order.pop_front();
-        (void)hipGraphExecDestroy(g_graphs[old]);
+        graph_release(g_graphs[old]);
         g_graphs.erase(old);
     }
-    g_graphs[key] = ex;
+    g_graphs[key] = c;
     g_graph_order.push_back(key);
-    return hipGraphLaunch(ex, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
+    if (hipGraphLaunch(c.exec, strm) != hipSuccess) return BRI_EHIP;
+    return hipEventRecord(c.done, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
 }
 
 // The pinned host word the solvers poll the all-done flag into: one per (host thread, device),
@@ -773,11 +799,17 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
 // The multi-shift solve behind an overlap apply or the gradient: FP64, or FP64 with a low-
 // precision phase for inner = BRI_F32 / BRI_F32_BF16W, entered once the base residual has
 // fallen to tol / u_lo (u_lo the inner precision's unit roundoff; at once when that exceeds 1).
+// i0, i1: the shifts [i0, i1) of the rational only (the gradient's recompute mode); -1: all.
 static void plan_shifts(MsSolve &m, const Geom &g, const ov_params *prm, int ncol, const void *W64, const void *Wlo,
-                        bool store_x) {
-    const int n = prm->kl_n;
-    double om[MAXS], sg[MAXS], tf[MAXS];
-    shift_coeffs(prm, &m.c0, om, sg, tf);
+                        bool store_x, int i0 = -1, int i1 = -1) {
+    double om_all[MAXS], sg_all[MAXS], tf_all[MAXS];
+    shift_coeffs(prm, &m.c0, om_all, sg_all, tf_all);
+    if (i0 < 0) {
+        i0 = 0;
+        i1 = prm->kl_n;
+    }
+    const int n = i1 - i0;
+    const double *om = om_all + i0, *sg = sg_all + i0, *tf = tf_all + i0;
     m.g = g;
     m.prec = BRI_F64;
     m.W = W64;
@@ -920,18 +952,24 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     return result;
 }
 
-// Multi-shift solve of (A + sigma_i) x_i = b over the Kenney-Laub shifts with every x_i kept
-// in FP64, [shift][ncol][12 V] inside the workspace (the gradient needs the individual shift
-// solutions).  inner = BRI_F64 runs it in FP64; a low-precision inner relaxes the precision
+// Multi-shift solve of (A + sigma_i) x_i = b over the Kenney-Laub shifts i0 <= i < i1 (all for
+// i0 = -1) with every x_i kept in FP64, [shift][ncol][12 V] inside the workspace (the gradient
+// needs the individual shift solutions).  inner = BRI_F64 runs it in FP64; a low-precision inner relaxes the precision
 // of the late iterations as the overlap apply does.  With work == NULL only *need is set.
 // st (may be NULL) receives iterations and the final residual of each shift (the worst column).
 int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_params *prm, const void *b, int ncol,
-                    void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st) {
-    const int n = prm->kl_n;
-    if (n < 1 || n > MAXS || ncol < 1) return BRI_EINVAL;
+                    void *work, size_t work_bytes, size_t *need, hipStream_t s, void **x_out, ov_stats *st, int i0,
+                    int i1) {
+    if (prm->kl_n < 1 || prm->kl_n > MAXS || ncol < 1) return BRI_EINVAL;
+    if (i0 < 0) {
+        i0 = 0;
+        i1 = prm->kl_n;
+    }
+    if (i1 <= i0 || i1 > prm->kl_n) return BRI_EINVAL;
+    const int n = i1 - i0;
     const bool mixed = prm->inner != BRI_F64;
     MsSolve m;
-    plan_shifts(m, g, prm, ncol, W64, Wlo, true);
+    plan_shifts(m, g, prm, ncol, W64, Wlo, true, i0, i1);
     Arena ar(work);
     m.carve(ar);
     if (!work) {

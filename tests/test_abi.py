@@ -129,6 +129,17 @@ def test_gradient_workspace_and_invalid_arguments():
     assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(lo), None, None, None, None, None, None,
                              ctypes.byref(nb_lo), None, None) == bri.OK
     assert nb_lo.value > nb.value
+    # recomputed shift solutions, two shifts per solve: G, the 4 applied solutions, [psi | X^dag chi], y
+    # and a two-column two-shift solve (r, p, t: 3 x 2; x: 2 x 2; shifted directions: 1 x 2)
+    rcp = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0, 0, 0, 0, 2)
+    nb_r = ctypes.c_size_t(0)
+    assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(rcp), None, None, None, None, None, None,
+                             ctypes.byref(nb_r), None, None) == bri.OK
+    assert 81 * 9 * V * 16 + vec * (4 + 2 + 1 + 6 + 4 + 2) <= nb_r.value < nb.value
+    for m in (-1, bri.MAX_SHIFTS + 1):
+        bad = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0, 0, 0, 0, m)
+        assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(bad), None, None, None, None, None,
+                                 None, ctypes.byref(nb), None, None) == bri.EINVAL
 
 
 def test_solver_graph_switch_rejects_other_values():

@@ -257,3 +257,51 @@ def test_overlap_grad_directional_at_bench_size():
     # the force is the projection of the same gradient onto i lambda_a U / 2
     Fh = _force_host(F)
     assert np.abs(_force_from_gu(U, _gu_host(GU)) - Fh).max() <= 1e-12 * np.abs(Fh).max()
+
+
+@pytest.mark.parametrize("tbc", [0, 1])
+def test_overlap_grad_recompute_4_4(tbc):
+    """Shift solutions recomputed (the shifts solved 1 and 4 at a time, keeping only those) give
+    the force and D_ov^dag chi of the stored mode and of the oracle (Sec. 9 force of the
+    partial fractions)."""
+    need_gpu()
+    U, _ = field(L4, "cfg1", tbc)
+    rng = np.random.default_rng(31 + tbc)
+    chi, psi = _rand_spinor(rng, 256), _rand_spinor(rng, 256)
+    n, rho = 6, 1.0
+    Fref, gref = oracle.ov_force(L4, U, tbc, rho, n, chi, psi, tol=1e-13)
+    Ud = bri.links_to_device(U)
+    W = bri.build_links(L4, Ud, bri.F64, tbc=tbc)
+    Fs, _, gs, _ = bri.OverlapOp(L4, W, kl_n=n, rho=rho, tol=1e-12, tbc=tbc).grad(Ud, _dev(chi), _dev(psi))
+    for m in (1, 4):
+        op = bri.OverlapOp(L4, W, kl_n=n, rho=rho, tol=1e-12, tbc=tbc, recompute=m)
+        F, _, g, st = op.grad(Ud, _dev(chi), _dev(psi))
+        got = _force_host(F)
+        assert np.abs(got - Fref).max() <= 1e-9 * np.abs(Fref).max(), m
+        assert np.abs(got - _force_host(Fs)).max() <= 1e-9 * np.abs(Fref).max(), m
+        gh = bri.spinor_to_host(g[None])[0]
+        assert rel_l2(gh, gref) < 1e-10 and rel_l2(gh, bri.spinor_to_host(gs[None])[0]) < 1e-10
+        assert max(st.rel_resid) <= 1e-12 and all(i > 0 for i in st.shift_iters)
+        # every shift solved in its own group (m = 1) takes more iterations than one multi-shift
+        if m == 1:
+            assert st.iters > max(st.shift_iters)
+
+
+def test_overlap_grad_recompute_16_4():
+    """The gradient workload (16^4, [16/16]) with the shift solutions recomputed four at a time:
+    force and D_ov^dag chi against the stored mode, and a smaller workspace."""
+    need_gpu()
+    L = (16, 16, 16, 16)
+    U, _ = field(L, "cfg2", 0)
+    Ud = bri.links_to_device(U)
+    chi = bri.spinor_to_device(synth.gaussian_source(L, 7))[0]
+    psi = bri.spinor_to_device(synth.gaussian_source(L, 8))[0]
+    W = bri.build_links(L, Ud, bri.F64)
+    ops = {m: bri.OverlapOp(L, W, kl_n=16, rho=1.0, tol=1e-12, recompute=m) for m in (0, 4)}
+    out = {m: op.grad(Ud, chi, psi) for m, op in ops.items()}
+    F0, _, g0, _ = out[0]
+    F4, _, g4, st4 = out[4]
+    assert float((F4 - F0).abs().max()) <= 1e-9 * float(F0.abs().max())
+    assert float(torch.linalg.vector_norm(g4 - g0) / torch.linalg.vector_norm(g0)) < 1e-10
+    assert max(st4.rel_resid) <= 1e-12
+    assert ops[4]._gwork.numel() < ops[0]._gwork.numel()

@@ -128,3 +128,63 @@ def test_graph_cache_eviction_and_concurrent_threads():
         t.join(timeout=120)
     assert not any(t.is_alive() for t in threads)
     assert not errors, errors
+
+
+def test_eviction_while_another_thread_runs_its_graphs():
+    """One host thread keeps applying an operator on a larger lattice (its graphs in flight on
+    its stream) while a second thread cycles through more solve layouts than the cache holds,
+    so cache entries are evicted while graphs of the first thread may still run; eviction waits
+    for each entry's last launch.  Every result bit for bit the eager one."""
+    import threading
+
+    need_gpu()
+    Lb, Ls = (8, 8, 8, 8), (4, 4, 4, 4)
+    Ub, _ = field(Lb, "cfg1")
+    Us, _ = field(Ls, "cfg1")
+    Wb = bri.build_links(Lb, bri.links_to_device(Ub), bri.F64)
+    Ws = bri.build_links(Ls, bri.links_to_device(Us), bri.F64)
+    bb = bri.spinor_to_device(synth.gaussian_source(Lb, synth.SOURCE_SEED_BASE + 11))
+    bs = bri.spinor_to_device(synth.gaussian_source(Ls, synth.SOURCE_SEED_BASE + 12))
+    bri.set_solver_graphs(False)
+    refb, _ = bri.OverlapOp(Lb, Wb, kl_n=16, tol=1e-12).apply(bb)
+    refs, _ = bri.OverlapOp(Ls, Ws, kl_n=8, tol=1e-12).apply(bs)
+    bri.set_solver_graphs(True)
+    big = bri.OverlapOp(Lb, Wb, kl_n=16, tol=1e-12)
+    smalls = [bri.OverlapOp(Ls, Ws, kl_n=8, tol=1e-12) for _ in range(24)]
+    errors, stop = [], threading.Event()
+
+    def runner():
+        s = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(s):
+                while not stop.is_set():
+                    out, _ = big.apply(bb, stream=s)
+                    s.synchronize()
+                    if not torch.equal(out, refb):
+                        errors.append("big mismatch")
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    def evictor():
+        s = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    for op in smalls:  # 24 layouts x 2 block lengths > 16 cache entries
+                        out, _ = op.apply(bs, stream=s)
+                        s.synchronize()
+                        if not torch.equal(out, refs):
+                            errors.append("small mismatch")
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+        finally:
+            stop.set()
+
+    threads = [threading.Thread(target=runner), threading.Thread(target=evictor)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=180)
+    stop.set()
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors[:5]
