@@ -329,7 +329,10 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  *      link inside one slice; col_z and nsplit are ignored;
  *   2  x-line: as 0 with tile_x = L_x (whole x-lines in every wave), the three
  *      x-displacements of each (dy, dz, dt) sharing one spinor load; with
- *      rpt = 2, 3 or 4 right-hand sides per thread as the multi-RHS kernel.
+ *      rpt = 2, 3 or 4 right-hand sides per thread as the multi-RHS kernel;
+ *   3  matrix cores (BRI_F32 and BRI_F32_BF16W only): rpt = 1..4 right-hand sides
+ *      per thread, the colour transport by FP32 MFMA (16 sites per wave, a site's
+ *      four spins in four lanes), the spin weights applied across those lanes.
  */
 typedef struct {
     int tile_x, tile_y, tile_z, tile_t;

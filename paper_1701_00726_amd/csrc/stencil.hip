@@ -79,7 +79,8 @@ int plan_tile(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
     const int rc = plan_tile_base(g, cfg, tile, nb);
     if (rc != BRI_OK) return rc;
     if (cfg.variant == VAR_XLINE && (tile[0] != g.L[0] || cfg.rpt == 1 || cfg.rpt > 4)) return BRI_EINVAL;
-    if (cfg.variant < VAR_STANDARD || cfg.variant > VAR_XLINE) return BRI_EINVAL;
+    if (cfg.variant == VAR_MFMA && (cfg.rpt < 1 || cfg.rpt > 4)) return BRI_EINVAL;
+    if (cfg.variant < VAR_STANDARD || cfg.variant > VAR_MFMA) return BRI_EINVAL;
     return BRI_OK;
 }
 

@@ -76,9 +76,11 @@ struct StencilConfig {
                       //   VAR_XLINE     64-site tiles spanning whole x-lines (tile[0] = L_x): the
                       //                 three x-displacements of every (dy, dz, dt) share one
                       //                 spinor load, the x-neighbours come by cross-lane moves
+                      //   VAR_MFMA      FP32 / bfloat16 links only: rpt (1..4) right-hand sides
+                      //                 per thread, the colour transport on the matrix cores
 };
 
-enum StencilVariant { VAR_STANDARD = 0, VAR_TSTREAM = 1, VAR_XLINE = 2 };
+enum StencilVariant { VAR_STANDARD = 0, VAR_TSTREAM = 1, VAR_XLINE = 2, VAR_MFMA = 3 };
 
 constexpr int STREAM_THREADS = 256;  // sites (threads) per block of the t-streaming kernel
 

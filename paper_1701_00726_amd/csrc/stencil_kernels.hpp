@@ -31,6 +31,8 @@
 // compile in parallel.
 #pragma once
 
+#include <type_traits>
+
 #include "stencil.hpp"
 #include "stencil_core.hpp"
 
@@ -775,6 +777,12 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilAr
     }
 }
 
+}  // namespace bri
+
+#include "stencil_mfma.hpp"
+
+namespace bri {
+
 // ------------------------------------------------------------------ launch
 
 template <class LS, int NSPLIT, bool DAG, int KIND>
@@ -854,8 +862,36 @@ inline hipError_t launch_xline_mrhs(const StencilArgs &a, int mode, hipStream_t 
     return hipGetLastError();
 }
 
+template <class LS, int R, bool DAG>
+inline hipError_t launch_mfma(const StencilArgs &a, int mode, hipStream_t st) {
+    const int groups = (a.ncol + R - 1) / R;
+    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(256);
+    switch (mode) {
+    case EPI_PLAIN: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
+    case EPI_NORMS: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
+    case EPI_CG_R: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_CG_R>), grid, block, 0, st, a); break;
+    case EPI_OV: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_OV>), grid, block, 0, st, a); break;
+    case EPI_SIGN: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_SIGN>), grid, block, 0, st, a); break;
+    case EPI_RESID: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_RESID>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <class LS, bool DAG, int KIND>
 inline hipError_t launch_cfg(const StencilArgs &a, int mode, const StencilConfig &cfg, hipStream_t st) {
+    if (cfg.variant == VAR_MFMA) {
+        if constexpr (KIND == KERN_BRI && !std::is_same<LS, LinkF64>::value) {
+            switch (cfg.rpt) {
+            case 1: return launch_mfma<LS, 1, DAG>(a, mode, st);
+            case 2: return launch_mfma<LS, 2, DAG>(a, mode, st);
+            case 3: return launch_mfma<LS, 3, DAG>(a, mode, st);
+            case 4: return launch_mfma<LS, 4, DAG>(a, mode, st);
+            default: return hipErrorInvalidValue;
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     if (cfg.variant == VAR_XLINE) {
         if constexpr (KIND == KERN_BRI) {
             switch (cfg.rpt) {

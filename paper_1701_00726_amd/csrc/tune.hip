@@ -120,6 +120,20 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
                     out.push_back(c);
                 }
             }
+    // the matrix-core transport (FP32 / bfloat16 links), on the tiles and traversals above
+    if (prec != BRI_F64)
+        for (const auto &t : trav)
+            for (int rpt : {1, 2, 3, 4}) {
+                if (rpt > 1 && ncol < 2) continue;
+                StencilConfig c;
+                for (int mu = 0; mu < 4; ++mu) c.tile[mu] = t[mu];
+                c.colz = t[4];
+                c.nsplit = 4;
+                c.rpt = rpt;
+                c.xcd_remap = 1;
+                c.variant = VAR_MFMA;
+                out.push_back(c);
+            }
     // t-streaming kernel (one right-hand side per block row): xyz tiles of 256 sites, t-chunks
     if (ncol <= 4) {
         const int xyz[6][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 8}, {16, 8, 2}, {32, 8, 1}, {16, 16, 1}};
@@ -206,7 +220,7 @@ int bri_set_stencil_cfg(const bri_geom *geom, int prec, int nrhs, const bri_sten
     StencilConfig c = from_public(*cfg);
     int tile[4], nb[4];
     if (plan_tile(g, c, tile, nb) != BRI_OK) return BRI_EINVAL;
-    if (c.variant < VAR_STANDARD || c.variant > VAR_XLINE) return BRI_EINVAL;
+    if (c.variant < VAR_STANDARD || c.variant > VAR_MFMA) return BRI_EINVAL;
     if (c.rpt < 0 || c.rpt > 4 || (c.variant != VAR_TSTREAM && c.rpt == 0 && c.nsplit != 1 && c.nsplit != 2 &&
                                    c.nsplit != 4))
         return BRI_EINVAL;

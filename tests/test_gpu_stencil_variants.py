@@ -287,3 +287,82 @@ def test_xline_mrhs_solver_epilogues(field):
         ref, _, _ = oracle.ov_apply(L, Wo, 1.0, 8, b[r], tol=1e-13)
         assert rel_l2(got[r], ref) < 1e-10
     assert max(st.rel_resid) <= 1e-12
+
+
+# ------------------------------------------------------------ matrix-core variant
+
+@pytest.mark.parametrize("prec,tol", [(bri.F32, 2e-6), (bri.F32_BF16W, 2e-2)])
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_mfma_configs_match_oracle(field, prec, tol, nrhs):
+    """The FP32-MFMA transport: every right-hand-side count per thread (a partial last group
+    with 5 columns), both traversals, against the oracle's 81-term sum."""
+    need_gpu()
+    U, Wo, _ = field
+    W = bri.build_links(L, bri.links_to_device(U), prec)
+    psi = synth.gaussian_source(L, 75 + nrhs, nrhs=nrhs)
+    x = bri.spinor_to_device(psi, prec)
+    ref = oracle.dirac(L, Wo, -0.9, psi)
+    refd = oracle.dirac_adj(L, Wo, -0.9, psi)
+    n = 0
+    try:
+        for (t, cz), rpt in itertools.product([((16, 4, 1, 1), 2), ((0, 0, 0, 0), 0), ((4, 4, 4, 1), 0)],
+                                              (1, 2, 3, 4)):
+            if rpt > 1 and nrhs == 1:
+                continue
+            bri.set_stencil_cfg(L, prec, nrhs, bri.StencilCfg(t[0], t[1], t[2], t[3], cz, 4, rpt, 1, 3))
+            got = bri.spinor_to_host(bri.apply(L, W, prec, -0.9, x))
+            gotd = bri.spinor_to_host(bri.apply_dag(L, W, prec, -0.9, x))
+            for r in range(nrhs):
+                assert rel_l2(got[r], ref[r]) < tol, (rpt, t)
+                assert rel_l2(gotd[r], refd[r]) < tol, (rpt, t)
+            n += 1
+    finally:
+        bri.set_stencil_cfg(L, prec, nrhs, None)
+    assert n >= 3
+
+
+def test_mfma_rejected_for_fp64(field):
+    need_gpu()
+    _, _, W = field
+    x = bri.spinor_to_device(synth.gaussian_source(L, 80))
+    with pytest.raises(bri.BriError):
+        bri.stencil_time(L, W, bri.F64, x, cfg=bri.StencilCfg(16, 4, 1, 1, 2, 4, 1, 1, 3), reps=1)
+
+
+def test_mfma_clover():
+    need_gpu()
+    U = synth.random_links(L, 0.5, 4248)
+    csw = 1.0
+    Wo = oracle.BrillouinKernel(oracle.links(L, U), oracle.clover_field(L, U, csw))
+    W = bri.build_links(L, bri.links_to_device(U), bri.F32, csw=csw)
+    psi = synth.gaussian_source(L, 81, nrhs=3)
+    x = bri.spinor_to_device(psi, bri.F32)
+    try:
+        bri.set_stencil_cfg(L, bri.F32, 3, bri.StencilCfg(16, 4, 1, 1, 2, 4, 2, 1, 3))
+        got = bri.spinor_to_host(bri.apply(L, W, bri.F32, -0.8, x))
+        gotd = bri.spinor_to_host(bri.apply_dag(L, W, bri.F32, -0.8, x))
+    finally:
+        bri.set_stencil_cfg(L, bri.F32, 3, None)
+    for r in range(3):
+        assert rel_l2(got[r], oracle.dirac(L, Wo, -0.8, psi[r])) < 2e-6
+        assert rel_l2(gotd[r], oracle.dirac_adj(L, Wo, -0.8, psi[r])) < 2e-6
+
+
+def test_mfma_in_the_mixed_solver(field):
+    """The mixed-precision batch with the MFMA stencil installed for its FP32 phase (norms and CG
+    residual epilogues on FP32 vectors) against the oracle's eq. (def_over)."""
+    need_gpu()
+    U, Wo, W64 = field
+    W32 = bri.build_links(L, bri.links_to_device(U), bri.F32)
+    b = synth.gaussian_source(L, 82, nrhs=4)
+    try:
+        bri.set_stencil_cfg(L, bri.F32, 4, bri.StencilCfg(16, 4, 1, 1, 2, 4, 4, 1, 3))
+        op = bri.OverlapOp(L, W64, kl_n=8, tol=1e-12, Wlo=W32, inner=bri.F32, nrhs=4)
+        out, st = op.apply(bri.spinor_to_device(b))
+    finally:
+        bri.set_stencil_cfg(L, bri.F32, 4, None)
+    assert st.refine >= 1
+    got = bri.spinor_to_host(out)
+    for r in (0, 3):
+        ref, _, _ = oracle.ov_apply(L, Wo, 1.0, 8, b[r], tol=1e-13)
+        assert rel_l2(got[r], ref) < 1e-10
