@@ -239,6 +239,8 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="autotune the stencil launches before timing")
     ap.add_argument("--survey", action="store_true",
                     help="stencil (tuned, FP64/FP32/BF16-link, 1 and 12 RHS) and overlap timings at 16^4, 24^3x48, 32^3x64")
+    ap.add_argument("--variants", action="store_true",
+                    help="time the stencil kernel variants at 32^3x64 (FP64 / FP32 / bfloat16 links, 1 and 12 RHS)")
     ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
     ap.add_argument("--stencil-rhs", type=int, default=1,
                     help="with --stencil-only: also launch the multi-RHS kernel on this many RHS (FP64 and FP32)")
@@ -399,6 +401,55 @@ def cascade_table(dev):
 
 
 
+# (name, tile, col_z, nsplit, rpt, xcd, variant) of the launches compared by --variants
+VARIANTS_1RHS = (
+    ("standard 16x4 column traversal", (16, 4, 0, 0), 8, 4, 0, 1, 0),
+    ("t-streaming 32x8x1, chunks of 4", (32, 8, 1, 4), 0, 1, 0, 1, 1),
+    ("x-line 32x2", (32, 2, 1, 1), 0, 4, 0, 0, 2),
+    ("matrix cores (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 1, 0, 3),
+)
+VARIANTS_12RHS = (
+    ("standard multi-RHS, 4 per thread", (16, 4, 0, 0), 8, 4, 4, 1, 0),
+    ("x-line multi-RHS, 3 per thread", (32, 2, 1, 1), 4, 4, 3, 1, 2),
+    ("matrix cores, 4 per thread (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 4, 0, 3),
+)
+
+
+def variants(torch, bri, synth, dev):
+    """HIP-event times of the stencil kernel variants on the 32^3x64 workload field (the same
+    random input for every launch of a precision; each variant's output checked against the
+    first), one JSON line per launch."""
+    L = L_BENCH
+    V = int(np.prod(L))
+    U = synth.smeared_links_torch(L, LINK_EPS, LINK_SEED, APE_ALPHA, APE_STEPS, device=dev, chunk=1 << 18)
+    U = U.permute(0, 2, 3, 1).contiguous()
+    bpr = {bri.F64: (8, 8), bri.F32: (4, 4), bri.F32_BF16W: (4, 2)}
+    for prec, pname in ((bri.F64, "f64"), (bri.F32, "f32"), (bri.F32_BF16W, "bf16w")):
+        W = bri.build_links(L, U, prec)
+        for nr, table in ((1, VARIANTS_1RHS), (NSRC, VARIANTS_12RHS)):
+            x = torch.randn((nr, 4, 3, V), dtype=bri.spinor_dtype(prec), device=dev)
+            ref = None
+            for name, t, cz, ns, rpt, xcd, var in table:
+                if var == 3 and prec == bri.F64:
+                    continue
+                cfg = bri.StencilCfg(t[0], t[1], t[2], t[3], cz, ns, rpt, xcd, var)
+                us = bri.stencil_time(L, W, prec, x, cfg=cfg, reps=10 if nr == 1 else 3)
+                bri.set_stencil_cfg(L, prec, nr, cfg)
+                y = bri.apply(L, W, prec, -RHO, x)
+                bri.set_stencil_cfg(L, prec, nr, None)
+                if ref is None:
+                    ref = y
+                diff = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
+                alg = stencil_bytes_per_site(*bpr[prec], nr) * V
+                print(json.dumps({"prec": pname, "nrhs": nr, "variant": name, "us": us,
+                                  "alg_GBps": alg / (us * 1e-6) / 1e9, "frac_hbm": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+                                  "TFLOPs": FLOP_PER_SITE_RHS * V * nr / (us * 1e-6) / 1e12, "rel_diff": diff,
+                                  "config": cfg.as_dict()}), flush=True)
+            del x, ref, y
+        del W
+        torch.cuda.empty_cache()
+
+
 def small_line(torch, bri, synth, dev, timed):
     """The former headline: 16^4 FP64 overlap apply of one Gaussian source and of the 12 point
     sources (links exp(0.5 i A) + 3 APE), HIP-event timed."""
@@ -499,6 +550,9 @@ def main():
         sys.exit(1)
     if args.survey:
         survey(torch, bri, synth)
+        return
+    if args.variants:
+        variants(torch, bri, synth, torch.device("cuda:0"))
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
