@@ -136,6 +136,21 @@ enum bri_kl_kind {
                         constant term                                                         */
 };
 
+/* Stopping rule of the multi-shift solve (ov_params.relax); r_i = b - (A + sigma_i) x_i. */
+enum bri_relax {
+    BRI_RELAX_OFF = 0,   /* every shift stops at |r_i| <= tol |psi|                          */
+    BRI_RELAX_OMEGA = 1, /* shift i stops at |r_i| <= tol |psi| omega_max / omega_i (App. B: the
+                            small shifts carry small weights, so they may stop earlier)       */
+    BRI_RELAX_BOUND = 2  /* tol bounds the result instead: the solve stops once
+                              sum_i omega_i |r_i| / (2 sqrt(sigma_i)) <= tol |psi|,
+                            which bounds the error of sign(H) psi (and of D_ov psi / rho),
+                            because |X (X^dag X + sigma)^-1| = max_s s / (s^2 + sigma)
+                            <= 1 / (2 sqrt(sigma)) over the singular values s of X; shift i
+                            stops by itself once its term is at most tol |psi| / (2n).
+                            ov_apply, ov_sign_apply and ov_solve only (the gradient and the
+                            cascade's levels reject or ignore it)                           */
+};
+
 /*
  * wil_apply     -- out = D_wil(m0) in,  eq. (def_wils):
  *   (D psi)(x) = (4 + m0) psi(x) - (1/2) sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
@@ -155,16 +170,16 @@ int wil_apply_dag(const bri_geom *geom, const void *W, int prec, double m0, cons
 typedef struct {
     int kl_n;       /* Kenney-Laub order n: f_{n,n} = g_{2n+1}, 1..BRI_MAX_SHIFTS */
     double rho;     /* 0 < rho < 2; kernel mass m0 = -rho                        */
-    double tol;     /* per-shift stop: |b - (A + sigma) x_sigma| <= tol |psi|    */
+    double tol;     /* per-shift stop |b - (A + sigma) x_sigma| <= tol |psi|, or
+                       the result bound (relax = BRI_RELAX_BOUND)                */
     int max_iter;   /* multi-shift CG iteration cap                              */
     int inner;      /* bri_prec of the late iterations: BRI_F64 (all FP64), or
                        BRI_F32 / BRI_F32_BF16W (FP32 vectors on Wlo once the base
                        residual has fallen to tol / u_lo |psi|, see ov_apply)   */
     int max_refine; /* unused (0..100 accepted)                                 */
     int kind;       /* bri_kl_kind; BRI_KL_DIAG unless stated                   */
-    int relax;      /* 1: shift i stops at tol * omega_max / omega_i (App. B: the
-                       weights grow with the shift, so small shifts may stop at a
-                       larger residual); 0: every shift at tol                  */
+    int relax;      /* bri_relax; BRI_RELAX_OFF unless stated (ov_apply_grad:
+                       BRI_EINVAL for BRI_RELAX_BOUND)                          */
     int kernel;     /* bri_kernel: X = D_kernel(-rho); BRI_KERNEL_BRILLOUIN unless
                        stated                                                  */
     int recompute;  /* ov_apply_grad only: 0 keeps all 2n shift solutions of one

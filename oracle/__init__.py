@@ -298,20 +298,27 @@ def kl_coeffs(n: int, kind: str = "diag"):
 
 
 def rational_apply(L, W, m0: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000,
-                   kind: str = "diag", relax: bool = False):
+                   kind: str = "diag", relax=False):
     """y = r_n(D^dag D) b = c0 b + sum_i omega_i (D^dag D + sigma_i)^{-1} b, shifts solved one by one.
 
     kind "diag": the coefficients of g_{2n+1} (eq. (KLnn_parfrac)); "upper": those of g_{2n}
-    (Sec. 3.3), c0 = 0.  relax: shift i is solved to tol * max(omega) / omega_i instead of tol
-    (App. B).  Returns (y, iters per shift, true relative residual per shift)."""
+    (Sec. 3.3), c0 = 0.  relax True: shift i is solved to tol * max(omega) / omega_i instead of
+    tol (App. B).  relax "bound": tol bounds the error of D r_n(D^dag D) b instead, through
+    |D (D^dag D + sigma)^{-1}| <= 1 / (2 sqrt(sigma)): shift i is solved to
+    tol 2 sqrt(sigma_i) / (n omega_i), so that sum_i omega_i |r_i| / (2 sqrt(sigma_i)) <= tol |b|.
+    Returns (y, iters per shift, true relative residual per shift)."""
     c0, om, sg = kl_coeffs(n, kind)
     if relax:
-        wmax = max(om)
+        if relax == "bound":
+            tols = [tol * 2.0 * np.sqrt(s) / (n * o) for o, s in zip(om, sg)]
+        else:
+            wmax = max(om)
+            tols = [tol * wmax / o for o in om]
         y = c0 * _c128(b)
         iters = np.zeros(n, dtype=np.int32)
         rel = np.zeros(n, dtype=np.float64)
         for i in range(n):
-            yi, it_i, rel_i = rational_apply_coeffs(L, W, m0, 0.0, [om[i]], [sg[i]], b, tol * wmax / om[i], maxit)
+            yi, it_i, rel_i = rational_apply_coeffs(L, W, m0, 0.0, [om[i]], [sg[i]], b, tols[i], maxit)
             y = y + yi
             iters[i], rel[i] = it_i[0], rel_i[0]
         return y, iters, rel
@@ -336,7 +343,7 @@ def rational_apply_coeffs(L, W, m0: float, c0: float, om, sg, b: np.ndarray, tol
 
 
 def sign_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000,
-               kind: str = "diag", relax: bool = False):
+               kind: str = "diag", relax=False):
     """g_{2n+1}(H) b (or g_{2n}(H) b for kind "upper") with H = gamma5 D(-rho):
     g(H) = H r_n(H^2), H^2 = D^dag D, so g(H) b = gamma5 D r_n(D^dag D) b."""
     y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit, kind, relax)
@@ -344,7 +351,7 @@ def sign_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxi
 
 
 def ov_apply(L, W, rho: float, n: int, b: np.ndarray, tol: float = 1e-13, maxit: int = 10000,
-             kind: str = "diag", relax: bool = False):
+             kind: str = "diag", relax=False):
     """D_ov b = rho (1 + gamma5 g(H)) b = rho (b + D(-rho) r_n(D^dag D) b), eq. (def_over), with
     g = g_{2n+1} (kind "diag") or g_{2n} (kind "upper")."""
     y, iters, rel = rational_apply(L, W, -rho, n, b, tol, maxit, kind, relax)

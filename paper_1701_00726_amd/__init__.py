@@ -31,6 +31,7 @@ LIB_PATH = os.environ.get("BRI_LIB") or os.path.join(_HERE, "libbrillouin.so")
 
 F64, F32, F32_BF16W = 0, 1, 2
 KL_DIAG, KL_UPPER = 0, 1
+RELAX_OFF, RELAX_OMEGA, RELAX_BOUND = 0, 1, 2
 KERNEL_BRILLOUIN, KERNEL_WILSON = 0, 1
 OK, EINVAL, ENOCONV, ENAN, EHIP, ESCRATCH = 0, -1, -2, -3, -4, -5
 MAX_SHIFTS = 32
@@ -410,8 +411,10 @@ class OverlapOp:
         F32_BF16W runs the late multi-shift iterations (once the residual has fallen to
         tol / unit roundoff) on FP32 vectors with the low-precision links `Wlo`,
         accumulating the result in FP64 (max_refine is unused).  kind = KL_UPPER
-        uses the first upper diagonal g_{2n} instead of g_{2n+1}; relax stops shift i
-        at tol * omega_max / omega_i; kernel = KERNEL_WILSON builds the overlap on the
+        uses the first upper diagonal g_{2n} instead of g_{2n+1}; relax = RELAX_OMEGA (or True)
+        stops shift i at tol * omega_max / omega_i, RELAX_BOUND stops once the bound
+        sum_i omega_i |r_i| / (2 sqrt(sigma_i)) on the error of sign(H) psi is at most
+        tol |psi|; kernel = KERNEL_WILSON builds the overlap on the
         Wilson operator (the one-hop slabs of W64) instead of the Brillouin one.  recompute = m > 0
         makes grad solve the shifts m at a time, keeping only those solutions (less memory,
         more solver iterations); 0 keeps all of one multi-shift solve."""
@@ -426,7 +429,7 @@ class OverlapOp:
         if max_refine is None:
             max_refine = 0
         self.params = _OvParams(int(kl_n), float(rho), float(tol), int(max_iter), int(inner), int(max_refine),
-                                int(kind), 1 if relax else 0, int(kernel), int(recompute))
+                                int(kind), int(relax), int(kernel), int(recompute))
         self.nrhs = int(nrhs)
         nbytes = ctypes.c_size_t(0)
         _check(

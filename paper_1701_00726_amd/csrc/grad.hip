@@ -563,7 +563,7 @@ int ov_apply_grad(const bri_geom *geom, const void *U, const void *W64, const vo
     if (rc != BRI_OK) return rc;
     if (!prm || !work_bytes || g.csw != 0.0) return BRI_EINVAL;
     const int n = prm->kl_n;
-    if (!params_ok(prm) || g.V % 64) return BRI_EINVAL;
+    if (!params_ok(prm) || prm->relax == 2 || g.V % 64) return BRI_EINVAL;  // (the bound is the apply's)
     GradPlan pl;
     rc = plan_grad(g, prm, pl);
     if (rc != BRI_OK) return rc;

@@ -202,6 +202,9 @@ __global__ void ms_alpha_kernel(ColState *states, const double *partial, int nbl
 // beta, beta^sigma, convergence after r -= alpha (A + sigma0) p (partials: |r|^2).  Thread
 // i < nshift updates shift i; the column scalars are written by thread 0 after a block-wide
 // vote on whether any shift is still active (every read of them precedes that barrier).
+// Stopping: shift i by itself once |r_i| <= tol_i |b|; with the result bound (joint), shift i
+// once ebw_i |r_i| <= tol |b| / (2 nshift), and every shift once sum_i ebw_i |r_i| <= tol |b|
+// (a stopped shift counts with its residual when it stopped).
 __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk) {
     ColState *st = states + blockIdx.x;
     if (st->done) return;
@@ -210,8 +213,10 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
     const double beta = rr_new / st->rr;
     const int it = st->iter + 1;
     const int i = threadIdx.x;
+    const int ns = st->nshift;
     int still = 0;
-    if (i < st->nshift) {
+    double res2 = 0.0, term = 0.0;  // |r_i|^2 of a shift still running; its bound term
+    if (i < ns) {
         if (bad) {
             st->active[i] = 0;
             st->upd_x[i] = 0;
@@ -221,14 +226,32 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
             st->beta_s[i] = beta * ratio * ratio;
             st->zeta_old[i] = z;
             st->zeta[i] = zn;
-            const double res2 = zn * zn * rr_new;
-            if (res2 <= st->tol2 * st->tolf2[i]) {
+            res2 = zn * zn * rr_new;
+            const double e2 = st->ebw[i] * st->ebw[i] * res2;
+            const bool stop = st->joint ? e2 * (4.0 * ns * ns) <= st->tol2 : res2 <= st->tol2 * st->tolf2[i];
+            if (stop) {
                 st->active[i] = 0;
                 st->conv_iter[i] = it;
                 st->conv_res[i] = sqrt(res2 / st->bnorm2);
             } else {
                 still = 1;
             }
+            term = sqrt(e2);
+        } else {
+            term = st->ebw[i] * st->conv_res[i] * sqrt(st->bnorm2);
+        }
+    }
+    // the bound over all shifts (they sit in the first wave); fixed-order sum
+    static_assert(MAXS <= 64, "one wave holds every shift");
+    if (st->joint && !bad && i < 64) {
+        double tot = term;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
+        if (still && tot * tot <= st->tol2) {
+            st->active[i] = 0;
+            st->conv_iter[i] = it;
+            st->conv_res[i] = sqrt(res2 / st->bnorm2);
+            still = 0;
         }
     }
     const int any = __syncthreads_or(still);
@@ -395,8 +418,9 @@ void kl_upper_coeffs(int n, double *omega, double *sigma) {
 
 // The rational of an overlap apply: c0, omega, sigma of the diagonal or first upper diagonal
 // Kenney-Laub function, and the per-shift factor on the stopping tolerance: 1, or with
-// relaxation omega_max / omega_i (App. B: the weights grow with the shift, so the small shifts,
-// whose terms carry small weights, may stop at a larger residual).
+// relaxation 1 omega_max / omega_i (App. B: the weights grow with the shift, so the small
+// shifts, whose terms carry small weights, may stop at a larger residual).  Relaxation 2 (the
+// result bound) stops on the weighted sum instead; plan_shifts sets its weights.
 void shift_coeffs(const ov_params *prm, double *c0, double *omega, double *sigma, double *tolf) {
     const int n = prm->kl_n;
     if (prm->kind == BRI_KL_UPPER) {
@@ -407,7 +431,7 @@ void shift_coeffs(const ov_params *prm, double *c0, double *omega, double *sigma
     }
     double wmax = 0.0;
     for (int i = 0; i < n; ++i) wmax = omega[i] > wmax ? omega[i] : wmax;
-    for (int i = 0; i < n; ++i) tolf[i] = prm->relax ? wmax / omega[i] : 1.0;
+    for (int i = 0; i < n; ++i) tolf[i] = prm->relax == 1 ? wmax / omega[i] : 1.0;
 }
 
 bool params_ok(const ov_params *prm) {
@@ -419,7 +443,7 @@ bool params_ok(const ov_params *prm) {
     if (prm->kind != BRI_KL_DIAG && prm->kind != BRI_KL_UPPER) return false;
     if (prm->kernel != BRI_KERNEL_BRILLOUIN && prm->kernel != BRI_KERNEL_WILSON) return false;
     if (prm->recompute < 0 || prm->recompute > MAXS) return false;
-    return prm->relax == 0 || prm->relax == 1;
+    return prm->relax >= 0 && prm->relax <= 2;
 }
 
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -458,6 +482,7 @@ struct MsSolve {
     std::vector<double> omega;  // [nshift]
     std::vector<double> sigma;  // [ncol][nshift], ascending per column
     std::vector<double> tolf;   // [nshift] factor on tol per shift (empty: 1)
+    std::vector<double> ebw;    // [nshift] result-bound weights (empty: stop shift by shift)
     double tol = 1e-12;
     int max_iter = 1000;
     // workspace pieces
@@ -618,11 +643,13 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         cs.nshift = s.nshift;
         cs.c0 = s.c0;
         cs.sigma0 = s.sigma[(size_t)c * s.nshift];
+        cs.joint = s.ebw.empty() ? 0 : 1;
         for (int i = 0; i < s.nshift; ++i) {
             cs.omega[i] = s.omega[i];
             cs.delta[i] = s.sigma[(size_t)c * s.nshift + i] - cs.sigma0;
             const double f = s.tolf.empty() ? 1.0 : s.tolf[i];
             cs.tolf2[i] = f * f;
+            cs.ebw[i] = s.ebw.empty() ? 0.0 : s.ebw[i];
         }
     }
     BRI_HIP_CHECK(hipMemcpyAsync(s.st, h.data(), sizeof(ColState) * s.ncol, hipMemcpyHostToDevice, strm));
@@ -820,6 +847,9 @@ static void plan_shifts(MsSolve &m, const Geom &g, const ov_params *prm, int nco
     m.store_x = store_x;
     m.omega.assign(om, om + n);
     m.tolf.assign(tf, tf + n);
+    m.ebw.clear();
+    if (prm->relax == 2)  // |X (X^dag X + sigma)^-1| <= max_s s / (s^2 + sigma) = 1 / (2 sqrt(sigma))
+        for (int i = 0; i < n; ++i) m.ebw.push_back(om[i] / (2.0 * sqrt(sg[i])));
     m.sigma.resize((size_t)ncol * n);
     for (int c = 0; c < ncol; ++c)
         for (int i = 0; i < n; ++i) m.sigma[(size_t)c * n + i] = sg[i];

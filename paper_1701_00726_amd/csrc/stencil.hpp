@@ -19,6 +19,8 @@ struct ColState {
     double c0;
     double delta[MAXS], omega[MAXS];
     double tolf2[MAXS];     // squared per-shift factor on the stopping tolerance
+    int joint;              // stop on the result bound sum_i ebw_i |r_i| <= tol |b| (else per shift)
+    double ebw[MAXS];       // omega_i / (2 sqrt(sigma_i)): weight of |r_i| in that bound
     double zeta[MAXS], zeta_old[MAXS], zeta_new[MAXS];
     double alpha_s[MAXS], beta_s[MAXS];
     int active[MAXS];       // shift still iterating

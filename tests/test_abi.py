@@ -245,12 +245,21 @@ def test_kind_and_relax_validated():
     g = bri._geom((8, 8, 8, 8))
     nb = ctypes.c_size_t(0)
     for kind, relax, want in ((1, 0, bri.OK), (0, 1, bri.OK), (1, 1, bri.OK), (2, 0, bri.EINVAL),
-                              (-1, 0, bri.EINVAL), (0, 2, bri.EINVAL)):
+                              (-1, 0, bri.EINVAL), (0, 3, bri.EINVAL), (0, -1, bri.EINVAL)):
         prm = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0, kind, relax)
         assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb),
                             None, None) == want, (kind, relax)
         assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None,
                                  None, ctypes.byref(nb), None, None) == want, (kind, relax)
+    # the result bound: the applies accept it, the gradient does not
+    for kind in (0, 1):
+        prm = bri._OvParams(8, 1.0, 1e-10, 100, 0, 0, kind, bri.RELAX_BOUND)
+        assert lib.ov_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None, ctypes.byref(nb),
+                            None, None) == bri.OK
+        assert lib.ov_sign_apply(ctypes.byref(g), None, None, ctypes.byref(prm), None, None, 1, None,
+                                 ctypes.byref(nb), None, None) == bri.OK
+        assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None,
+                                 None, ctypes.byref(nb), None, None) == bri.EINVAL
     om = (ctypes.c_double * 1)()
     assert lib.bri_kl_upper_coeffs(0, om, om) == bri.EINVAL
     assert lib.bri_kl_upper_coeffs(bri.MAX_SHIFTS + 1, om, om) == bri.EINVAL

@@ -6,7 +6,12 @@
   * relaxed per-shift stopping (ov_params.relax): every shift meets tol * omega_max / omega_i,
     the multi-shift stops no later than the strict one, and the result stays within the error
     bound its residuals imply, at 4^4 (against the dense exact rational) and at 16^4 (against
-    the strict apply).
+    the strict apply);
+  * the result bound (relax = RELAX_BOUND): the reported residuals satisfy
+    sum_i omega_i |r_i| / (2 sqrt(sigma_i)) <= tol, and the sign function lies within tol |b| of
+    the dense exact rational at 4^4 (FP64 single source and batch; the FP32 low-precision phase
+    within 2 tol |b|), and the 16^4 apply within rho tol |b| of the strict one, in fewer
+    iterations.
 """
 
 import numpy as np
@@ -122,3 +127,82 @@ def test_relaxed_stopping_bench_lattice():
     bound = 3.0 * sum(o * (r1 + r2) / s for o, r1, r2, s in zip(om, str_.rel_resid, sts.rel_resid, sg))
     diff = (torch.linalg.vector_norm(yr - ys) / torch.linalg.vector_norm(b)).item()
     assert diff <= bound, (diff, bound)
+
+
+def _bound_weights(om, sg):
+    return [o / (2.0 * np.sqrt(s)) for o, s in zip(om, sg)]
+
+
+@pytest.mark.parametrize("kind", [bri.KL_DIAG, bri.KL_UPPER])
+def test_result_bound_stopping_4_4(kind):
+    need_gpu()
+    U, Wo = field(L4, "cfg1")
+    n, tol = 8, 1e-9
+    kname = "diag" if kind == bri.KL_DIAG else "upper"
+    c0, om, sg = oracle.kl_coeffs(n, kname)
+    w = _bound_weights(om, sg)
+    b = np.concatenate([synth.gaussian_source(L4, synth.SOURCE_SEED_BASE + 23), synth.point_sources_12(L4)[[0, 7]]])
+    d = odense.DenseOverlap(oracle.dense_matrix(L4, Wo, -1.0), 256, 1.0)
+
+    def exact(r):
+        return d.apply_fn(lambda lam: lam * (c0 + sum(o / (lam * lam + s) for o, s in zip(om, sg))),
+                          b[r].ravel()).reshape(b[r].shape)
+
+    refs = [exact(r) for r in range(3)]
+    bd = bri.spinor_to_device(b)
+    op = _op(L4, U, n, tol=tol, kind=kind, relax=bri.RELAX_BOUND)
+    strict = _op(L4, U, n, tol=tol, kind=kind)
+    for r in range(3):
+        y, st = op.sign(bd[r:r + 1].contiguous())
+        assert sum(wi * st.rel_resid[i] for i, wi in enumerate(w)) <= tol * (1 + 1e-9), st.rel_resid
+        err = np.linalg.norm(bri.spinor_to_host(y)[0] - refs[r]) / np.linalg.norm(b[r])
+        assert err <= tol, (r, err)
+        _, sts = strict.sign(bd[r:r + 1].contiguous())
+        assert st.iters <= sts.iters
+    opb = _op(L4, U, n, tol=tol, kind=kind, relax=bri.RELAX_BOUND, nrhs=3)
+    yb, _ = opb.sign(bd)
+    yb = bri.spinor_to_host(yb)
+    for r in range(3):
+        assert np.linalg.norm(yb[r] - refs[r]) / np.linalg.norm(b[r]) <= tol, r
+    Ud = bri.links_to_device(U)
+    W = bri.build_links(L4, Ud, bri.F64)
+    W32 = bri.build_links(L4, Ud, bri.F32)
+    opm = bri.OverlapOp(L4, W, kl_n=n, rho=1.0, tol=tol, max_iter=3000, Wlo=W32, inner=bri.F32, kind=kind,
+                        relax=bri.RELAX_BOUND, nrhs=3)
+    ym, stm = opm.sign(bd)
+    ym = bri.spinor_to_host(ym)
+    for r in range(3):
+        err = np.linalg.norm(ym[r] - refs[r]) / np.linalg.norm(b[r])
+        assert err <= 2 * tol, (r, err, stm.refine)
+
+
+def test_result_bound_bench_lattice():
+    """16^4 smeared field, [16/16]: the result bound at 1e-11 against the strict apply at 1e-13,
+    in FP64 and with the FP32 low-precision phase."""
+    need_gpu()
+    L = (16, 16, 16, 16)
+    U, _ = field(L, "cfg2")
+    b = bri.spinor_to_device(synth.gaussian_source(L, synth.SOURCE_SEED_BASE + 2))
+    tol = 1e-11
+    ref, st_ref = _op(L, U, 16, tol=1e-13).apply(b)
+    _, st12 = _op(L, U, 16, tol=1e-12).apply(b)
+    yb, stb = _op(L, U, 16, tol=tol, relax=bri.RELAX_BOUND).apply(b)
+    _, om, sg = oracle.kl_coeffs(16)
+    w = _bound_weights(om, sg)
+    # the strict reference errs by at most sum_i w_i 1e-13 itself (rho = 1, |b| = 1)
+    slack = sum(w) * 1e-13
+    diff = (torch.linalg.vector_norm(yb - ref) / torch.linalg.vector_norm(b)).item()
+    print(f"bound 1e-11: {stb.iters} iterations (strict 1e-12: {st12.iters}), difference {diff:.1e}", flush=True)
+    assert sum(wi * stb.rel_resid[i] for i, wi in enumerate(w)) <= tol * (1 + 1e-9)
+    assert diff <= tol + slack, diff
+    assert stb.iters < st12.iters
+    Ud = bri.links_to_device(U)
+    W = bri.build_links(L, Ud, bri.F64)
+    W32 = bri.build_links(L, Ud, bri.F32)
+    opm = bri.OverlapOp(L, W, kl_n=16, rho=1.0, tol=tol, max_iter=3000, Wlo=W32, inner=bri.F32,
+                        relax=bri.RELAX_BOUND)
+    ym, stm = opm.apply(b)
+    diffm = (torch.linalg.vector_norm(ym - ref) / torch.linalg.vector_norm(b)).item()
+    print(f"bound 1e-11, FP32 phase: {stm.iters} iterations ({stm.refine} in FP32), difference {diffm:.1e}",
+          flush=True)
+    assert diffm <= 2 * tol + slack, diffm

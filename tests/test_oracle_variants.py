@@ -7,7 +7,12 @@
   * the overlap force with g_{2n} against five-point differences of that dense operator;
   * relaxed per-shift stopping (tol * omega_max / omega_i): every shift meets its own tolerance,
     the small shifts stop earlier, and the result stays within the error bound that the
-    residuals imply (sum_i omega_i |r_i| / sigma_i, since X^dag X >= 0).
+    residuals imply (sum_i omega_i |r_i| / sigma_i, since X^dag X >= 0);
+  * the result bound: |X (X^dag X + sigma)^{-1}| equals the largest s / (s^2 + sigma) over the
+    singular values s of X, at most 1 / (2 sqrt(sigma)) and nearly that when sqrt(sigma) lies
+    inside the singular spectrum (dense SVD); stopping the shifts so that
+    sum_i omega_i |r_i| / (2 sqrt(sigma_i)) <= tol |b| keeps the sign function within tol |b| of
+    the exact rational (dense eigendecomposition).
 """
 
 import numpy as np
@@ -107,3 +112,36 @@ def test_relaxed_shift_tolerances(small, kind):
     err = np.linalg.norm(y_relax.ravel() - exact)
     assert err <= bound
     assert np.linalg.norm(y_strict.ravel() - exact) <= sum(o * tol / s for o, s in zip(om, sg)) * np.linalg.norm(b)
+
+
+def test_result_bound_constant(small):
+    W, d, b = small
+    D = d.D
+    sv = np.linalg.svd(D, compute_uv=False)
+    A = D.conj().T @ D
+    eye = np.eye(D.shape[0])
+    _, _, sg = oracle.kl_coeffs(6)
+    inside = 0
+    for sig in sg:
+        nrm = np.linalg.norm(D @ np.linalg.inv(A + sig * eye), 2)
+        assert abs(nrm - np.max(sv / (sv * sv + sig))) <= 1e-10 * nrm
+        assert nrm <= (1 + 1e-10) / (2.0 * np.sqrt(sig))
+        if sv.min() <= np.sqrt(sig) <= sv.max():
+            inside += 1
+            assert nrm >= 0.95 / (2.0 * np.sqrt(sig)), (sig, nrm)
+    assert inside >= 2
+
+
+@pytest.mark.parametrize("kind", ["diag", "upper"])
+def test_result_bound_stopping(small, kind):
+    W, d, b = small
+    n, tol = 6, 1e-8
+    c0, om, sg = oracle.kl_coeffs(n, kind)
+    got, it_b, rel = oracle.sign_apply(L_SMALL, W, 1.0, n, b, tol=tol, kind=kind, relax="bound")
+    w = [o / (2.0 * np.sqrt(s)) for o, s in zip(om, sg)]
+    assert sum(wi * r for wi, r in zip(w, rel)) <= tol * (1 + 1e-9)
+    exact = d.apply_fn(lambda lam: lam * (c0 + sum(o / (lam * lam + s) for o, s in zip(om, sg))), b.ravel())
+    err = np.linalg.norm(got.ravel() - exact)
+    assert err <= tol * np.linalg.norm(b)
+    # the bound is not slack by orders of magnitude: the error is within 1000x of it
+    assert err >= 1e-3 * tol * np.linalg.norm(b)
