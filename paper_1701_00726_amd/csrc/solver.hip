@@ -56,6 +56,7 @@ namespace bri {
 
 constexpr int RED_THREADS = 256;
 constexpr int CHECK_EVERY = 8;
+constexpr double LONG_ITER_SEC = 2e-3;  // iterations this long are polled one by one before the switch
 constexpr int INIT_BLOCKS = 256;  // vector-kernel blocks per column
 
 // --------------------------------------------------------------- reductions
@@ -767,9 +768,15 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
     }
     int it = 0, it_switch = 0;
     rs.lo_iters = 0;
+    double sec_per_iter = 0.0;  // host wall time per iteration of the last polling block
     for (;;) {
-        // shorter polling blocks while the switch to the low-precision phase is pending
-        const int blk = (phase == 0 && has_lo) ? CHECK_EVERY / 2 : CHECK_EVERY;
+        // shorter polling blocks while the switch to the low-precision phase is pending: one
+        // iteration per poll once iterations are long enough that a host round trip (tens of us)
+        // costs little against them, so the switch comes at the first iteration that allows it
+        int blk = CHECK_EVERY;
+        if (phase == 0 && has_lo) blk = sec_per_iter > LONG_ITER_SEC ? 1 : CHECK_EVERY / 2;
+        const auto tb = std::chrono::steady_clock::now();
+        const int it_before = it;
         const Phase &ph = phases[phase];
         const bool lo = phase == 1;
         if (use_graph && it + blk <= s.max_iter) {
@@ -793,6 +800,9 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         }
         BRI_HIP_CHECK(hipMemcpyAsync(hflag, s.alldone, sizeof(int), hipMemcpyDeviceToHost, strm));
         BRI_HIP_CHECK(hipStreamSynchronize(strm));
+        if (it > it_before)
+            sec_per_iter = std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count() /
+                           (it - it_before);
         if (*hflag == 1 || it >= s.max_iter) break;
         if (*hflag == 2 && phase == 0 && has_lo) {
             // iterations done so far (the last of a polling block may find a column done)

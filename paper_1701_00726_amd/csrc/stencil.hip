@@ -145,18 +145,24 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.rpt = (prec == BRI_F64 || ncol <= 8) ? 2 : 3;
         else
             c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
-        // low-precision batches on large lattices whose x-lines fit a wave: the x-line kernel with
-        // three right-hand sides per thread (12 RHS at 32^3x64: 19.9 / 18.7 ms for FP32 / bfloat16
-        // links against 24.7 / 22.7 ms; in FP64 it only ties, its registers limit it to one wave
-        // per SIMD)
-        if (kind == KERN_BRI && prec != BRI_F64 && ncol >= 3 && xline_fits(g)) {
-            c.variant = VAR_XLINE;
+        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 16
+        // z-slices.  12 RHS at 32^3x64 measured 37.6 ms (FP64, R = 2) and 19.1 ms (FP32, R = 3)
+        // against 45.2 / 24.9 ms for 16 x 4 tiles with R = 4, and against 47.4 / 19.9 ms for the
+        // x-line kernel (its registers leave one FP64 wave per SIMD); bfloat16 links keep the
+        // x-line kernel with R = 3 (18.7 against 22.8 ms).
+        if (kind == KERN_BRI && ncol >= 3 && xline_fits(g)) {
             c.tile[0] = g.L[0];
             c.tile[1] = 64 / g.L[0];
             c.tile[2] = c.tile[3] = 1;
-            c.colz = g.L[2] % 4 == 0 ? 4 : 0;
-            c.rpt = 3;
             c.xcd_remap = 1;
+            if (prec == BRI_F32_BF16W) {
+                c.variant = VAR_XLINE;
+                c.colz = g.L[2] % 4 == 0 ? 4 : 0;
+                c.rpt = 3;
+            } else {
+                c.colz = g.L[2] % 16 == 0 ? 16 : (g.L[2] % 8 == 0 ? 8 : 0);
+                c.rpt = prec == BRI_F64 ? 2 : 3;
+            }
         }
     } else {
         // four waves split each tile's directions: fills the 1024 SIMDs on small lattices, and on
