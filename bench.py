@@ -528,6 +528,25 @@ def extras_16(torch, bri, synth, dev, timed, stencil_reps):
     ex["massive_solve_fp64_1src"] = {"mass": MASS, "outer_tol": OUTER_TOL, "outer_iters": sts.iters,
                                      "ov_applies": sts.applies, "ms_per_solve": ms_s,
                                      "ms_per_ov_apply": ms_s / sts.applies, "true_rel_resid": sts.rel_resid}
+    # the low-precision phase and the result bound on this field (one Gaussian source; 12 point sources)
+    W32 = bri.build_links(L, U, bri.F32)
+    b12 = bri.spinor_to_device(synth.point_sources_12(L), bri.F64, dev)
+    for name, kw in (("result_bound_fp64", dict(tol=RESULT_TOL, relax=bri.RELAX_BOUND)),
+                     ("mixed_f32", dict(tol=CG_TOL, Wlo=W32, inner=bri.F32)),
+                     ("mixed_f32_result_bound", dict(tol=RESULT_TOL, relax=bri.RELAX_BOUND, Wlo=W32, inner=bri.F32))):
+        row = {}
+        for nr, src in ((1, b), (12, b12)):
+            opx = bri.OverlapOp(L, W, kl_n=KL_N, rho=RHO, max_iter=5000, nrhs=nr, **kw)
+            ox, stx = opx.apply(src)
+            msx = timed(lambda: opx.apply(src), 3)
+            row[f"{nr}src"] = {"applies_per_s": nr * 1e3 / msx, "cg_iterations": stx.iters,
+                               "low_precision_iterations": stx.refine}
+            if nr == 1:
+                row["rel_diff_vs_fp64_1e-12"] = float(torch.linalg.vector_norm(ox - ref64) /
+                                                      torch.linalg.vector_norm(ref64))
+            del opx, ox
+        ex[name] = row
+    del W32, b12
     ex["cascaded_16x16x16x32"] = cascade_table(dev)
     ex["kernel_quality_16x16x16x32"] = quality_table(dev)
     return ex
