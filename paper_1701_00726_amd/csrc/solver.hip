@@ -91,6 +91,23 @@ __device__ double2 block_sum2(const double *partial, int n) {
 
 // ------------------------------------------------------------------ kernels
 
+// Deferred shift updates.  Within a window of at most WIN iterations the shifted directions and
+// y are carried as linear combinations of the vectors at the window's start and the residuals
+// r_{k0+1}, ..., r_{k0+m} the window stores (slots 1..m):
+//   p^sigma = a_sigma P_sigma + sum_j c[sigma][j] R_j,    y = y_0 + sum_sigma e_sigma P_sigma + sum_j f_j R_j,
+// with P_sigma = p^sigma_{k0} (P_0 = p_{k0}, the base direction) and y_0 = y_{k0}.  An iteration
+// then writes only p and one residual slot; the scalar recurrences of the multi-shift update
+// (x^sigma += alpha^sigma p^sigma, p^sigma = zeta r + beta^sigma p^sigma) act on the coefficients,
+// and a fold materialises y and the p^sigma once per window.  The sums are those of the
+// per-iteration updates, taken in another order.
+constexpr int WIN = 4;
+struct WinState {
+    int wn;                   // residuals stored in the window
+    double a[MAXS], e[MAXS];  // coefficients of P_sigma in p^sigma and in y
+    double c[MAXS][WIN + 1];  // c[sigma][j]: of R_j in p^sigma (j = 1..WIN)
+    double f[WIN + 1];        // f[j]: of R_j in y
+};
+
 // column c = blockIdx.y.  r = p = b, p_sigma = b, and y = c0 b (or x_sigma = 0);
 // partial |b|^2.  B is the input type (double2 or float2), C the solver type.
 template <typename B, typename C>
@@ -206,7 +223,7 @@ __global__ void ms_alpha_kernel(ColState *states, const double *partial, int nbl
 // Stopping: shift i by itself once |r_i| <= tol_i |b|; with the result bound (joint), shift i
 // once ebw_i |r_i| <= tol |b| / (2 nshift), and every shift once sum_i ebw_i |r_i| <= tol |b|
 // (a stopped shift counts with its residual when it stopped).
-__global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk) {
+__global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk, WinState *ws) {
     ColState *st = states + blockIdx.x;
     if (st->done) return;
     const double rr_new = block_sum2(partial + 2 * (size_t)blockIdx.x * nblk, nblk).x;
@@ -255,9 +272,42 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
             still = 0;
         }
     }
+    // deferred updates: this iteration's y steps and next directions act on the coefficients
+    // (wave 0 holds every shift, so the reads of c precede its writes in program order)
+    bool overflow = false;
+    if (ws && !bad && i < 64) {
+        WinState *w = ws + blockIdx.x;
+        const int m = w->wn;
+        overflow = m >= WIN;  // the host folds every WIN iterations; never reached
+        if (!overflow) {
+            // y += sum_sigma omega alpha^sigma p^sigma (the shifts that took their step)
+            const double wgt = (i < ns && st->upd_x[i]) ? st->omega[i] * st->alpha_s[i] : 0.0;
+            if (i < ns) w->e[i] += wgt * w->a[i];
+            for (int j = 1; j <= m; ++j) {
+                double v = i < ns ? wgt * w->c[i][j] : 0.0;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+                if (i == 0) w->f[j] += v;
+            }
+            // p^sigma <- zeta_{k+1} r_{k+1} + beta^sigma p^sigma for the shifts still running;
+            // the base direction p <- r_{k+1} + beta p always
+            if (i < ns && (i == 0 || st->active[i])) {
+                const double bs = i == 0 ? beta : st->beta_s[i];
+                w->a[i] *= bs;
+                for (int j = 1; j <= m; ++j) w->c[i][j] *= bs;
+                w->c[i][m + 1] = i == 0 ? 1.0 : st->zeta[i];
+            }
+            if (i == 0) w->wn = m + 1;
+        }
+    }
     const int any = __syncthreads_or(still);
     if (i == 0) {
         st->iter = it;
+        if (overflow) {
+            st->status = BRI_EINVAL;
+            st->done = 1;
+            return;
+        }
         if (bad) {
             st->status = BRI_ENAN;
             st->done = 1;
@@ -340,6 +390,125 @@ __global__ __launch_bounds__(256) void ms_update_kernel(const ColState *__restri
 static inline int update_blocks(size_t n) {
     const size_t b = (n + 511) / 512;
     return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+// Deferred updates, per iteration: R_m = r_{k+1} (m = the window count the beta kernel just
+// advanced) and p = r_{k+1} + beta p.  Column c = blockIdx.y; slot j of column c at
+// R + ((j - 1) ncol + c) n.
+template <typename C>
+__global__ __launch_bounds__(256) void ms_pupdate_kernel(const ColState *__restrict__ states,
+                                                         const WinState *__restrict__ ws, size_t n, int ncol,
+                                                         const C *__restrict__ r, C *__restrict__ p,
+                                                         C *__restrict__ R) {
+    const int col = blockIdx.y;
+    const ColState *st = states + col;
+    if (st->done == 1) return;
+    const int m = ws[col].wn;
+    if (m < 1 || m > WIN) return;
+    const double beta = st->beta;
+    const size_t off = (size_t)col * n;
+    C *__restrict__ Rm = R + ((size_t)(m - 1) * ncol + col) * n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const C ri = r[off + i];
+        C pi = p[off + i];
+        Rm[i] = ri;
+        pi.x = ri.x + beta * pi.x;
+        pi.y = ri.y + beta * pi.y;
+        p[off + i] = pi;
+    }
+}
+
+// The fold: y += e_0 P_0 + sum_{sigma>=1} e_sigma P_sigma + sum_j f_j R_j, and for a running column
+// P_sigma <- a_sigma P_sigma + sum_j c[sigma][j] R_j for the shifts still active and P_0 <- p, all
+// in FP64 arithmetic.  CI is the type of the window's vectors, CO that of the P written (FP32
+// at the switch to the low-precision phase, where Pout / P0out are the FP32 vectors).
+template <typename CI, typename CO>
+__global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict__ states,
+                                                      const WinState *__restrict__ ws, size_t n, int ncol,
+                                                      const CI *__restrict__ R, const CI *__restrict__ p,
+                                                      const CI *P0in, CO *P0out, const CI *Pin, CO *Pout,
+                                                      double2 *__restrict__ y, int convert) {
+    const int col = blockIdx.y;
+    const ColState *st = states + col;
+    const WinState *w = ws + col;
+    const int m = w->wn < WIN ? w->wn : WIN;
+    if (m == 0 && !convert) return;  // no iteration since the last fold: nothing changed
+    const int ns = st->nshift;
+    const bool running = st->done == 0;
+    const size_t off = (size_t)col * n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double2 rj[WIN];
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) {
+            if (j < m) {
+                const CI v = R[((size_t)j * ncol + col) * n + i];
+                rj[j] = make_double2(v.x, v.y);
+            } else {
+                rj[j] = make_double2(0.0, 0.0);
+            }
+        }
+        double2 yv = y[off + i];
+        // a direction is read only where it enters: a shift without a step in this window (e = 0)
+        // that no longer runs may hold a stale or never-written vector
+        if (w->e[0] != 0.0) {
+            const CI v = P0in[off + i];
+            yv.x += w->e[0] * v.x;
+            yv.y += w->e[0] * v.y;
+        }
+        for (int k = 1; k < ns; ++k) {
+            const double e = w->e[k];
+            const bool adv = running && st->active[k];
+            if (e == 0.0 && !adv) continue;
+            const size_t pidx = ((size_t)(k - 1) * ncol + col) * n + i;
+            const CI v = Pin[pidx];
+            yv.x += e * v.x;
+            yv.y += e * v.y;
+            if (adv) {
+                const double a = w->a[k];
+                double ux = a * v.x, uy = a * v.y;
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) {
+                    if (j < m) {
+                        const double c = w->c[k][j + 1];
+                        ux += c * rj[j].x;
+                        uy += c * rj[j].y;
+                    }
+                }
+                CO u;
+                u.x = ux;
+                u.y = uy;
+                Pout[pidx] = u;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) {
+            if (j < m) {
+                yv.x += w->f[j + 1] * rj[j].x;
+                yv.y += w->f[j + 1] * rj[j].y;
+            }
+        }
+        y[off + i] = yv;
+        if (running) {
+            const CI v = p[off + i];
+            CO u;
+            u.x = v.x;
+            u.y = v.y;
+            P0out[off + i] = u;
+        }
+    }
+}
+
+// empties every column's window after a fold (one block per column)
+__global__ void ms_window_reset_kernel(WinState *ws) {
+    WinState *w = ws + blockIdx.x;
+    const int i = threadIdx.x;
+    if (i < MAXS) {
+        w->a[i] = 1.0;
+        w->e[i] = 0.0;
+        for (int j = 0; j <= WIN; ++j) w->c[i][j] = 0.0;
+    }
+    if (i <= WIN) w->f[i] = 0.0;
+    if (i == 0) w->wn = 0;
 }
 
 // done 2 -> 1 for every column; *alldone = 1 once every column is done, else 2 when sw2 > 0 and
@@ -492,6 +661,11 @@ struct MsSolve {
     int *alldone = nullptr;
     void *r = nullptr, *p = nullptr, *t = nullptr, *y = nullptr, *x = nullptr, *ps = nullptr;
     int nblk_st = 0;
+    // deferred shift updates (y accumulation only): window state, the base direction at the
+    // window's start and the stored residuals, per phase
+    bool windowed = false;
+    WinState *ws = nullptr;
+    void *P0 = nullptr, *R = nullptr, *P0_lo = nullptr, *R_lo = nullptr;
 
 
     void carve(Arena &ar) {
@@ -509,12 +683,22 @@ struct MsSolve {
         else
             y = ar.take(vb);
         if (nshift > 1) ps = ar.take(vb * (nshift - 1));
+        windowed = windowed && !store_x;
+        if (windowed) {
+            ws = (WinState *)ar.take(sizeof(WinState) * ncol);
+            P0 = ar.take(vb);
+            R = ar.take(vb * WIN);
+        }
         if (prec_lo >= 0) {
             const size_t vl = (size_t)12 * g.V * sizeof(float2) * ncol;
             r_lo = ar.take(vl);
             p_lo = ar.take(vl);
             t_lo = ar.take(vl);
             if (nshift > 1) ps_lo = ar.take(vl * (nshift - 1));
+            if (windowed) {
+                P0_lo = ar.take(vl);
+                R_lo = ar.take(vl * WIN);
+            }
         }
     }
 };
@@ -661,6 +845,10 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                        s.nshift, s.c0, s.partial);
     hipLaunchKernelGGL(ms_scalar_init_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, INIT_BLOCKS,
                        s.tol);
+    if (s.windowed) {
+        BRI_HIP_CHECK(hipMemcpyAsync(s.P0, s.p, n * s.ncol * sizeof(double2), hipMemcpyDeviceToDevice, strm));
+        hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, strm, s.ws);
+    }
     BRI_HIP_CHECK(hipGetLastError());
 
     // phase 0 runs at s.prec on (r, p, t, ps); phase 1 (FP64 solves with a low-precision phase)
@@ -671,8 +859,9 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         StencilConfig cfg;
         StencilArgs a1, a2;
         void *r, *p, *ps;
+        void *P0, *R;  // deferred updates: base direction at the window's start, stored residuals
     };
-    auto make_phase = [&](int prec, const void *W, void *r, void *p, void *t, void *ps) {
+    auto make_phase = [&](int prec, const void *W, void *r, void *p, void *t, void *ps, void *P0, void *R) {
         Phase ph;
         ph.prec = prec;
         ph.cfg = default_config(s.g, prec, s.ncol, s.kind);
@@ -694,11 +883,14 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         ph.r = r;
         ph.p = p;
         ph.ps = ps;
+        ph.P0 = P0;
+        ph.R = R;
         return ph;
     };
     const bool has_lo = s.prec == BRI_F64 && s.prec_lo >= 0;
-    Phase phases[2] = {make_phase(s.prec, s.W, s.r, s.p, s.t, s.ps),
-                       has_lo ? make_phase(s.prec_lo, s.Wlo, s.r_lo, s.p_lo, s.t_lo, s.ps_lo) : Phase{}};
+    Phase phases[2] = {make_phase(s.prec, s.W, s.r, s.p, s.t, s.ps, s.P0, s.R),
+                       has_lo ? make_phase(s.prec_lo, s.Wlo, s.r_lo, s.p_lo, s.t_lo, s.ps_lo, s.P0_lo, s.R_lo)
+                              : Phase{}};
     const double sw2 = has_lo ? s.lo_switch * s.lo_switch : 0.0;
 
     // one CG iteration for every column: t = X p, alpha, r update, beta, vector updates, done flags
@@ -706,8 +898,15 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         const int e1 = stencil_launch(ph.a1, ph.prec, false, EPI_NORMS, ph.cfg, q);
         hipLaunchKernelGGL(ms_alpha_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
         const int e2 = stencil_launch(ph.a2, ph.prec, true, EPI_CG_R, ph.cfg, q);
-        hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
-        if (!lo)
+        hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st,
+                           s.windowed ? s.ws : nullptr);
+        if (s.windowed && !lo)
+            hipLaunchKernelGGL((ms_pupdate_kernel<double2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
+                               (const double2 *)ph.r, (double2 *)ph.p, (double2 *)ph.R);
+        else if (s.windowed)
+            hipLaunchKernelGGL((ms_pupdate_kernel<float2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
+                               (const float2 *)ph.r, (float2 *)ph.p, (float2 *)ph.R);
+        else if (!lo)
             hipLaunchKernelGGL((ms_update_kernel<double2, double2>), ugrid, dim3(256), 0, q, s.st, n, s.ncol,
                                (const double2 *)ph.r, (double2 *)ph.p, (double2 *)s.y, (double2 *)s.x,
                                (double2 *)ph.ps);
@@ -729,6 +928,31 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                                (const double2 *)s.ps, (float2 *)s.ps_lo);
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     };
+    // deferred updates: materialise y and the p^sigma of the phase's window, then empty it
+    auto fold = [&](const Phase &ph, bool lo, hipStream_t q) -> int {
+        if (!lo)
+            hipLaunchKernelGGL((ms_fold_kernel<double2, double2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
+                               (const double2 *)ph.R, (const double2 *)ph.p, (const double2 *)ph.P0,
+                               (double2 *)ph.P0, (const double2 *)ph.ps, (double2 *)ph.ps, (double2 *)s.y, 0);
+        else
+            hipLaunchKernelGGL((ms_fold_kernel<float2, float2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
+                               (const float2 *)ph.R, (const float2 *)ph.p, (const float2 *)ph.P0, (float2 *)ph.P0,
+                               (const float2 *)ph.ps, (float2 *)ph.ps, (double2 *)s.y, 0);
+        hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, q, s.ws);
+        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+    };
+    // the switch to the low-precision phase with deferred updates: the fold writes the FP32
+    // p^sigma and base direction from the FP64 window, then r and p are rounded
+    auto fold_switch = [&]() -> int {
+        hipLaunchKernelGGL((ms_fold_kernel<double2, float2>), ugrid, dim3(256), 0, strm, s.st, s.ws, n, s.ncol,
+                           (const double2 *)s.R, (const double2 *)s.p, (const double2 *)s.P0, (float2 *)s.P0_lo,
+                           (const double2 *)s.ps, (float2 *)s.ps_lo, (double2 *)s.y, 1);
+        hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, strm, s.ws);
+        const size_t cnt = n * s.ncol;
+        hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt, (const double2 *)s.r, (float2 *)s.r_lo);
+        hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt, (const double2 *)s.p, (float2 *)s.p_lo);
+        return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+    };
     const bool use_graph = allow_graphs && graphs_enabled();
     std::vector<uint64_t> key0;
     if (use_graph) {
@@ -747,26 +971,31 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                 (uint64_t)(uintptr_t)s.t, (uint64_t)(uintptr_t)s.y, (uint64_t)(uintptr_t)s.x,
                 (uint64_t)(uintptr_t)s.ps, (uint64_t)(int64_t)s.prec_lo, (uint64_t)(uintptr_t)s.Wlo,
                 (uint64_t)(uintptr_t)s.r_lo, (uint64_t)(uintptr_t)s.p_lo, (uint64_t)(uintptr_t)s.t_lo,
-                (uint64_t)(uintptr_t)s.ps_lo, swbits};
+                (uint64_t)(uintptr_t)s.ps_lo, swbits, (uint64_t)s.windowed, (uint64_t)(uintptr_t)s.ws,
+                (uint64_t)(uintptr_t)s.P0, (uint64_t)(uintptr_t)s.R, (uint64_t)(uintptr_t)s.P0_lo,
+                (uint64_t)(uintptr_t)s.R_lo};
     }
-    auto key_of = [&](int phase, int nblock) {
+    auto key_of = [&](int phase, int nblock, int win_at) {
         std::vector<uint64_t> k = key0;
         const StencilConfig &cfg = phases[phase].cfg;
         for (uint64_t v : {(uint64_t)phase, (uint64_t)nblock, (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1],
                            (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3], (uint64_t)cfg.colz, (uint64_t)cfg.nsplit,
-                           (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap, (uint64_t)cfg.variant})
+                           (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap, (uint64_t)cfg.variant, (uint64_t)win_at})
             k.push_back(v);
         return k;
     };
+    // the switch to the low-precision phase
+    auto to_low = [&]() -> int { return s.windowed ? fold_switch() : narrow(); };
 
     // a solve whose tolerance is already within the low precision's reach starts in phase 1
     int phase = 0;
     if (has_lo && s.lo_switch >= 1.0) {
-        const int e = narrow();
+        const int e = to_low();
         if (e != BRI_OK) return e;
         phase = 1;
     }
     int it = 0, it_switch = 0;
+    int since_fold = 0;  // iterations launched since the window was last folded
     rs.lo_iters = 0;
     double sec_per_iter = 0.0;  // host wall time per iteration of the last polling block
     for (;;) {
@@ -779,12 +1008,23 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         const int it_before = it;
         const Phase &ph = phases[phase];
         const bool lo = phase == 1;
+        // one iteration, then the fold whenever the window is full (every WIN iterations)
+        auto step = [&](int &sf, hipStream_t q) -> int {
+            int e = iteration(ph, lo, q);
+            if (e == BRI_OK && s.windowed && ++sf == WIN) {
+                e = fold(ph, lo, q);
+                sf = 0;
+            }
+            return e;
+        };
         if (use_graph && it + blk <= s.max_iter) {
+            const int at = since_fold;
             const int rc = graph_launch(
-                key_of(phase, blk),
+                key_of(phase, blk, s.windowed ? at : 0),
                 [&](hipStream_t q) -> int {
+                    int sf = at;
                     for (int k = 0; k < blk; ++k) {
-                        const int e = iteration(ph, lo, q);
+                        const int e = step(sf, q);
                         if (e != BRI_OK) return e;
                     }
                     return BRI_OK;
@@ -792,9 +1032,10 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                 strm);
             if (rc != BRI_OK) return rc;
             it += blk;
+            if (s.windowed) since_fold = (since_fold + blk) % WIN;
         } else {
             for (int k = 0; k < blk && it < s.max_iter; ++k, ++it) {
-                const int e = iteration(ph, lo, strm);
+                const int e = step(since_fold, strm);
                 if (e != BRI_OK) return e;
             }
         }
@@ -810,10 +1051,16 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
             BRI_HIP_CHECK(hipMemcpyAsync(cur.data(), s.st, sizeof(ColState) * s.ncol, hipMemcpyDeviceToHost, strm));
             BRI_HIP_CHECK(hipStreamSynchronize(strm));
             for (const ColState &c : cur) it_switch = c.iter > it_switch ? c.iter : it_switch;
-            const int e = narrow();
+            const int e = to_low();
             if (e != BRI_OK) return e;
+            since_fold = 0;
             phase = 1;
         }
+    }
+    // the last window's steps into y
+    if (s.windowed && since_fold > 0) {
+        const int e = fold(phases[phase], phase == 1, strm);
+        if (e != BRI_OK) return e;
     }
     rs.fin.resize(s.ncol);
     BRI_HIP_CHECK(hipMemcpyAsync(rs.fin.data(), s.st, sizeof(ColState) * s.ncol, hipMemcpyDeviceToHost, strm));
@@ -932,6 +1179,7 @@ static int ov_impl(const bri_geom *geom, const void *W64, const void *Wlo, const
     const bool mixed = prm->inner != BRI_F64;
     MsSolve m;
     plan_shifts(m, g, prm, nrhs, W64, Wlo, false);
+    m.windowed = !noalloc;  // (the static scratch holds the per-iteration form only)
     size_t scratch_bytes = 0;
     if (noalloc) {
         Arena ar(nullptr);
