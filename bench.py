@@ -667,7 +667,7 @@ def main():
     rate = NSRC / (ms_step / 1e3)
     print(f"[bench] gate against stored oracle outputs: {gate_rows}", file=sys.stderr, flush=True)
     last = stats[-1]
-    opm = None  # its workspace (~170 GB at 32^3x64) goes before the comparison paths allocate theirs
+    opm = None  # its workspace (~200 GB at 32^3x64) goes before the comparison paths allocate theirs
     torch.cuda.empty_cache()
 
     # dominant kernel family: the FP64 stencil at 32^3x64, timed live on the stream it runs on

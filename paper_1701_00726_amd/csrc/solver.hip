@@ -19,7 +19,10 @@
 // with zeta_0 = zeta_{-1} = 1, alpha_{-1} = 1, beta_{-1} = 0.  Shift sigma stops once
 // |zeta^sigma| |r| <= tol |b|.  The base shift has zeta = 1, so its search
 // direction is p itself.  When only y = c0 b + sum_sigma omega_sigma x^sigma is
-// needed the x^sigma are never stored: y accumulates omega_sigma alpha^sigma p^sigma.
+// needed the x^sigma are never stored: y accumulates omega_sigma alpha^sigma p^sigma, and the
+// applies defer even that: within a window of iterations y and the p^sigma are carried as
+// coefficients of the stored residuals and written once per window (WinState below), so an
+// iteration streams r and p instead of every p^sigma and y.
 //
 // Mixed precision (inner = BRI_F32 or BRI_F32_BF16W): the same multi-shift recurrences, with the
 // precision of the operator and of the Krylov vectors relaxed as the residual falls.  A matrix-
@@ -100,7 +103,7 @@ __device__ double2 block_sum2(const double *partial, int n) {
 // (x^sigma += alpha^sigma p^sigma, p^sigma = zeta r + beta^sigma p^sigma) act on the coefficients,
 // and a fold materialises y and the p^sigma once per window.  The sums are those of the
 // per-iteration updates, taken in another order.
-constexpr int WIN = 4;
+constexpr int WIN = 8;
 struct WinState {
     int wn;                   // residuals stored in the window
     double a[MAXS], e[MAXS];  // coefficients of P_sigma in p^sigma and in y
