@@ -214,6 +214,11 @@ typedef struct {
  * scalar stays FP64.  A low-precision product then perturbs the result by about
  * tol |psi| (the relaxation rule of inexact Krylov methods), so no shift needs a
  * separate correction.  The final X y uses W64.
+ * The shifted directions and y are written once per window of 8 iterations: in between
+ * they are carried as coefficients of the residuals the window stores (8 per right-hand
+ * side in the workspace, and 8 FP32 ones for a low-precision inner), so an iteration
+ * streams r and p rather than every p_sigma and y.  The result is the same sum taken in
+ * another order.
  *   W64 : [40][3][3][V] complex double off-axis links ([48]... with the clover term)
  *   Wlo : links in precision `inner` (from bri_build_links); NULL when inner = BRI_F64
  *   in, out : [nrhs][4][3][V] complex double (device); must not overlap each other or the
@@ -233,11 +238,12 @@ int ov_apply(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
 /*
  * ov_apply_noalloc -- ov_apply for callers that cannot allocate (no hipMalloc, hipFree, pinned
  * host memory or HIP-graph instantiation on their path): the same computation and kernels, with
- * the workspace taken from a static device array of ov_noalloc_max_bytes() = 256 MiB that the
- * library holds on each GPU it runs on until the process ends (enough for a 16^4 FP64 apply of
- * one right-hand side with 16 shifts).  The caller passes inputs and outputs as for ov_apply;
- * stats may be NULL.  Returns BRI_ESCRATCH, before launching anything, when the workspace
- * ov_apply would ask for exceeds that size.  The array's address is resolved on the first call
+ * the shifted directions and y updated every iteration (no window of stored residuals, so a
+ * smaller workspace) taken from a static device array of ov_noalloc_max_bytes() = 256 MiB that
+ * the library holds on each GPU it runs on until the process ends (enough for a 16^4 FP64 apply
+ * of one right-hand side with 16 shifts).  The caller passes inputs and outputs as for ov_apply;
+ * stats may be NULL.  Returns BRI_ESCRATCH, before launching anything, when that workspace
+ * exceeds the array.  The array's address is resolved on the first call
  * on each device.  Every call on a GPU uses that GPU's one array and nothing in it needs to be
  * cleared between calls (each call initialises what it reads); calls that overlap in time on
  * one GPU (other streams or host threads) race on it and must be serialised by the caller.
