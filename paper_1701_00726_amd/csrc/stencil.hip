@@ -146,10 +146,11 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
         else
             c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
         // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 16
-        // z-slices.  12 RHS at 32^3x64 measured 37.6 ms (FP64, R = 2) and 19.1 ms (FP32, R = 3)
-        // against 45.2 / 24.9 ms for 16 x 4 tiles with R = 4, and against 47.4 / 19.9 ms for the
-        // x-line kernel (its registers leave one FP64 wave per SIMD); bfloat16 links keep the
-        // x-line kernel with R = 3 (18.7 against 22.8 ms).
+        // z-slices.  12 RHS at 32^3x64 measured 37.6 ms (FP64, R = 2) and 18.5 ms (FP32, R = 4 at
+        // three waves per SIMD; 19.1-19.5 ms with R = 3) against 45.2 / 24.9 ms for 16 x 4 tiles
+        // with R = 4 at two waves, and against 47.4 / 19.9 ms for the x-line kernel (its
+        // registers leave one FP64 wave per SIMD); bfloat16 links keep the x-line kernel with
+        // R = 3 (18.7 against 22.8 ms).
         if (kind == KERN_BRI && ncol >= 3 && xline_fits(g)) {
             c.tile[0] = g.L[0];
             c.tile[1] = 64 / g.L[0];
@@ -161,7 +162,7 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
                 c.rpt = 3;
             } else {
                 c.colz = g.L[2] % 16 == 0 ? 16 : (g.L[2] % 8 == 0 ? 8 : 0);
-                c.rpt = prec == BRI_F64 ? 2 : 3;
+                c.rpt = prec == BRI_F64 ? 2 : 4;
             }
         }
     } else {

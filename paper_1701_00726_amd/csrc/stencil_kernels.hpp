@@ -656,8 +656,14 @@ __global__ __launch_bounds__(STREAM_THREADS) void stencil_stream_kernel(StencilA
 
 // ------------------------------------------------------ many right-hand sides
 
+// waves per SIMD the multi-RHS kernel is compiled for: three for single-precision arithmetic
+// with four right-hand sides per thread (168 VGPRs, a few spilled: 12 RHS at 32^3x64 in 18.5
+// against 20.4 ms at the two waves its 177 VGPRs would allow), else what the registers give
+template <class LS, int R> constexpr int mrhs_waves() { return sizeof(typename LS::R) == 4 && R == 4 ? 3 : 1; }
+
 template <class LS, int R, bool DAG, int MODE, int KIND>
-__global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_mrhs_kernel(StencilArgs a) {
+__global__ __launch_bounds__(64 * MRHS_SPLIT) __attribute__((amdgpu_waves_per_eu(mrhs_waves<LS, R>())))
+void stencil_mrhs_kernel(StencilArgs a) {
     using RT = typename LS::R;
     using C = typename Cx<RT>::T;
     constexpr int NSPLIT = MRHS_SPLIT;
