@@ -754,9 +754,10 @@ void graph_cache_clear_locked() {
 // The launch happens under the cache lock, so another host thread cannot evict (destroy) the
 // executable graph between lookup and launch.
 template <typename F>
-static int graph_launch(const std::vector<uint64_t> &key, F enqueue, hipStream_t strm) {
+static int graph_launch(const std::vector<uint64_t> &key, F enqueue, hipStream_t strm, bool *captured = nullptr) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
+    if (captured) *captured = it == g_graphs.end();
     if (it != g_graphs.end()) {
         if (hipGraphLaunch(it->second.exec, strm) != hipSuccess) return BRI_EHIP;
         return hipEventRecord(it->second.done, strm) == hipSuccess ? BRI_OK : BRI_EHIP;
@@ -1020,6 +1021,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
             }
             return e;
         };
+        bool captured = false;  // a block whose graph was captured now: its time is not an iteration's
         if (use_graph && it + blk <= s.max_iter) {
             const int at = since_fold;
             const int rc = graph_launch(
@@ -1032,7 +1034,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                     }
                     return BRI_OK;
                 },
-                strm);
+                strm, &captured);
             if (rc != BRI_OK) return rc;
             it += blk;
             if (s.windowed) since_fold = (since_fold + blk) % WIN;
@@ -1044,7 +1046,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         }
         BRI_HIP_CHECK(hipMemcpyAsync(hflag, s.alldone, sizeof(int), hipMemcpyDeviceToHost, strm));
         BRI_HIP_CHECK(hipStreamSynchronize(strm));
-        if (it > it_before)
+        if (it > it_before && !captured)
             sec_per_iter = std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count() /
                            (it - it_before);
         if (*hflag == 1 || it >= s.max_iter) break;
