@@ -641,7 +641,7 @@ def main():
 
     def step():
         bri.build_links(L, U, bri.F64, out=W)
-        bri.build_links(L, U, inner, out=Wlo)
+        bri.round_links(L, W, inner, out=Wlo)
         _, st = opm.apply(b12, out=o12)
         return st
 
@@ -698,7 +698,7 @@ def main():
             f"multi-shift stopped at the result bound {RESULT_TOL:g} (error of D_ov psi <= rho {RESULT_TOL:g} |psi|), "
             f"links exp(0.7iA) + 3 APE(0.6); mixed-precision batched ov_apply (FP64 multi-shift, "
             f"{args.inner} links and vectors once the residual allows, FP64 final apply); "
-            f"step = bri_build_links (FP64 + {args.inner}) + ov_apply over the 12 sources",
+            f"step = bri_build_links (FP64) + bri_round_links ({args.inner}) + ov_apply over the 12 sources",
             "lattice": list(L),
             "kl_n": KL_N,
             "nrhs": NSRC,

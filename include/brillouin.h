@@ -96,9 +96,22 @@ typedef enum {
  * overlapping U,
  * BRI_EHIP on a HIP failure.  Asynchronous on `stream` for wprec = BRI_F64; for the lower
  * precisions a temporary FP64 buffer of 5760*V bytes (6912*V with the clover term) is
- * allocated, and the call synchronises `stream` before freeing it.
+ * allocated, and the call synchronises `stream` before freeing it (bri_round_links takes an
+ * FP64 array already built instead, without either).
  */
 int bri_build_links(const bri_geom *geom, const void *U, void *W, int wprec, void *stream);
+
+/*
+ * bri_round_links -- the link array of bri_build_links rounded from FP64 to wprec = BRI_F32 or
+ * BRI_F32_BF16W, entry by entry (the rounding bri_build_links applies on store), for a caller
+ * that holds the FP64 array already: the mixed-precision applies take both.  geom->csw != 0:
+ * the clover slabs are rounded with the links.
+ *   W64 : [40 or 48][3][3][V] complex double (device, read)
+ *   W   : the same shape in precision wprec (device, written); must not overlap W64
+ * Returns BRI_EINVAL for a bad geometry, precision or pointer, or overlapping arrays; BRI_EHIP
+ * on a launch failure.  Asynchronous on `stream`; allocates nothing.
+ */
+int bri_round_links(const bri_geom *geom, const void *W64, void *W, int wprec, void *stream);
 
 /*
  * bri_apply -- out = D_bri(m0) in, the 81-point sum (App. C.1)

@@ -181,6 +181,7 @@ def load():
             P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
             G = ctypes.POINTER(_Geom)
             lib.bri_build_links.argtypes = [G, P, P, I, P]
+            lib.bri_round_links.argtypes = [G, P, P, I, P]
             lib.bri_apply.argtypes = [G, P, I, D, P, P, I, P]
             lib.bri_apply_dag.argtypes = [G, P, I, D, P, P, I, P]
             lib.wil_apply.argtypes = [G, P, I, D, P, P, I, P]
@@ -215,6 +216,7 @@ def load():
 
 EXPORTS = (
     "bri_build_links",
+    "bri_round_links",
     "bri_apply",
     "bri_apply_dag",
     "wil_apply",
@@ -362,6 +364,22 @@ def build_links(L, U, prec=F64, tbc=0, stream=None, out=None, csw=0.0):
     _check_out(out, link_dtype(prec), (nslab, 3, 3, V), U.device)
     g = _geom(L, tbc, csw)
     _check("bri_build_links", load().bri_build_links(ctypes.byref(g), _dptr(U), _dptr(out), int(prec), _stream(stream)))
+    return out
+
+
+def round_links(L, W64, prec, stream=None, out=None):
+    """The FP64 link array W64 of build_links rounded to prec (F32 or F32_BF16W), as build_links
+    would store it; no allocation in the library."""
+    torch = _torch()
+    V = int(np.prod(L))
+    if W64.dtype != torch.complex128 or W64.shape[0] not in (40, 48) or tuple(W64.shape[1:]) != (3, 3, V):
+        raise ValueError("W64 must be complex128 of shape (40 or 48, 3, 3, V)")
+    if out is None:
+        out = torch.empty(tuple(W64.shape), dtype=link_dtype(prec), device=W64.device)
+    _check_out(out, link_dtype(prec), tuple(W64.shape), W64.device)
+    g = _geom(L, 0, _clover_flag(W64))
+    _check("bri_round_links", load().bri_round_links(ctypes.byref(g), _dptr(W64), _dptr(out), int(prec),
+                                                     _stream(stream)))
     return out
 
 

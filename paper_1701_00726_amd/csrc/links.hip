@@ -127,6 +127,16 @@ __global__ void convert_bf16_kernel(size_t n, const double2 *__restrict__ src, u
     }
 }
 
+// n link entries of an FP64 array rounded into W (complex float, or a (re, im) bfloat16 pair)
+static int round_links(size_t n, const double2 *src, void *W, int wprec, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (wprec == BRI_F32)
+        hipLaunchKernelGGL(convert_f32_kernel, dim3(blocks), dim3(256), 0, s, n, src, (float2 *)W);
+    else
+        hipLaunchKernelGGL(convert_bf16_kernel, dim3(blocks), dim3(256), 0, s, n, src, (uint32_t *)W);
+    return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
+}
+
 int geom_check(const bri_geom *geom, Geom *g) {
     if (!geom) return BRI_EINVAL;
     long long V = 1;
@@ -306,15 +316,19 @@ extern "C" int bri_build_links(const bri_geom *geom, const void *U, void *W, int
     BRI_HIP_CHECK(hipMalloc(&tmp, n * sizeof(double2)));
     st = build_links_f64(g, (const double2 *)U, tmp, s);
     if (st == BRI_OK && g.csw != 0.0) st = build_clover(g, (const double2 *)U, tmp + (size_t)LINK_SLAB_ENTRIES * g.V, s);
-    if (st == BRI_OK) {
-        const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-        if (wprec == BRI_F32)
-            hipLaunchKernelGGL(convert_f32_kernel, dim3(blocks), dim3(256), 0, s, n, tmp, (float2 *)W);
-        else
-            hipLaunchKernelGGL(convert_bf16_kernel, dim3(blocks), dim3(256), 0, s, n, tmp, (uint32_t *)W);
-        if (hipGetLastError() != hipSuccess) st = BRI_EHIP;
-    }
+    if (st == BRI_OK) st = round_links(n, tmp, W, wprec, s);
     if (hipStreamSynchronize(s) != hipSuccess) st = BRI_EHIP;
     if (hipFree(tmp) != hipSuccess) st = BRI_EHIP;
     return st;
+}
+
+extern "C" int bri_round_links(const bri_geom *geom, const void *W64, void *W, int wprec, void *stream) {
+    using namespace bri;
+    Geom g;
+    const int st = geom_check(geom, &g);
+    if (st != BRI_OK) return st;
+    if (!W64 || !W || (wprec != BRI_F32 && wprec != BRI_F32_BF16W)) return BRI_EINVAL;
+    const size_t n = link_entries(g);
+    if (ranges_overlap(W64, n * sizeof(double2), W, n * (wprec == BRI_F32 ? 8 : 4))) return BRI_EINVAL;
+    return round_links(n, (const double2 *)W64, W, wprec, (hipStream_t)stream);
 }

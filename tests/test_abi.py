@@ -92,6 +92,16 @@ def test_invalid_stencil_arguments():
     assert lib.bri_build_links(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 5, None) == bri.EINVAL
     g.tbc = 2
     assert lib.bri_build_links(ctypes.byref(g), ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None) == bri.EINVAL
+    g.tbc = 0
+    P = ctypes.c_void_p
+    assert lib.bri_round_links(None, P(1 << 24), P(1 << 26), 1, None) == bri.EINVAL
+    assert lib.bri_round_links(ctypes.byref(g), None, P(1 << 26), 1, None) == bri.EINVAL
+    assert lib.bri_round_links(ctypes.byref(g), P(1 << 24), None, 2, None) == bri.EINVAL
+    for prec in (0, 3, -1):  # FP64 is the source precision, not a target
+        assert lib.bri_round_links(ctypes.byref(g), P(1 << 24), P(1 << 26), prec, None) == bri.EINVAL
+    # the rounded array written over the FP64 one
+    assert lib.bri_round_links(ctypes.byref(g), P(1 << 24), P((1 << 24) + 64), 1, None) == bri.EINVAL
+    assert lib.bri_round_links(ctypes.byref(g), P(1 << 24), P((1 << 24) - 4096), 2, None) == bri.EINVAL
 
 
 def test_gradient_workspace_and_invalid_arguments():

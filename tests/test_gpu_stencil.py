@@ -55,6 +55,23 @@ def test_build_links_low_precision_bit_exact(prec):
     assert np.abs(Wg - Wo[:, :40]).max() <= (4e-3 if prec == bri.F32_BF16W else 1e-7)
 
 
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+@pytest.mark.parametrize("prec", [bri.F32, bri.F32_BF16W])
+def test_round_links_equals_low_precision_build(prec, csw):
+    """bri_round_links on the FP64 array gives bri_build_links' low-precision array bit for bit
+    (the clover slabs too for csw != 0)."""
+    need_gpu()
+    L = (4, 8, 4, 6)
+    U, _ = field(L, "rough")
+    Ud = bri.links_to_device(U)
+    W64 = bri.build_links(L, Ud, bri.F64, csw=csw)
+    Wb = bri.build_links(L, Ud, prec, csw=csw)
+    Wr = bri.round_links(L, W64, prec)
+    torch.cuda.synchronize()
+    assert Wr.shape == Wb.shape == (48 if csw else 40, 3, 3, int(np.prod(L)))
+    assert np.array_equal(Wr.cpu().numpy().view(np.uint32), Wb.cpu().numpy().view(np.uint32))
+
+
 @pytest.mark.parametrize("L,kind,tbc", CASES)
 @pytest.mark.parametrize("dag", [False, True])
 def test_apply_f64(L, kind, tbc, dag):
