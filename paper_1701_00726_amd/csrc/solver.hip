@@ -112,7 +112,8 @@ struct WinState {
 };
 
 // column c = blockIdx.y.  r = p = b, p_sigma = b, and y = c0 b (or x_sigma = 0);
-// partial |b|^2.  B is the input type (double2 or float2), C the solver type.
+// partial |b|^2.  B is the input type (double2 or float2), C the solver type.  With deferred
+// updates y and ps are NULL: the first window reads b in their place.
 template <typename B, typename C>
 __global__ void ms_init_kernel(size_t n, const B *__restrict__ b, C *__restrict__ r, C *__restrict__ p,
                                C *__restrict__ y, C *__restrict__ x, C *__restrict__ ps, int ncol, int nshift,
@@ -139,7 +140,8 @@ __global__ void ms_init_kernel(size_t n, const B *__restrict__ b, C *__restrict_
             z.y = 0;
             for (int k = 0; k < nshift; ++k) x[((size_t)k * ncol + col) * n + i] = z;
         }
-        for (int k = 1; k < nshift; ++k) ps[((size_t)(k - 1) * ncol + col) * n + i] = v;
+        if (ps)
+            for (int k = 1; k < nshift; ++k) ps[((size_t)(k - 1) * ncol + col) * n + i] = v;
         s += (double)v.x * v.x + (double)v.y * v.y;
     }
     __shared__ double sh[256];
@@ -424,18 +426,20 @@ __global__ __launch_bounds__(256) void ms_pupdate_kernel(const ColState *__restr
 // The fold: y += e_0 P_0 + sum_{sigma>=1} e_sigma P_sigma + sum_j f_j R_j, and for a running column
 // P_sigma <- a_sigma P_sigma + sum_j c[sigma][j] R_j for the shifts still active and P_0 <- p, all
 // in FP64 arithmetic.  CI is the type of the window's vectors, CO that of the P written (FP32
-// at the switch to the low-precision phase, where Pout / P0out are the FP32 vectors).
+// at the switch to the low-precision phase, where Pout / P0out are the FP32 vectors).  In the
+// first window (first = 1) every P_sigma is the right-hand side b, which P_0 holds, and y starts
+// at c0 b, so P_0 is read in their place (neither y nor the P_sigma was written at the start).
 template <typename CI, typename CO>
 __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict__ states,
                                                       const WinState *__restrict__ ws, size_t n, int ncol,
                                                       const CI *__restrict__ R, const CI *__restrict__ p,
                                                       const CI *P0in, CO *P0out, const CI *Pin, CO *Pout,
-                                                      double2 *__restrict__ y, int convert) {
+                                                      double2 *__restrict__ y, int convert, int first) {
     const int col = blockIdx.y;
     const ColState *st = states + col;
     const WinState *w = ws + col;
     const int m = w->wn < WIN ? w->wn : WIN;
-    if (m == 0 && !convert) return;  // no iteration since the last fold: nothing changed
+    if (m == 0 && !convert && !first) return;  // no iteration since the last fold: nothing changed
     const int ns = st->nshift;
     const bool running = st->done == 0;
     const size_t off = (size_t)col * n;
@@ -450,11 +454,22 @@ __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict
                 rj[j] = make_double2(0.0, 0.0);
             }
         }
-        double2 yv = y[off + i];
+        double2 yv, bv = make_double2(0.0, 0.0);
+        if (first) {
+            const CI u = P0in[off + i];
+            bv = make_double2(u.x, u.y);
+            yv = make_double2(st->c0 * bv.x, st->c0 * bv.y);
+        } else {
+            yv = y[off + i];
+        }
         // a direction is read only where it enters: a shift without a step in this window (e = 0)
         // that no longer runs may hold a stale or never-written vector
         if (w->e[0] != 0.0) {
-            const CI v = P0in[off + i];
+            double2 v = bv;
+            if (!first) {
+                const CI u = P0in[off + i];
+                v = make_double2(u.x, u.y);
+            }
             yv.x += w->e[0] * v.x;
             yv.y += w->e[0] * v.y;
         }
@@ -463,7 +478,11 @@ __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict
             const bool adv = running && st->active[k];
             if (e == 0.0 && !adv) continue;
             const size_t pidx = ((size_t)(k - 1) * ncol + col) * n + i;
-            const CI v = Pin[pidx];
+            double2 v = bv;
+            if (!first) {
+                const CI u = Pin[pidx];
+                v = make_double2(u.x, u.y);
+            }
             yv.x += e * v.x;
             yv.y += e * v.y;
             if (adv) {
@@ -844,13 +863,15 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
     BRI_HIP_CHECK(hipMemcpyAsync(s.st, h.data(), sizeof(ColState) * s.ncol, hipMemcpyHostToDevice, strm));
     const dim3 vgrid(INIT_BLOCKS, s.ncol);
     const dim3 ugrid(update_blocks(n), s.ncol);
+    // (with deferred updates y and the p^sigma are c0 b and b until the first fold, which reads the
+    // window's base direction P_0 = b in their place)
     hipLaunchKernelGGL((ms_init_kernel<double2, double2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
-                       (double2 *)s.r, (double2 *)s.p, (double2 *)s.y, (double2 *)s.x, (double2 *)s.ps, s.ncol,
-                       s.nshift, s.c0, s.partial);
+                       (double2 *)s.r, (double2 *)s.p, s.windowed ? nullptr : (double2 *)s.y, (double2 *)s.x,
+                       s.windowed ? nullptr : (double2 *)s.ps, s.ncol, s.nshift, s.c0, s.partial);
     hipLaunchKernelGGL(ms_scalar_init_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, INIT_BLOCKS,
                        s.tol);
     if (s.windowed) {
-        BRI_HIP_CHECK(hipMemcpyAsync(s.P0, s.p, n * s.ncol * sizeof(double2), hipMemcpyDeviceToDevice, strm));
+        BRI_HIP_CHECK(hipMemcpyAsync(s.P0, b, n * s.ncol * sizeof(double2), hipMemcpyDeviceToDevice, strm));
         hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, strm, s.ws);
     }
     BRI_HIP_CHECK(hipGetLastError());
@@ -933,24 +954,25 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     };
     // deferred updates: materialise y and the p^sigma of the phase's window, then empty it
-    auto fold = [&](const Phase &ph, bool lo, hipStream_t q) -> int {
+    // (first: no fold yet, so P_0 = b stands for y / c0 and every direction)
+    auto fold = [&](const Phase &ph, bool lo, hipStream_t q, int first) -> int {
         if (!lo)
             hipLaunchKernelGGL((ms_fold_kernel<double2, double2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
                                (const double2 *)ph.R, (const double2 *)ph.p, (const double2 *)ph.P0,
-                               (double2 *)ph.P0, (const double2 *)ph.ps, (double2 *)ph.ps, (double2 *)s.y, 0);
+                               (double2 *)ph.P0, (const double2 *)ph.ps, (double2 *)ph.ps, (double2 *)s.y, 0, first);
         else
             hipLaunchKernelGGL((ms_fold_kernel<float2, float2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
                                (const float2 *)ph.R, (const float2 *)ph.p, (const float2 *)ph.P0, (float2 *)ph.P0,
-                               (const float2 *)ph.ps, (float2 *)ph.ps, (double2 *)s.y, 0);
+                               (const float2 *)ph.ps, (float2 *)ph.ps, (double2 *)s.y, 0, first);
         hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, q, s.ws);
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     };
     // the switch to the low-precision phase with deferred updates: the fold writes the FP32
     // p^sigma and base direction from the FP64 window, then r and p are rounded
-    auto fold_switch = [&]() -> int {
+    auto fold_switch = [&](int first) -> int {
         hipLaunchKernelGGL((ms_fold_kernel<double2, float2>), ugrid, dim3(256), 0, strm, s.st, s.ws, n, s.ncol,
                            (const double2 *)s.R, (const double2 *)s.p, (const double2 *)s.P0, (float2 *)s.P0_lo,
-                           (const double2 *)s.ps, (float2 *)s.ps_lo, (double2 *)s.y, 1);
+                           (const double2 *)s.ps, (float2 *)s.ps_lo, (double2 *)s.y, 1, first);
         hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, strm, s.ws);
         const size_t cnt = n * s.ncol;
         hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt, (const double2 *)s.r, (float2 *)s.r_lo);
@@ -979,17 +1001,24 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                 (uint64_t)(uintptr_t)s.P0, (uint64_t)(uintptr_t)s.R, (uint64_t)(uintptr_t)s.P0_lo,
                 (uint64_t)(uintptr_t)s.R_lo};
     }
-    auto key_of = [&](int phase, int nblock, int win_at) {
+    auto key_of = [&](int phase, int nblock, int win_at, int first) {
         std::vector<uint64_t> k = key0;
         const StencilConfig &cfg = phases[phase].cfg;
         for (uint64_t v : {(uint64_t)phase, (uint64_t)nblock, (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1],
                            (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3], (uint64_t)cfg.colz, (uint64_t)cfg.nsplit,
-                           (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap, (uint64_t)cfg.variant, (uint64_t)win_at})
+                           (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap, (uint64_t)cfg.variant, (uint64_t)win_at,
+                           (uint64_t)first})
             k.push_back(v);
         return k;
     };
     // the switch to the low-precision phase
-    auto to_low = [&]() -> int { return s.windowed ? fold_switch() : narrow(); };
+    bool first_window = s.windowed;  // no fold yet
+    auto to_low = [&]() -> int {
+        if (!s.windowed) return narrow();
+        const int e = fold_switch(first_window ? 1 : 0);
+        first_window = false;
+        return e;
+    };
 
     // a solve whose tolerance is already within the low precision's reach starts in phase 1
     int phase = 0;
@@ -1013,23 +1042,26 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         const Phase &ph = phases[phase];
         const bool lo = phase == 1;
         // one iteration, then the fold whenever the window is full (every WIN iterations)
-        auto step = [&](int &sf, hipStream_t q) -> int {
+        auto step = [&](int &sf, bool &fw, hipStream_t q) -> int {
             int e = iteration(ph, lo, q);
             if (e == BRI_OK && s.windowed && ++sf == WIN) {
-                e = fold(ph, lo, q);
+                e = fold(ph, lo, q, fw ? 1 : 0);
                 sf = 0;
+                fw = false;
             }
             return e;
         };
         bool captured = false;  // a block whose graph was captured now: its time is not an iteration's
         if (use_graph && it + blk <= s.max_iter) {
             const int at = since_fold;
+            const bool fw0 = first_window;
             const int rc = graph_launch(
-                key_of(phase, blk, s.windowed ? at : 0),
+                key_of(phase, blk, s.windowed ? at : 0, fw0 ? 1 : 0),
                 [&](hipStream_t q) -> int {
                     int sf = at;
+                    bool fw = fw0;
                     for (int k = 0; k < blk; ++k) {
-                        const int e = step(sf, q);
+                        const int e = step(sf, fw, q);
                         if (e != BRI_OK) return e;
                     }
                     return BRI_OK;
@@ -1037,10 +1069,13 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
                 strm, &captured);
             if (rc != BRI_OK) return rc;
             it += blk;
-            if (s.windowed) since_fold = (since_fold + blk) % WIN;
+            if (s.windowed) {
+                if (first_window && at + blk >= WIN) first_window = false;  // the block folded
+                since_fold = (since_fold + blk) % WIN;
+            }
         } else {
             for (int k = 0; k < blk && it < s.max_iter; ++k, ++it) {
-                const int e = step(since_fold, strm);
+                const int e = step(since_fold, first_window, strm);
                 if (e != BRI_OK) return e;
             }
         }
@@ -1062,9 +1097,9 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
             phase = 1;
         }
     }
-    // the last window's steps into y
-    if (s.windowed && since_fold > 0) {
-        const int e = fold(phases[phase], phase == 1, strm);
+    // the last window's steps into y (and y itself, if no fold has written it yet)
+    if (s.windowed && (since_fold > 0 || first_window)) {
+        const int e = fold(phases[phase], phase == 1, strm, first_window ? 1 : 0);
         if (e != BRI_OK) return e;
     }
     rs.fin.resize(s.ncol);
