@@ -103,12 +103,15 @@ __device__ double2 block_sum2(const double *partial, int n) {
 // (x^sigma += alpha^sigma p^sigma, p^sigma = zeta r + beta^sigma p^sigma) act on the coefficients,
 // and a fold materialises y and the p^sigma once per window.  The sums are those of the
 // per-iteration updates, taken in another order.
+// When every x^sigma is kept (the gradient's shift solutions) the same holds per shift:
+//   x^sigma = x^sigma_0 + e_sigma P_sigma + sum_j h[sigma][j] R_j.
 constexpr int WIN = 8;
 struct WinState {
     int wn;                   // residuals stored in the window
-    double a[MAXS], e[MAXS];  // coefficients of P_sigma in p^sigma and in y
+    double a[MAXS], e[MAXS];  // coefficients of P_sigma in p^sigma and in y (or in x^sigma)
     double c[MAXS][WIN + 1];  // c[sigma][j]: of R_j in p^sigma (j = 1..WIN)
     double f[WIN + 1];        // f[j]: of R_j in y
+    double h[MAXS][WIN + 1];  // h[sigma][j]: of R_j in x^sigma
 };
 
 // column c = blockIdx.y.  r = p = b, p_sigma = b, and y = c0 b (or x_sigma = 0);
@@ -228,7 +231,7 @@ __global__ void ms_alpha_kernel(ColState *states, const double *partial, int nbl
 // Stopping: shift i by itself once |r_i| <= tol_i |b|; with the result bound (joint), shift i
 // once ebw_i |r_i| <= tol |b| / (2 nshift), and every shift once sum_i ebw_i |r_i| <= tol |b|
 // (a stopped shift counts with its residual when it stopped).
-__global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk, WinState *ws) {
+__global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk, WinState *ws, int xmode) {
     ColState *st = states + blockIdx.x;
     if (st->done) return;
     const double rr_new = block_sum2(partial + 2 * (size_t)blockIdx.x * nblk, nblk).x;
@@ -285,14 +288,21 @@ __global__ void ms_beta_kernel(ColState *states, const double *partial, int nblk
         const int m = w->wn;
         overflow = m >= WIN;  // the host folds every WIN iterations; never reached
         if (!overflow) {
-            // y += sum_sigma omega alpha^sigma p^sigma (the shifts that took their step)
-            const double wgt = (i < ns && st->upd_x[i]) ? st->omega[i] * st->alpha_s[i] : 0.0;
+            // y += sum_sigma omega alpha^sigma p^sigma, or x^sigma += alpha^sigma p^sigma (the
+            // shifts that took their step)
+            const bool step = i < ns && st->upd_x[i];
+            const double wgt = step ? (xmode ? 1.0 : st->omega[i]) * st->alpha_s[i] : 0.0;
             if (i < ns) w->e[i] += wgt * w->a[i];
-            for (int j = 1; j <= m; ++j) {
-                double v = i < ns ? wgt * w->c[i][j] : 0.0;
+            if (xmode) {
+                if (step)
+                    for (int j = 1; j <= m; ++j) w->h[i][j] += wgt * w->c[i][j];
+            } else {
+                for (int j = 1; j <= m; ++j) {
+                    double v = i < ns ? wgt * w->c[i][j] : 0.0;
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-                if (i == 0) w->f[j] += v;
+                    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if (i == 0) w->f[j] += v;
+                }
             }
             // p^sigma <- zeta_{k+1} r_{k+1} + beta^sigma p^sigma for the shifts still running;
             // the base direction p <- r_{k+1} + beta p always
@@ -423,18 +433,21 @@ __global__ __launch_bounds__(256) void ms_pupdate_kernel(const ColState *__restr
     }
 }
 
-// The fold: y += e_0 P_0 + sum_{sigma>=1} e_sigma P_sigma + sum_j f_j R_j, and for a running column
+// The fold: y += e_0 P_0 + sum_{sigma>=1} e_sigma P_sigma + sum_j f_j R_j (or, with x != NULL,
+// x^sigma += e_sigma P_sigma + sum_j h[sigma][j] R_j for every shift), and for a running column
 // P_sigma <- a_sigma P_sigma + sum_j c[sigma][j] R_j for the shifts still active and P_0 <- p, all
 // in FP64 arithmetic.  CI is the type of the window's vectors, CO that of the P written (FP32
 // at the switch to the low-precision phase, where Pout / P0out are the FP32 vectors).  In the
-// first window (first = 1) every P_sigma is the right-hand side b, which P_0 holds, and y starts
-// at c0 b, so P_0 is read in their place (neither y nor the P_sigma was written at the start).
+// first window (first = 1) every P_sigma is the right-hand side b, which P_0 holds, y starts
+// at c0 b and every x^sigma at 0, so P_0 is read in their place (neither y, the x^sigma nor the
+// P_sigma was written at the start) and every x^sigma is written.
 template <typename CI, typename CO>
 __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict__ states,
                                                       const WinState *__restrict__ ws, size_t n, int ncol,
                                                       const CI *__restrict__ R, const CI *__restrict__ p,
                                                       const CI *P0in, CO *P0out, const CI *Pin, CO *Pout,
-                                                      double2 *__restrict__ y, int convert, int first) {
+                                                      double2 *__restrict__ y, double2 *__restrict__ x, int convert,
+                                                      int first) {
     const int col = blockIdx.y;
     const ColState *st = states + col;
     const WinState *w = ws + col;
@@ -442,6 +455,7 @@ __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict
     if (m == 0 && !convert && !first) return;  // no iteration since the last fold: nothing changed
     const int ns = st->nshift;
     const bool running = st->done == 0;
+    const bool xmode = x != nullptr;
     const size_t off = (size_t)col * n;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         double2 rj[WIN];
@@ -454,37 +468,60 @@ __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict
                 rj[j] = make_double2(0.0, 0.0);
             }
         }
-        double2 yv, bv = make_double2(0.0, 0.0);
+        double2 yv = make_double2(0.0, 0.0), bv = make_double2(0.0, 0.0);
         if (first) {
             const CI u = P0in[off + i];
             bv = make_double2(u.x, u.y);
-            yv = make_double2(st->c0 * bv.x, st->c0 * bv.y);
-        } else {
-            yv = y[off + i];
         }
+        if (!xmode) yv = first ? make_double2(st->c0 * bv.x, st->c0 * bv.y) : y[off + i];
+        // x^sigma += e_sigma P_sigma + sum_j h[sigma][j] R_j for a shift with steps in this window
+        auto x_step = [&](int k, const double2 &v) {
+            const double e = w->e[k];
+            if (e == 0.0 && !first) return;
+            const size_t xi = ((size_t)k * ncol + col) * n + i;
+            double2 xv = first ? make_double2(0.0, 0.0) : x[xi];
+            xv.x += e * v.x;
+            xv.y += e * v.y;
+#pragma unroll
+            for (int j = 0; j < WIN; ++j) {
+                if (j < m) {
+                    xv.x += w->h[k][j + 1] * rj[j].x;
+                    xv.y += w->h[k][j + 1] * rj[j].y;
+                }
+            }
+            x[xi] = xv;
+        };
         // a direction is read only where it enters: a shift without a step in this window (e = 0)
         // that no longer runs may hold a stale or never-written vector
-        if (w->e[0] != 0.0) {
+        if (w->e[0] != 0.0 || (xmode && first)) {
             double2 v = bv;
             if (!first) {
                 const CI u = P0in[off + i];
                 v = make_double2(u.x, u.y);
             }
-            yv.x += w->e[0] * v.x;
-            yv.y += w->e[0] * v.y;
+            if (xmode) {
+                x_step(0, v);
+            } else {
+                yv.x += w->e[0] * v.x;
+                yv.y += w->e[0] * v.y;
+            }
         }
         for (int k = 1; k < ns; ++k) {
             const double e = w->e[k];
             const bool adv = running && st->active[k];
-            if (e == 0.0 && !adv) continue;
+            if (e == 0.0 && !adv && !(xmode && first)) continue;
             const size_t pidx = ((size_t)(k - 1) * ncol + col) * n + i;
             double2 v = bv;
             if (!first) {
                 const CI u = Pin[pidx];
                 v = make_double2(u.x, u.y);
             }
-            yv.x += e * v.x;
-            yv.y += e * v.y;
+            if (xmode) {
+                x_step(k, v);
+            } else {
+                yv.x += e * v.x;
+                yv.y += e * v.y;
+            }
             if (adv) {
                 const double a = w->a[k];
                 double ux = a * v.x, uy = a * v.y;
@@ -502,14 +539,16 @@ __global__ __launch_bounds__(256) void ms_fold_kernel(const ColState *__restrict
                 Pout[pidx] = u;
             }
         }
+        if (!xmode) {
 #pragma unroll
-        for (int j = 0; j < WIN; ++j) {
-            if (j < m) {
-                yv.x += w->f[j + 1] * rj[j].x;
-                yv.y += w->f[j + 1] * rj[j].y;
+            for (int j = 0; j < WIN; ++j) {
+                if (j < m) {
+                    yv.x += w->f[j + 1] * rj[j].x;
+                    yv.y += w->f[j + 1] * rj[j].y;
+                }
             }
+            y[off + i] = yv;
         }
-        y[off + i] = yv;
         if (running) {
             const CI v = p[off + i];
             CO u;
@@ -527,7 +566,10 @@ __global__ void ms_window_reset_kernel(WinState *ws) {
     if (i < MAXS) {
         w->a[i] = 1.0;
         w->e[i] = 0.0;
-        for (int j = 0; j <= WIN; ++j) w->c[i][j] = 0.0;
+        for (int j = 0; j <= WIN; ++j) {
+            w->c[i][j] = 0.0;
+            w->h[i][j] = 0.0;
+        }
     }
     if (i <= WIN) w->f[i] = 0.0;
     if (i == 0) w->wn = 0;
@@ -683,7 +725,7 @@ struct MsSolve {
     int *alldone = nullptr;
     void *r = nullptr, *p = nullptr, *t = nullptr, *y = nullptr, *x = nullptr, *ps = nullptr;
     int nblk_st = 0;
-    // deferred shift updates (y accumulation only): window state, the base direction at the
+    // deferred shift updates: window state, the base direction at the
     // window's start and the stored residuals, per phase
     bool windowed = false;
     WinState *ws = nullptr;
@@ -705,7 +747,6 @@ struct MsSolve {
         else
             y = ar.take(vb);
         if (nshift > 1) ps = ar.take(vb * (nshift - 1));
-        windowed = windowed && !store_x;
         if (windowed) {
             ws = (WinState *)ar.take(sizeof(WinState) * ncol);
             P0 = ar.take(vb);
@@ -866,8 +907,9 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
     // (with deferred updates y and the p^sigma are c0 b and b until the first fold, which reads the
     // window's base direction P_0 = b in their place)
     hipLaunchKernelGGL((ms_init_kernel<double2, double2>), vgrid, dim3(256), 0, strm, n, (const double2 *)b,
-                       (double2 *)s.r, (double2 *)s.p, s.windowed ? nullptr : (double2 *)s.y, (double2 *)s.x,
-                       s.windowed ? nullptr : (double2 *)s.ps, s.ncol, s.nshift, s.c0, s.partial);
+                       (double2 *)s.r, (double2 *)s.p, s.windowed ? nullptr : (double2 *)s.y,
+                       s.windowed ? nullptr : (double2 *)s.x, s.windowed ? nullptr : (double2 *)s.ps, s.ncol,
+                       s.nshift, s.c0, s.partial);
     hipLaunchKernelGGL(ms_scalar_init_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, strm, s.st, s.partial, INIT_BLOCKS,
                        s.tol);
     if (s.windowed) {
@@ -924,7 +966,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         hipLaunchKernelGGL(ms_alpha_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st);
         const int e2 = stencil_launch(ph.a2, ph.prec, true, EPI_CG_R, ph.cfg, q);
         hipLaunchKernelGGL(ms_beta_kernel, dim3(s.ncol), dim3(RED_THREADS), 0, q, s.st, s.partial, s.nblk_st,
-                           s.windowed ? s.ws : nullptr);
+                           s.windowed ? s.ws : nullptr, s.store_x ? 1 : 0);
         if (s.windowed && !lo)
             hipLaunchKernelGGL((ms_pupdate_kernel<double2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
                                (const double2 *)ph.r, (double2 *)ph.p, (double2 *)ph.R);
@@ -955,15 +997,17 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
     };
     // deferred updates: materialise y and the p^sigma of the phase's window, then empty it
     // (first: no fold yet, so P_0 = b stands for y / c0 and every direction)
+    double2 *xv = s.store_x ? (double2 *)s.x : nullptr;
     auto fold = [&](const Phase &ph, bool lo, hipStream_t q, int first) -> int {
         if (!lo)
             hipLaunchKernelGGL((ms_fold_kernel<double2, double2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
                                (const double2 *)ph.R, (const double2 *)ph.p, (const double2 *)ph.P0,
-                               (double2 *)ph.P0, (const double2 *)ph.ps, (double2 *)ph.ps, (double2 *)s.y, 0, first);
+                               (double2 *)ph.P0, (const double2 *)ph.ps, (double2 *)ph.ps, (double2 *)s.y, xv, 0,
+                               first);
         else
             hipLaunchKernelGGL((ms_fold_kernel<float2, float2>), ugrid, dim3(256), 0, q, s.st, s.ws, n, s.ncol,
                                (const float2 *)ph.R, (const float2 *)ph.p, (const float2 *)ph.P0, (float2 *)ph.P0,
-                               (const float2 *)ph.ps, (float2 *)ph.ps, (double2 *)s.y, 0, first);
+                               (const float2 *)ph.ps, (float2 *)ph.ps, (double2 *)s.y, xv, 0, first);
         hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, q, s.ws);
         return hipGetLastError() == hipSuccess ? BRI_OK : BRI_EHIP;
     };
@@ -972,7 +1016,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
     auto fold_switch = [&](int first) -> int {
         hipLaunchKernelGGL((ms_fold_kernel<double2, float2>), ugrid, dim3(256), 0, strm, s.st, s.ws, n, s.ncol,
                            (const double2 *)s.R, (const double2 *)s.p, (const double2 *)s.P0, (float2 *)s.P0_lo,
-                           (const double2 *)s.ps, (float2 *)s.ps_lo, (double2 *)s.y, 1, first);
+                           (const double2 *)s.ps, (float2 *)s.ps_lo, (double2 *)s.y, xv, 1, first);
         hipLaunchKernelGGL(ms_window_reset_kernel, dim3(s.ncol), dim3(64), 0, strm, s.ws);
         const size_t cnt = n * s.ncol;
         hipLaunchKernelGGL(narrow_kernel, dim3(4096), dim3(256), 0, strm, cnt, (const double2 *)s.r, (float2 *)s.r_lo);
@@ -1298,6 +1342,7 @@ int ov_solve_shifts(const Geom &g, const void *W64, const void *Wlo, const ov_pa
     const bool mixed = prm->inner != BRI_F64;
     MsSolve m;
     plan_shifts(m, g, prm, ncol, W64, Wlo, true, i0, i1);
+    m.windowed = true;
     Arena ar(work);
     m.carve(ar);
     if (!work) {
