@@ -126,10 +126,11 @@ def test_gradient_workspace_and_invalid_arguments():
     assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(prm), None, None, None, None, None,
                              None, ctypes.byref(nb), None, None) == bri.OK
     # G, the 2n applied shift solutions, [psi | X^dag chi], y, and the two-column multi-shift
-    # (r, p, t: 3 x 2 columns; x: 8 x 2; shifted directions: 7 x 2)
+    # (r, p, t: 3 x 2 columns; x: 8 x 2; shifted directions: 7 x 2; the window's base direction
+    # and 8 stored residuals: 9 x 2)
     vec = 12 * V * 16
-    assert 81 * 9 * V * 16 + vec * (16 + 2 + 1 + 6 + 16 + 14) <= nb.value
-    assert nb.value < 81 * 9 * V * 16 + vec * (16 + 2 + 1 + 6 + 16 + 14) + (1 << 20)
+    assert 81 * 9 * V * 16 + vec * (16 + 2 + 1 + 6 + 16 + 14 + 18) <= nb.value
+    assert nb.value < 81 * 9 * V * 16 + vec * (16 + 2 + 1 + 6 + 16 + 14 + 18) + (1 << 20)
     for bad in (bri._OvParams(8, 1.0, 1e-10, 100, 7, 0), bri._OvParams(0, 1.0, 1e-10, 100, 0, 0),
                 bri._OvParams(8, 2.0, 1e-10, 100, 0, 0), bri._OvParams(8, 1.0, 1e-10, 100, 1, 101)):
         assert lib.ov_apply_grad(ctypes.byref(g), None, None, None, ctypes.byref(bad), None, None, None, None, None,
