@@ -145,24 +145,24 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.rpt = (prec == BRI_F64 || ncol <= 8) ? 2 : 3;
         else
             c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
-        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 16
-        // z-slices.  12 RHS at 32^3x64 measured 37.6 ms (FP64, R = 2) and 18.5 ms (FP32, R = 4 at
-        // three waves per SIMD; 19.1-19.5 ms with R = 3) against 45.2 / 24.9 ms for 16 x 4 tiles
-        // with R = 4 at two waves, and against 47.4 / 19.9 ms for the x-line kernel (its
-        // registers leave one FP64 wave per SIMD); bfloat16 links keep the x-line kernel with
-        // R = 3 (18.7 against 22.8 ms).
+        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 4
+        // z-slices, the column groups of a tile run together (tile_and_group).  12 RHS at 32^3x64
+        // measured 29.2 ms (FP64, R = 2; 30.2 / 31.4 ms in columns of 8 / 16), 17.1 ms (FP32, R = 3;
+        // 17.4 ms with R = 4) and 15.1 ms (bfloat16 links: the x-line kernel, one RHS per thread;
+        // 15.7 ms for the multi-RHS kernel with R = 3).  Before the tiles' column groups ran
+        // together (each group a separate pass over the lattice, re-reading every link) the same
+        // launches took 37.6 / 18.5 / 18.7 ms.
         if (kind == KERN_BRI && ncol >= 3 && xline_fits(g)) {
             c.tile[0] = g.L[0];
             c.tile[1] = 64 / g.L[0];
             c.tile[2] = c.tile[3] = 1;
             c.xcd_remap = 1;
+            c.colz = g.L[2] % 4 == 0 ? 4 : 0;
             if (prec == BRI_F32_BF16W) {
                 c.variant = VAR_XLINE;
-                c.colz = g.L[2] % 4 == 0 ? 4 : 0;
-                c.rpt = 3;
+                c.rpt = 0;
             } else {
-                c.colz = g.L[2] % 16 == 0 ? 16 : (g.L[2] % 8 == 0 ? 8 : 0);
-                c.rpt = prec == BRI_F64 ? 2 : 4;
+                c.rpt = prec == BRI_F64 ? 2 : 3;
             }
         }
     } else {

@@ -46,8 +46,9 @@ struct StencilArgs {
     int colz;     // column traversal depth in z (0 = lexicographic tiles)
     int xcd_remap;
     int ncol;     // columns (right-hand sides); column c lives at offset c * 12 V
-    int nslots;   // partial-sum slots per column the reductions read (V / 64); a kernel with fewer
-                  // blocks zeroes the slots it does not fill
+    int nslots;   // partial-sum slots per column the reductions read (V / 64, one per 64-site tile,
+                  // filled by the tile's block); a kernel with fewer blocks zeroes the slots it does
+                  // not fill
     const void *W;
     const void *in;
     void *out;

@@ -215,6 +215,18 @@ __device__ __forceinline__ int xcd_order(int blk, int nblk, int remap) {
     return (remap && (nblk & 7) == 0) ? (blk & 7) * (nblk >> 3) + (blk >> 3) : blk;
 }
 
+// Tile and column group of this block.  The column groups (one column, or R of them) of a tile are
+// consecutive along x, gridDim.x / ntiles of them (all, unless grid.x would grow too large, the
+// rest follow in blockIdx.y), so that after the XCD ordering the blocks that read the same links
+// run together on one XCD and share those links in its L2 instead of re-reading them from HBM or
+// the Infinity Cache one pass over the lattice later.
+__device__ __forceinline__ void tile_and_group(int ntiles, int remap, int &blk, int &grp) {
+    const int gin = gridDim.x / ntiles;
+    const int lin = xcd_order(blockIdx.x, gridDim.x, remap);
+    blk = lin / gin;
+    grp = blockIdx.y * gin + (lin - blk * gin);
+}
+
 // v += (C(x) psi(x))_comp for the clover term stored after the link slabs: two chirality blocks
 // of 6x6 entries, component index comp = 3*spin + colour, block k holding spins 2k and 2k+1.
 // Applied where a wave finishes its output components, after the slab loop, so the term adds

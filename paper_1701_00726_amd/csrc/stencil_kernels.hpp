@@ -101,13 +101,13 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
     using R = typename LS::R;
     using C = typename Cx<R>::T;
     constexpr int NCOMP = 12 / NSPLIT;
-    const int col = blockIdx.y;
-    if (col_done<MODE>(a, col)) return;  // whole block: this column has converged
+    int blk, col;
+    tile_and_group(a.nslots, a.xcd_remap, blk, col);
+    if (col >= a.ncol || col_done<MODE>(a, col)) return;  // whole block: this column has converged
 
     const unsigned V = (unsigned)a.g.V;
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
     const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
 
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
                 s0 += wsum[w][0];
                 s1 += wsum[w][1];
             }
-            const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+            const size_t pb = (size_t)col * a.nslots + blk;
             a.partial[2 * pb] = s0;
             a.partial[2 * pb + 1] = s1;
         }
@@ -248,13 +248,13 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_xline_kernel(StencilArgs 
     using C = typename Cx<R>::T;
     using S = typename LS::store_t;
     constexpr int NCOMP = 12 / NSPLIT;
-    const int col = blockIdx.y;
-    if (col_done<MODE>(a, col)) return;
+    int blk, col;
+    tile_and_group(a.nslots, a.xcd_remap, blk, col);
+    if (col >= a.ncol || col_done<MODE>(a, col)) return;
 
     const unsigned V = (unsigned)a.g.V;
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
     const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
     const int tx = a.tile[0];  // = L_x
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_xline_kernel(StencilArgs 
                 s0 += wsum[w][0];
                 s1 += wsum[w][1];
             }
-            const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+            const size_t pb = (size_t)col * a.nslots + blk;
             a.partial[2 * pb] = s0;
             a.partial[2 * pb + 1] = s1;
         }
@@ -380,7 +380,9 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_xline_mrhs_kernel(Ste
     const unsigned V = (unsigned)a.g.V;
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int col0 = blockIdx.y * R;
+    int blk, grp;
+    tile_and_group(a.nslots, a.xcd_remap, blk, grp);
+    const int col0 = grp * R;
     bool live[R];
     bool any = false;
 #pragma unroll
@@ -390,7 +392,6 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_xline_mrhs_kernel(Ste
     }
     if (!any) return;
 
-    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
     const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
     const int tx = a.tile[0];  // = L_x
@@ -491,7 +492,7 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_xline_mrhs_kernel(Ste
                     s0 += wsum[w][0];
                     s1 += wsum[w][1];
                 }
-                const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+                const size_t pb = (size_t)col * a.nslots + blk;
                 a.partial[2 * pb] = s0;
                 a.partial[2 * pb + 1] = s1;
             }
@@ -658,7 +659,8 @@ __global__ __launch_bounds__(STREAM_THREADS) void stencil_stream_kernel(StencilA
 
 // waves per SIMD the multi-RHS kernel is compiled for: three for single-precision arithmetic
 // with four right-hand sides per thread (168 VGPRs, a few spilled: 12 RHS at 32^3x64 in 18.5
-// against 20.4 ms at the two waves its 177 VGPRs would allow), else what the registers give
+// against 20.4 ms at the two waves its 177 VGPRs would allow, when each column group was a pass
+// of its own over the lattice), else what the registers give
 template <class LS, int R> constexpr int mrhs_waves() { return sizeof(typename LS::R) == 4 && R == 4 ? 3 : 1; }
 
 template <class LS, int R, bool DAG, int MODE, int KIND>
@@ -671,7 +673,9 @@ void stencil_mrhs_kernel(StencilArgs a) {
     const unsigned V = (unsigned)a.g.V;
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int col0 = blockIdx.y * R;
+    int blk, grp;
+    tile_and_group(a.nslots, a.xcd_remap, blk, grp);
+    const int col0 = grp * R;
     // block-uniform: every wave of the block carries the same R columns
     bool live[R];
     bool any = false;
@@ -682,7 +686,6 @@ void stencil_mrhs_kernel(StencilArgs a) {
     }
     if (!any) return;
 
-    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
     const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
     const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
@@ -774,7 +777,7 @@ void stencil_mrhs_kernel(StencilArgs a) {
                     s0 += wsum[w][0];
                     s1 += wsum[w][1];
                 }
-                const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+                const size_t pb = (size_t)col * a.nslots + blk;
                 a.partial[2 * pb] = s0;
                 a.partial[2 * pb + 1] = s1;
             }
@@ -791,9 +794,19 @@ namespace bri {
 
 // ------------------------------------------------------------------ launch
 
+// Grid of a launch of ngroups column groups (tile_and_group): one block per 64-site tile and group,
+// the groups of a tile consecutive along x, as many as keep grid.x * threads within 32 bits (HIP's
+// limit on a dimension's work-items); further groups continue along y.
+inline dim3 group_grid(const StencilArgs &a, int ngroups, int threads) {
+    const long long ntiles = a.nslots;
+    const long long fit = 0xffffffffLL / (ntiles * threads);
+    const long long gin = fit < 1 ? 1 : (fit < ngroups ? fit : ngroups);
+    return dim3((unsigned)(ntiles * gin), (unsigned)((ngroups + gin - 1) / gin));
+}
+
 template <class LS, int NSPLIT, bool DAG, int KIND>
 inline hipError_t launch_1rhs(const StencilArgs &a, int mode, hipStream_t st) {
-    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)a.ncol), block(64 * NSPLIT);
+    const dim3 grid = group_grid(a, a.ncol, 64 * NSPLIT), block(64 * NSPLIT);
     switch (mode) {
     case EPI_PLAIN: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_PLAIN, KIND>), grid, block, 0, st, a); break;
     case EPI_NORMS: hipLaunchKernelGGL((stencil_kernel<LS, NSPLIT, DAG, EPI_NORMS, KIND>), grid, block, 0, st, a); break;
@@ -809,7 +822,7 @@ inline hipError_t launch_1rhs(const StencilArgs &a, int mode, hipStream_t st) {
 template <class LS, int R, bool DAG, int KIND>
 inline hipError_t launch_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
     const int groups = (a.ncol + R - 1) / R;
-    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(64 * MRHS_SPLIT);
+    const dim3 grid = group_grid(a, groups, 64 * MRHS_SPLIT), block(64 * MRHS_SPLIT);
     switch (mode) {
     case EPI_PLAIN: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_PLAIN, KIND>), grid, block, 0, st, a); break;
     case EPI_NORMS: hipLaunchKernelGGL((stencil_mrhs_kernel<LS, R, DAG, EPI_NORMS, KIND>), grid, block, 0, st, a); break;
@@ -839,7 +852,7 @@ inline hipError_t launch_stream(const StencilArgs &a, int mode, hipStream_t st) 
 
 template <class LS, int NSPLIT, bool DAG>
 inline hipError_t launch_xline(const StencilArgs &a, int mode, hipStream_t st) {
-    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)a.ncol), block(64 * NSPLIT);
+    const dim3 grid = group_grid(a, a.ncol, 64 * NSPLIT), block(64 * NSPLIT);
     switch (mode) {
     case EPI_PLAIN: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
     case EPI_NORMS: hipLaunchKernelGGL((stencil_xline_kernel<LS, NSPLIT, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
@@ -855,7 +868,7 @@ inline hipError_t launch_xline(const StencilArgs &a, int mode, hipStream_t st) {
 template <class LS, int R, bool DAG>
 inline hipError_t launch_xline_mrhs(const StencilArgs &a, int mode, hipStream_t st) {
     const int groups = (a.ncol + R - 1) / R;
-    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(64 * MRHS_SPLIT);
+    const dim3 grid = group_grid(a, groups, 64 * MRHS_SPLIT), block(64 * MRHS_SPLIT);
     switch (mode) {
     case EPI_PLAIN: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
     case EPI_NORMS: hipLaunchKernelGGL((stencil_xline_mrhs_kernel<LS, R, DAG, EPI_NORMS>), grid, block, 0, st, a); break;
@@ -871,7 +884,7 @@ inline hipError_t launch_xline_mrhs(const StencilArgs &a, int mode, hipStream_t 
 template <class LS, int R, bool DAG>
 inline hipError_t launch_mfma(const StencilArgs &a, int mode, hipStream_t st) {
     const int groups = (a.ncol + R - 1) / R;
-    const dim3 grid((unsigned)(a.g.V / 64), (unsigned)groups), block(256);
+    const dim3 grid = group_grid(a, groups, 256), block(256);
     switch (mode) {
     case EPI_PLAIN: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_PLAIN>), grid, block, 0, st, a); break;
     case EPI_NORMS: hipLaunchKernelGGL((stencil_mfma_kernel<LS, R, DAG, EPI_NORMS>), grid, block, 0, st, a); break;

@@ -41,7 +41,9 @@ __global__ __launch_bounds__(256) void stencil_mfma_kernel(StencilArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sub = lane & 3;                 // spin of this lane; colour row of the link it feeds
     const int site_in_tile = 16 * w + (lane >> 2);
-    const int col0 = blockIdx.y * R;
+    int blk, grp;
+    tile_and_group(a.nslots, a.xcd_remap, blk, grp);
+    const int col0 = grp * R;
     bool live[R];
     bool any = false;
 #pragma unroll
@@ -51,7 +53,6 @@ __global__ __launch_bounds__(256) void stencil_mfma_kernel(StencilArgs a) {
     }
     if (!any) return;
 
-    const int blk = xcd_order(blockIdx.x, gridDim.x, a.xcd_remap);
     unsigned om[4], o0[4], op[4];
     const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, site_in_tile, om, o0, op);
     const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void stencil_mfma_kernel(StencilArgs a) {
                     t0 += wsum[q][0];
                     t1 += wsum[q][1];
                 }
-                const size_t pb = (size_t)col * gridDim.x + blockIdx.x;
+                const size_t pb = (size_t)col * a.nslots + blk;
                 a.partial[2 * pb] = t0;
                 a.partial[2 * pb + 1] = t1;
             }

@@ -102,7 +102,9 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
     } else if (ncol < 4) {
         work = {{4, 0}, {4, ncol}};
     } else {
-        work = {{4, 2}, {4, 3}, {4, 4}};
+        // one right-hand side per thread too: the column groups of a tile run together and share
+        // its links in L2 (the bfloat16-link default for batches on whole-line tiles)
+        work = {{4, 0}, {4, 2}, {4, 3}, {4, 4}};
     }
     for (const auto &t : trav)
         for (const auto &w : work)
