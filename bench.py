@@ -412,7 +412,10 @@ VARIANTS_1RHS = (
     ("matrix cores (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 1, 0, 3),
 )
 VARIANTS_12RHS = (
-    ("standard multi-RHS, 4 per thread", (16, 4, 0, 0), 8, 4, 4, 1, 0),
+    ("standard multi-RHS 16x4, 4 per thread", (16, 4, 0, 0), 8, 4, 4, 1, 0),
+    ("standard multi-RHS 32x2, 2 per thread (FP64 default)", (32, 2, 1, 1), 4, 4, 2, 1, 0),
+    ("standard multi-RHS 32x2, 3 per thread (FP32 default)", (32, 2, 1, 1), 4, 4, 3, 1, 0),
+    ("x-line, 1 per thread (bf16-link default)", (32, 2, 1, 1), 4, 4, 0, 1, 2),
     ("x-line multi-RHS, 3 per thread", (32, 2, 1, 1), 4, 4, 3, 1, 2),
     ("matrix cores, 4 per thread (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 4, 0, 3),
 )
