@@ -348,9 +348,10 @@ int ov_solve(const bri_geom *geom, const void *W64, const void *Wlo, const ov_pa
  * Stencil launch configuration and autotuner.  A configuration picks the
  * 64-site tile (tile_x * tile_y * tile_z * tile_t = 64, each dividing its
  * lattice extent; all zero = automatic), the traversal (col_z > 0: tiles of
- * tile_x x tile_y x 1 x 1 walked z-fastest then t inside columns of col_z
- * z-planes, so that stencil neighbours run together on one XCD; col_z = 0:
- * lexicographic tiles), the work split (rpt = 0: one right-hand side per
+ * tile_x x tile_y x 1 x 1 walked inside columns of col_y tile rows along y
+ * (0 = 1; must divide L_y / tile_y) by col_z z-planes by all of t, y fastest,
+ * then z, then t, so that stencil neighbours run together on one XCD; col_z = 0:
+ * lexicographic tiles and col_y 0 or 1), the work split (rpt = 0: one right-hand side per
  * block row with nsplit = 1, 2 or 4 waves sharing the 80 displacements;
  * rpt = 1..4: rpt right-hand sides per thread, four waves sharing the
  * displacements, nsplit ignored) and xcd = 1 to give each XCD a
@@ -375,6 +376,7 @@ typedef struct {
     int rpt;
     int xcd;
     int variant;
+    int col_y;
 } bri_stencil_cfg;
 
 /* bri_stencil_time -- average time of `reps` back-to-back bri_apply launches

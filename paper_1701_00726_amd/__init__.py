@@ -123,6 +123,7 @@ class StencilCfg(ctypes.Structure):
         ("rpt", ctypes.c_int),
         ("xcd", ctypes.c_int),
         ("variant", ctypes.c_int),
+        ("col_y", ctypes.c_int),
     ]
 
     def as_dict(self):

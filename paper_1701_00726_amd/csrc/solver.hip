@@ -1049,7 +1049,7 @@ static int ms_run(MsSolve &s, const void *b, hipStream_t strm, int *hflag, RunSt
         std::vector<uint64_t> k = key0;
         const StencilConfig &cfg = phases[phase].cfg;
         for (uint64_t v : {(uint64_t)phase, (uint64_t)nblock, (uint64_t)cfg.tile[0], (uint64_t)cfg.tile[1],
-                           (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3], (uint64_t)cfg.colz, (uint64_t)cfg.nsplit,
+                           (uint64_t)cfg.tile[2], (uint64_t)cfg.tile[3], (uint64_t)cfg.colz, (uint64_t)cfg.coly, (uint64_t)cfg.nsplit,
                            (uint64_t)cfg.rpt, (uint64_t)cfg.xcd_remap, (uint64_t)cfg.variant, (uint64_t)win_at,
                            (uint64_t)first})
             k.push_back(v);

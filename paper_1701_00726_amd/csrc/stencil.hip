@@ -17,6 +17,7 @@ hipError_t launch_bf16_wil(const StencilArgs &, bool, int, const StencilConfig &
 // then y, z, t.
 static int plan_tile_base(const Geom &g, const StencilConfig &cfg, int tile[4], int nb[4]) {
     if (g.V % 64) return BRI_EINVAL;
+    if (cfg.colz <= 0 && cfg.coly > 1) return BRI_EINVAL;  // y-blocked columns need the column traversal
     if (cfg.variant == VAR_TSTREAM) {
         // t-streaming: an xyz tile of STREAM_THREADS sites and chunks of tile[3] t-slices
         if (cfg.rpt != 0) return BRI_EINVAL;
@@ -42,6 +43,7 @@ static int plan_tile_base(const Geom &g, const StencilConfig &cfg, int tile[4], 
         nb[1] = g.L[1] / ty;
         nb[2] = g.L[2];
         nb[3] = g.L[3];
+        if (cfg.coly < 0 || (cfg.coly > 0 && nb[1] % cfg.coly)) return BRI_EINVAL;
         return BRI_OK;
     }
     if (cfg.tile[0] > 0) {
@@ -89,6 +91,7 @@ int stencil_launch(StencilArgs a, int prec, bool dag, int mode, const StencilCon
     int rc = plan_tile(a.g, cfg, a.tile, a.nb);
     if (rc != BRI_OK) return rc;
     a.colz = cfg.colz;
+    a.coly = cfg.coly > 0 ? cfg.coly : 1;
     a.xcd_remap = cfg.xcd_remap;
     a.nslots = a.g.V / 64;
     if (a.kind != KERN_BRI && a.kind != KERN_WIL) return BRI_EINVAL;
@@ -145,19 +148,21 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.rpt = (prec == BRI_F64 || ncol <= 8) ? 2 : 3;
         else
             c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
-        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 4
-        // z-slices, the column groups of a tile run together (tile_and_group).  12 RHS at 32^3x64
-        // measured 29.2 ms (FP64, R = 2; 30.2 / 31.4 ms in columns of 8 / 16), 17.1 ms (FP32, R = 3;
-        // 17.4 ms with R = 4) and 15.1 ms (bfloat16 links: the x-line kernel, one RHS per thread;
-        // 15.7 ms for the multi-RHS kernel with R = 3).  Before the tiles' column groups ran
-        // together (each group a separate pass over the lattice, re-reading every link) the same
-        // launches took 37.6 / 18.5 / 18.7 ms.
+        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 2
+        // tile rows by 4 z-slices, the column groups of a tile run together (tile_and_group).  12
+        // RHS at 32^3x64 measured 28.8 ms (FP64, R = 2; 29.2 / 30.2 / 31.4 ms in columns of one
+        // row by 4 / 8 / 16 z-slices), 16.4 ms (FP32, R = 3; 17.4 ms with R = 4) and 14.9 ms
+        // (bfloat16 links: the x-line kernel, one RHS per thread; 15.1 ms for the multi-RHS
+        // kernel with R = 3).  Before the tiles' column groups ran together (each group a
+        // separate pass over the lattice, re-reading every link) the same launches took 37.6 /
+        // 18.5 / 18.7 ms.
         if (kind == KERN_BRI && ncol >= 3 && xline_fits(g)) {
             c.tile[0] = g.L[0];
             c.tile[1] = 64 / g.L[0];
             c.tile[2] = c.tile[3] = 1;
             c.xcd_remap = 1;
-            c.colz = g.L[2] % 4 == 0 ? 4 : 0;
+            c.colz = g.L[2] % 4 == 0 ? 4 : (g.L[2] % 2 == 0 ? 2 : 1);
+            c.coly = (g.L[1] / c.tile[1]) % 2 == 0 ? 2 : 1;
             if (prec == BRI_F32_BF16W) {
                 c.variant = VAR_XLINE;
                 c.rpt = 0;
@@ -171,16 +176,21 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
         c.rpt = 0;
         c.nsplit = 4;
         // large lattices whose x-lines fit a wave: the x-line kernel (one spinor load per three
-        // x-displacements).  At 32^3x64 it measured 4.15 / 2.08 / 1.49 ms (FP64 / FP32 /
-        // bfloat16 links) against 5.52 / 3.37 / 2.64 ms for the column traversal above, with
-        // lexicographic whole-line tiles and no XCD remap fastest; at 16^4 the two tie.
+        // x-displacements) on whole-line tiles in XCD-ordered columns of 8 tile rows by 4
+        // z-slices, whose tiles run together with their y, z and t neighbours, where the partner
+        // sites re-read the links.  At 32^3x64 it measured 3.63 / 2.05 / 1.49 ms (FP64 / FP32 /
+        // bfloat16 links) against 4.17 / 2.21 / 1.71 ms for lexicographic tiles (the fastest
+        // traversal without y-blocked columns) and 5.52 / 3.37 / 2.64 ms for the 16 x 4 column
+        // traversal above; at 16^4 the kernels tie.
         if (kind == KERN_BRI && xline_fits(g)) {
             c.variant = VAR_XLINE;
             c.tile[0] = g.L[0];
             c.tile[1] = 64 / g.L[0];
             c.tile[2] = c.tile[3] = 1;
-            c.colz = 0;
-            c.xcd_remap = 0;
+            const int rows = g.L[1] / c.tile[1];
+            c.colz = g.L[2] % 4 == 0 ? 4 : (g.L[2] % 2 == 0 ? 2 : 1);
+            c.coly = rows % 8 == 0 ? 8 : (rows % 4 == 0 ? 4 : (rows % 2 == 0 ? 2 : 1));
+            c.xcd_remap = 1;
         }
     }
     return c;

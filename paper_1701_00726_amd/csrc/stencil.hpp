@@ -44,6 +44,7 @@ struct StencilArgs {
     int tile[4];  // 64-site tile extents (t-streaming: xyz tile of 256 sites and the t-chunk length)
     int nb[4];    // tiles per axis
     int colz;     // column traversal depth in z (0 = lexicographic tiles)
+    int coly;     // column traversal width in tile rows along y (>= 1)
     int xcd_remap;
     int ncol;     // columns (right-hand sides); column c lives at offset c * 12 V
     int nslots;   // partial-sum slots per column the reductions read (V / 64, one per 64-site tile,
@@ -69,6 +70,7 @@ struct StencilArgs {
 struct StencilConfig {
     int tile[4];    // 0 = automatic
     int colz;       // column traversal: z-planes per column (0 = lexicographic tiles)
+    int coly = 0;   // column traversal: tile rows along y per column (0 = 1)
     int nsplit;     // 1-RHS kernel: waves per 64-site tile (1, 2, 4)
     int rpt;        // multi-RHS kernel: right-hand sides per thread (0 = use the 1-RHS kernel)
     int xcd_remap;  // 1 = give each XCD a contiguous range of tiles

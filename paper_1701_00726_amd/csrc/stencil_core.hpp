@@ -168,22 +168,25 @@ __device__ __forceinline__ void transport_reg(C (&chi)[4][3], const C (&w)[3][3]
 // offsets om/o0/op per axis, premultiplied by the axis stride.  Two traversals:
 //   colz == 0: tiles of extents tile[4] in lexicographic order (x fastest);
 //   colz  > 0: tiles of tile[0] x tile[1] x 1 x 1 sites grouped in columns of
-//              colz z-planes and all t; inside a column the tiles run z fastest,
-//              then t, and the columns run x, y, z.  Consecutive tiles (which an
-//              XCD runs together) then hold every stencil neighbour of each other
-//              except across the column walls, so re-read links and spinors stay
-//              in that XCD's L2.
-__device__ __forceinline__ unsigned tile_site(const Geom &g, const int tile[4], const int nb[4], int colz, int blk,
-                                              int lane, unsigned om[4], unsigned o0[4], unsigned op[4]) {
+//              coly tile rows along y, colz z-planes and all t; inside a column
+//              the tiles run y fastest, then z, then t, and the columns run x, y,
+//              z.  A tile's neighbours in y, z and t are then 1, coly and
+//              coly * colz tiles away: tiles an XCD runs together hold most stencil
+//              neighbours of each other, so the second read of a link (by the
+//              partner site) and re-read spinors stay in that XCD's L2.
+__device__ __forceinline__ unsigned tile_site(const Geom &g, const int tile[4], const int nb[4], int colz, int coly,
+                                              int blk, int lane, unsigned om[4], unsigned o0[4], unsigned op[4]) {
     int c[4];
     if (colz > 0) {
-        const int per_col = colz * g.L[3];
+        const int per_col = coly * colz * g.L[3];
         const int col = blk / per_col, rem = blk - col * per_col;
-        const int zt = rem % colz, tt = rem / colz;
+        const int yy = rem % coly, r1 = rem / coly;
+        const int zt = r1 % colz, tt = r1 / colz;
+        const int ncy = nb[1] / coly;
         const int cx = col % nb[0], r2 = col / nb[0];
-        const int cy = r2 % nb[1], cz = r2 / nb[1];
+        const int cy = r2 % ncy, cz = r2 / ncy;
         c[0] = cx * tile[0] + lane % tile[0];
-        c[1] = cy * tile[1] + lane / tile[0];
+        c[1] = (cy * coly + yy) * tile[1] + lane / tile[0];
         c[2] = cz * colz + zt;
         c[3] = tt;
     } else {

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_kernel(StencilArgs a) {
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, a.coly, blk, lane, om, o0, op);
 
     const C *__restrict__ in = (const C *)a.in + (size_t)col * 12 * V;
     const typename LS::store_t *__restrict__ W = (const typename LS::store_t *)a.W;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(64 * NSPLIT) void stencil_xline_kernel(StencilArgs 
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, a.coly, blk, lane, om, o0, op);
     const int tx = a.tile[0];  // = L_x
     const int lx = lane % tx;
     const int lane_m = lane - lx + (lx == 0 ? tx - 1 : lx - 1);  // holds x - 1 (periodic in x)
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(64 * MRHS_SPLIT) void stencil_xline_mrhs_kernel(Ste
     if (!any) return;
 
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, a.coly, blk, lane, om, o0, op);
     const int tx = a.tile[0];  // = L_x
     const int lx = lane % tx;
     const int lane_m = lane - lx + (lx == 0 ? tx - 1 : lx - 1);
@@ -687,7 +687,7 @@ void stencil_mrhs_kernel(StencilArgs a) {
     if (!any) return;
 
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, lane, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, a.coly, blk, lane, om, o0, op);
     const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
     const typename LS::store_t *__restrict__ W = (const typename LS::store_t *)a.W;
 

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void stencil_mfma_kernel(StencilArgs a) {
     if (!any) return;
 
     unsigned om[4], o0[4], op[4];
-    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, blk, site_in_tile, om, o0, op);
+    const unsigned x = tile_site(a.g, a.tile, a.nb, a.colz, a.coly, blk, site_in_tile, om, o0, op);
     const C *__restrict__ in = (const C *)a.in + (size_t)col0 * 12 * V;
     const S *__restrict__ W = (const S *)a.W;
     // chiral-basis signs of this lane's spin

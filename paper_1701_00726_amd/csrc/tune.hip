@@ -41,6 +41,7 @@ static StencilConfig from_public(const bri_stencil_cfg &c) {
     s.rpt = c.rpt;
     s.xcd_remap = c.xcd;
     s.variant = c.variant;
+    s.coly = c.col_y;
     return s;
 }
 
@@ -55,6 +56,7 @@ static bri_stencil_cfg to_public(const StencilConfig &s) {
     c.rpt = s.rpt;
     c.xcd = s.xcd_remap;
     c.variant = s.variant;
+    c.col_y = s.coly;
     return c;
 }
 
@@ -90,12 +92,18 @@ static int time_config(const Geom &g, const void *W, int prec, const void *in, v
 
 static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) {
     std::vector<StencilConfig> out;
-    std::vector<std::array<int, 5>> trav;  // tile x, y, z, t, colz
+    std::vector<std::array<int, 6>> trav;  // tile x, y, z, t, colz, coly
     const int tx_opts[5][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}, {64, 1}};
     for (const auto &t : tx_opts)
         for (int cz : {2, 4, 8, 16})
-            if (g.L[0] % t[0] == 0 && g.L[1] % t[1] == 0 && g.L[2] % cz == 0) trav.push_back({t[0], t[1], 1, 1, cz});
-    trav.push_back({0, 0, 0, 0, 0});  // automatic lexicographic tile
+            if (g.L[0] % t[0] == 0 && g.L[1] % t[1] == 0 && g.L[2] % cz == 0) {
+                trav.push_back({t[0], t[1], 1, 1, cz, 1});
+                // whole-line tiles also in columns several tile rows wide (y fastest inside)
+                for (int cy : {2, 8})
+                    if (t[0] == g.L[0] && cz <= 4 && (g.L[1] / t[1]) % cy == 0)
+                        trav.push_back({t[0], t[1], 1, 1, cz, cy});
+            }
+    trav.push_back({0, 0, 0, 0, 0, 0});  // automatic lexicographic tile
     std::vector<std::pair<int, int>> work;  // (nsplit, rpt)
     if (ncol == 1) {
         work = {{2, 0}, {4, 0}};
@@ -112,6 +120,7 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
                 StencilConfig c;
                 for (int mu = 0; mu < 4; ++mu) c.tile[mu] = t[mu];
                 c.colz = t[4];
+                c.coly = t[5];
                 c.nsplit = w.first;
                 c.rpt = w.second;
                 c.xcd_remap = xcd;
@@ -130,6 +139,7 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
                 StencilConfig c;
                 for (int mu = 0; mu < 4; ++mu) c.tile[mu] = t[mu];
                 c.colz = t[4];
+                c.coly = t[5];
                 c.nsplit = 4;
                 c.rpt = rpt;
                 c.xcd_remap = 1;

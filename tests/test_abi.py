@@ -104,6 +104,24 @@ def test_invalid_stencil_arguments():
     assert lib.bri_round_links(ctypes.byref(g), P(1 << 24), P((1 << 24) - 4096), 2, None) == bri.EINVAL
 
 
+def test_stencil_config_col_y_validated_and_kept():
+    """Host-side validation of the y-blocked column traversal (no launch): col_y must divide the
+    tile rows along y and needs col_z > 0; an accepted configuration reads back unchanged."""
+    L = (16, 16, 8, 8)  # 16 x 4 tiles: four tile rows along y
+    try:
+        good = bri.StencilCfg(16, 4, 1, 1, 2, 4, 0, 1, 2, 4)
+        bri.set_stencil_cfg(L, bri.F64, 1, good)
+        assert bri.get_stencil_cfg(L, bri.F64, 1).as_dict() == good.as_dict()
+        for bad in (bri.StencilCfg(16, 4, 1, 1, 2, 4, 0, 1, 0, 3),   # 3 does not divide 4 rows
+                    bri.StencilCfg(16, 4, 1, 1, 2, 4, 0, 1, 0, 8),   # wider than the lattice
+                    bri.StencilCfg(16, 4, 1, 1, 0, 4, 0, 1, 0, 2),   # lexicographic tiles
+                    bri.StencilCfg(16, 4, 1, 1, 2, 4, 0, 1, 0, -1)):
+            with pytest.raises(bri.BriError):
+                bri.set_stencil_cfg(L, bri.F64, 1, bad)
+    finally:
+        bri.set_stencil_cfg(L, bri.F64, 1, None)
+
+
 def test_gradient_workspace_and_invalid_arguments():
     lib = bri.load()
     L = (8, 8, 8, 8)

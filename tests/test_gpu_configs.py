@@ -19,11 +19,16 @@ L = (16, 8, 8, 6)
 
 
 def _configs(nrhs):
-    trav = [(0, 0, 0, 0, 0), (16, 4, 1, 1, 0), (4, 4, 4, 1, 0)]
-    trav += [(tx, ty, 1, 1, cz) for (tx, ty), cz in itertools.product([(8, 8), (16, 4)], [2, 4, 8])]
+    # (tile x, y, z, t, col_z, col_y); the last two: columns two tile rows wide (y fastest inside)
+    trav = [(0, 0, 0, 0, 0, 0), (16, 4, 1, 1, 0, 0), (4, 4, 4, 1, 0, 0)]
+    trav += [(tx, ty, 1, 1, cz, 0) for (tx, ty), cz in itertools.product([(8, 8), (16, 4)], [2, 4, 8])]
+    trav += [(16, 4, 1, 1, cz, 2) for cz in (2, 8)]
     work = [(2, 0), (4, 0), (1, 0)] if nrhs == 1 else [(4, 0), (4, 1), (4, 2), (4, 3), (4, 4)]
     for t, w, xcd in itertools.product(trav, work, (0, 1)):
-        yield bri.StencilCfg(t[0], t[1], t[2], t[3], t[4], w[0], w[1], xcd)
+        yield bri.StencilCfg(t[0], t[1], t[2], t[3], t[4], w[0], w[1], xcd, 0, t[5])
+    # the x-line kernel (tile_x = L_x) in y-blocked columns, one or several RHS per thread
+    for cz, xcd, rpt in itertools.product((2, 4), (0, 1), (0,) if nrhs == 1 else (0, 2, 3)):
+        yield bri.StencilCfg(16, 4, 1, 1, cz, 4, rpt, xcd, 2, 2)
 
 
 @pytest.fixture(scope="module")
@@ -81,3 +86,8 @@ def test_invalid_config_rejected():
         bri.set_stencil_cfg(L, bri.F64, 1, bri.StencilCfg(5, 4, 1, 1, 0, 4, 0, 1))
     with pytest.raises(bri.BriError):
         bri.set_stencil_cfg(L, bri.F64, 1, bri.StencilCfg(8, 8, 1, 1, 5, 4, 0, 1))
+    # col_y must divide the tile rows along y (2 here) and needs the column traversal
+    with pytest.raises(bri.BriError):
+        bri.set_stencil_cfg(L, bri.F64, 1, bri.StencilCfg(16, 4, 1, 1, 2, 4, 0, 1, 0, 3))
+    with pytest.raises(bri.BriError):
+        bri.set_stencil_cfg(L, bri.F64, 1, bri.StencilCfg(16, 4, 1, 1, 0, 4, 0, 1, 0, 2))
