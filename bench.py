@@ -405,19 +405,21 @@ def cascade_table(dev):
 
 
 # (name, tile, col_z, nsplit, rpt, xcd, variant) of the launches compared by --variants
-VARIANTS_1RHS = (
-    ("standard 16x4 column traversal", (16, 4, 0, 0), 8, 4, 0, 1, 0),
-    ("t-streaming 32x8x1, chunks of 4", (32, 8, 1, 4), 0, 1, 0, 1, 1),
-    ("x-line 32x2", (32, 2, 1, 1), 0, 4, 0, 0, 2),
-    ("matrix cores (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 1, 0, 3),
+VARIANTS_1RHS = (  # name, tile, col_z, nsplit, rpt, xcd, variant, col_y
+    ("standard 16x4 column traversal", (16, 4, 0, 0), 8, 4, 0, 1, 0, 0),
+    ("t-streaming 32x8x1, chunks of 4", (32, 8, 1, 4), 0, 1, 0, 1, 1, 0),
+    ("x-line 32x2, lexicographic", (32, 2, 1, 1), 0, 4, 0, 0, 2, 0),
+    ("x-line 32x2, columns of 8 rows x 4 z (default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 8),
+    ("matrix cores (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 1, 0, 3, 0),
 )
 VARIANTS_12RHS = (
-    ("standard multi-RHS 16x4, 4 per thread", (16, 4, 0, 0), 8, 4, 4, 1, 0),
-    ("standard multi-RHS 32x2, 2 per thread (FP64 default)", (32, 2, 1, 1), 4, 4, 2, 1, 0),
-    ("standard multi-RHS 32x2, 3 per thread (FP32 default)", (32, 2, 1, 1), 4, 4, 3, 1, 0),
-    ("x-line, 1 per thread (bf16-link default)", (32, 2, 1, 1), 4, 4, 0, 1, 2),
-    ("x-line multi-RHS, 3 per thread", (32, 2, 1, 1), 4, 4, 3, 1, 2),
-    ("matrix cores, 4 per thread (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 4, 0, 3),
+    ("standard multi-RHS 16x4, 4 per thread", (16, 4, 0, 0), 8, 4, 4, 1, 0, 0),
+    ("standard multi-RHS 32x2, 2 per thread (FP64 default)", (32, 2, 1, 1), 4, 4, 2, 1, 0, 2),
+    ("standard multi-RHS 32x2, 3 per thread (FP32 default)", (32, 2, 1, 1), 4, 4, 3, 1, 0, 2),
+    ("x-line, 1 per thread (bf16-link default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 2),
+    ("x-line, 1 per thread, columns of 8 rows", (32, 2, 1, 1), 4, 4, 0, 1, 2, 8),
+    ("x-line multi-RHS, 3 per thread", (32, 2, 1, 1), 4, 4, 3, 1, 2, 2),
+    ("matrix cores, 4 per thread (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 4, 0, 3, 0),
 )
 
 
@@ -435,10 +437,10 @@ def variants(torch, bri, synth, dev):
         for nr, table in ((1, VARIANTS_1RHS), (NSRC, VARIANTS_12RHS)):
             x = torch.randn((nr, 4, 3, V), dtype=bri.spinor_dtype(prec), device=dev)
             ref = None
-            for name, t, cz, ns, rpt, xcd, var in table:
+            for name, t, cz, ns, rpt, xcd, var, cy in table:
                 if var == 3 and prec == bri.F64:
                     continue
-                cfg = bri.StencilCfg(t[0], t[1], t[2], t[3], cz, ns, rpt, xcd, var)
+                cfg = bri.StencilCfg(t[0], t[1], t[2], t[3], cz, ns, rpt, xcd, var, cy)
                 us = bri.stencil_time(L, W, prec, x, cfg=cfg, reps=10 if nr == 1 else 3)
                 bri.set_stencil_cfg(L, prec, nr, cfg)
                 y = bri.apply(L, W, prec, -RHO, x)

@@ -148,13 +148,14 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.rpt = (prec == BRI_F64 || ncol <= 8) ? 2 : 3;
         else
             c.rpt = (ncol % 4 == 0 || ncol % 3 != 0) ? 4 : 3;
-        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 2
-        // tile rows by 4 z-slices, the column groups of a tile run together (tile_and_group).  12
-        // RHS at 32^3x64 measured 28.8 ms (FP64, R = 2; 29.2 / 30.2 / 31.4 ms in columns of one
-        // row by 4 / 8 / 16 z-slices), 16.4 ms (FP32, R = 3; 17.4 ms with R = 4) and 14.9 ms
-        // (bfloat16 links: the x-line kernel, one RHS per thread; 15.1 ms for the multi-RHS
-        // kernel with R = 3).  Before the tiles' column groups ran together (each group a
-        // separate pass over the lattice, re-reading every link) the same launches took 37.6 /
+        // large lattices whose x-lines fit a wave: whole-line tiles (Lx x 64/Lx) in columns of 4
+        // z-slices (FP64: one tile row wide; FP32 and bfloat16 links: two), the column groups of
+        // a tile run together (tile_and_group).  12 RHS at 32^3x64 measured 28.8-29.2 ms (FP64, R
+        // = 2; 30.2 / 31.4 ms in columns of 8 / 16 z-slices; two rows wide the same time with 8%
+        // more bytes fetched), 16.4 ms (FP32, R = 3; 16.8 ms one row wide, 17.4 ms with R = 4) and
+        // 14.9 ms (bfloat16 links: the x-line kernel, one RHS per thread; 15.1 ms for the
+        // multi-RHS kernel with R = 3).  Before the tiles' column groups ran together (each group
+        // a separate pass over the lattice, re-reading every link) the same launches took 37.6 /
         // 18.5 / 18.7 ms.
         if (kind == KERN_BRI && ncol >= 3 && xline_fits(g)) {
             c.tile[0] = g.L[0];
@@ -162,7 +163,7 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.tile[2] = c.tile[3] = 1;
             c.xcd_remap = 1;
             c.colz = g.L[2] % 4 == 0 ? 4 : (g.L[2] % 2 == 0 ? 2 : 1);
-            c.coly = (g.L[1] / c.tile[1]) % 2 == 0 ? 2 : 1;
+            c.coly = prec != BRI_F64 && (g.L[1] / c.tile[1]) % 2 == 0 ? 2 : 1;
             if (prec == BRI_F32_BF16W) {
                 c.variant = VAR_XLINE;
                 c.rpt = 0;
@@ -176,12 +177,12 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
         c.rpt = 0;
         c.nsplit = 4;
         // large lattices whose x-lines fit a wave: the x-line kernel (one spinor load per three
-        // x-displacements) on whole-line tiles in XCD-ordered columns of 8 tile rows by 4
-        // z-slices, whose tiles run together with their y, z and t neighbours, where the partner
-        // sites re-read the links.  At 32^3x64 it measured 3.63 / 2.05 / 1.49 ms (FP64 / FP32 /
-        // bfloat16 links) against 4.17 / 2.21 / 1.71 ms for lexicographic tiles (the fastest
-        // traversal without y-blocked columns) and 5.52 / 3.37 / 2.64 ms for the 16 x 4 column
-        // traversal above; at 16^4 the kernels tie.
+        // x-displacements) on whole-line tiles in XCD-ordered columns of 4 z-slices and 8 (FP64)
+        // or 16 tile rows, whose tiles run together with their y, z and t neighbours, where the
+        // partner sites re-read the links.  At 32^3x64 it measured 3.59-3.63 / 2.00 / 1.47 ms
+        // (FP64 / FP32 / bfloat16 links) against 4.17 / 2.21 / 1.71 ms for lexicographic tiles
+        // (the fastest traversal without y-blocked columns) and 5.52 / 3.37 / 2.64 ms for the 16 x
+        // 4 column traversal above; at 16^4 the kernels tie.
         if (kind == KERN_BRI && xline_fits(g)) {
             c.variant = VAR_XLINE;
             c.tile[0] = g.L[0];
@@ -189,7 +190,13 @@ StencilConfig default_config(const Geom &g, int prec, int ncol, int kind) {
             c.tile[2] = c.tile[3] = 1;
             const int rows = g.L[1] / c.tile[1];
             c.colz = g.L[2] % 4 == 0 ? 4 : (g.L[2] % 2 == 0 ? 2 : 1);
-            c.coly = rows % 8 == 0 ? 8 : (rows % 4 == 0 ? 4 : (rows % 2 == 0 ? 2 : 1));
+            const int widest = prec == BRI_F64 ? 8 : 16;
+            c.coly = 1;
+            for (int cy = widest; cy > 1; cy /= 2)
+                if (rows % cy == 0) {
+                    c.coly = cy;
+                    break;
+                }
             c.xcd_remap = 1;
         }
     }
