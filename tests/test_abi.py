@@ -122,6 +122,27 @@ def test_stencil_config_col_y_validated_and_kept():
         bri.set_stencil_cfg(L, bri.F64, 1, None)
 
 
+@pytest.mark.parametrize("L", [(32, 32, 32, 64), (16, 16, 16, 16), (24, 24, 24, 48), (64, 8, 16, 16),
+                               (16, 32, 8, 32), (8, 8, 8, 8)])
+def test_default_configs_are_valid(L):
+    """Host-side: the default launch configuration of every precision and batch size is one the
+    validation accepts (tile, column width and depth dividing the lattice) and reads back unchanged
+    when installed."""
+    for prec in (bri.F64, bri.F32, bri.F32_BF16W):
+        for nrhs in (1, 2, 3, 12):
+            d = bri.get_stencil_cfg(L, prec, nrhs)
+            try:
+                bri.set_stencil_cfg(L, prec, nrhs, d)
+                assert bri.get_stencil_cfg(L, prec, nrhs).as_dict() == d.as_dict()
+            finally:
+                bri.set_stencil_cfg(L, prec, nrhs, None)
+    if L == (32, 32, 32, 64):  # whole-line tiles in y-blocked columns on the benchmark lattice
+        d1 = bri.get_stencil_cfg(L, bri.F64, 1)
+        assert (d1.tile_x, d1.tile_y, d1.col_z, d1.col_y, d1.variant) == (32, 2, 4, 8, 2)
+        assert bri.get_stencil_cfg(L, bri.F32, 1).col_y == 16
+        assert bri.get_stencil_cfg(L, bri.F32, 12).col_y == 2
+
+
 def test_gradient_workspace_and_invalid_arguments():
     lib = bri.load()
     L = (8, 8, 8, 8)
