@@ -409,16 +409,17 @@ VARIANTS_1RHS = (  # name, tile, col_z, nsplit, rpt, xcd, variant, col_y
     ("standard 16x4 column traversal", (16, 4, 0, 0), 8, 4, 0, 1, 0, 0),
     ("t-streaming 32x8x1, chunks of 4", (32, 8, 1, 4), 0, 1, 0, 1, 1, 0),
     ("x-line 32x2, lexicographic", (32, 2, 1, 1), 0, 4, 0, 0, 2, 0),
-    ("x-line 32x2, columns of 8 rows x 4 z (default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 8),
+    ("x-line 32x2, columns 8 rows x 4 z (FP64 default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 8),
+    ("x-line 32x2, columns 16 rows x 4 z (FP32 default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 16),
     ("matrix cores (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 1, 0, 3, 0),
 )
 VARIANTS_12RHS = (
     ("standard multi-RHS 16x4, 4 per thread", (16, 4, 0, 0), 8, 4, 4, 1, 0, 0),
-    ("standard multi-RHS 32x2, 2 per thread (FP64 default)", (32, 2, 1, 1), 4, 4, 2, 1, 0, 2),
-    ("standard multi-RHS 32x2, 3 per thread (FP32 default)", (32, 2, 1, 1), 4, 4, 3, 1, 0, 2),
-    ("x-line, 1 per thread (bf16-link default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 2),
-    ("x-line, 1 per thread, columns of 8 rows", (32, 2, 1, 1), 4, 4, 0, 1, 2, 8),
-    ("x-line multi-RHS, 3 per thread", (32, 2, 1, 1), 4, 4, 3, 1, 2, 2),
+    ("standard multi-RHS 32x2, 2 per thread, 1 row (FP64 default)", (32, 2, 1, 1), 4, 4, 2, 1, 0, 1),
+    ("standard multi-RHS 32x2, 3 per thread, 2 rows (FP32 default)", (32, 2, 1, 1), 4, 4, 3, 1, 0, 2),
+    ("x-line, 1 per thread, 2 rows (bf16-link default)", (32, 2, 1, 1), 4, 4, 0, 1, 2, 2),
+    ("x-line, 1 per thread, 8 rows", (32, 2, 1, 1), 4, 4, 0, 1, 2, 8),
+    ("x-line multi-RHS, 3 per thread, 2 rows", (32, 2, 1, 1), 4, 4, 3, 1, 2, 2),
     ("matrix cores, 4 per thread (FP32 / bf16 links)", (16, 4, 1, 1), 2, 4, 4, 0, 3, 0),
 )
 
