@@ -31,6 +31,7 @@
 // compile in parallel.
 #pragma once
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "stencil.hpp"
@@ -796,10 +797,16 @@ namespace bri {
 
 // Grid of a launch of ngroups column groups (tile_and_group): one block per 64-site tile and group,
 // the groups of a tile consecutive along x, as many as keep grid.x * threads within 32 bits (HIP's
-// limit on a dimension's work-items); further groups continue along y.
+// limit on a dimension's work-items); further groups continue along y.  BRI_GROUPS_ALONG_X (a
+// positive integer in the environment) lowers that count, so that tests reach the y split with
+// small lattices; it is read at every launch (a captured graph keeps the grid it was captured with).
 inline dim3 group_grid(const StencilArgs &a, int ngroups, int threads) {
     const long long ntiles = a.nslots;
-    const long long fit = 0xffffffffLL / (ntiles * threads);
+    long long fit = 0xffffffffLL / (ntiles * threads);
+    if (const char *cap = std::getenv("BRI_GROUPS_ALONG_X")) {
+        const long long c = std::atoll(cap);
+        if (c > 0 && c < fit) fit = c;
+    }
     const long long gin = fit < 1 ? 1 : (fit < ngroups ? fit : ngroups);
     return dim3((unsigned)(ntiles * gin), (unsigned)((ngroups + gin - 1) / gin));
 }
