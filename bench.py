@@ -27,7 +27,8 @@ cpu_baseline the FP64 CPU oracle (every shift solved on its own) on the host: it
              iterations the oracle itself needed on this workload (stored with its outputs).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
-       python bench.py --stencil-only [--stencil-rhs 12]   (copy calibration + stencil launches, for counters)
+       python bench.py --stencil-only [--stencil-rhs 12] [--stencil-cols 2,4]
+                                                            (copy calibration + stencil launches, for counters)
        python bench.py --survey                             (tuned stencil and overlap timings, 3 lattices)
 """
 
@@ -247,6 +248,10 @@ def parse():
     ap.add_argument("--stencil-only", action="store_true", help="copy calibration + stencil launches only")
     ap.add_argument("--stencil-rhs", type=int, default=1,
                     help="with --stencil-only: also launch the multi-RHS kernel on this many RHS (FP64 and FP32)")
+    ap.add_argument("--stencil-cols", type=str, default="",
+                    help="with --stencil-only: also launch the FP64 1-RHS default kernel and traversal over each of "
+                         "these numbers of columns (comma-separated), the columns of a tile back to back, to split "
+                         "the 1-RHS traffic into its link and spinor parts")
     ap.add_argument("--inner", default="f32", choices=["f32", "bf16w"], help="inner precision of the timed path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     return ap.parse_args()
@@ -628,6 +633,21 @@ def main():
         rec = {"stencil_only": True, "lattice": list(L), "launches": args.stencil_reps, "copy_bytes": 1 << 30,
                "alg_bytes_per_launch": stencil_bytes_per_site(8, 8) * V, "kernel_src_sha": kernel_source_digest(),
                "config": bri.get_stencil_cfg(L, bri.F64, 1).as_dict()}
+        for nc in [int(v) for v in args.stencil_cols.split(",") if v.strip()]:
+            # the 1-RHS launch over nc columns: a tile's columns run in consecutive blocks, so the
+            # columns after the first find the tile's links in L2 and add mostly spinor traffic
+            one = bri.get_stencil_cfg(L, bri.F64, 1)
+            xc = b12[:nc].clone()
+            yc = torch.empty_like(xc)
+            bri.set_stencil_cfg(L, bri.F64, nc, one)
+            try:
+                for _ in range(args.stencil_reps):
+                    bri.apply(L, W, bri.F64, -RHO, xc, out=yc)
+                torch.cuda.synchronize()
+            finally:
+                bri.set_stencil_cfg(L, bri.F64, nc, None)
+            rec[f"cols_{nc}"] = {"launches": args.stencil_reps, "config": one.as_dict()}
+            del xc, yc
         if args.stencil_rhs > 1:
             nr = args.stencil_rhs
             for prec, Wp, name in ((bri.F64, W, "f64"), (bri.F32, bri.build_links(L, U, bri.F32), "f32")):
