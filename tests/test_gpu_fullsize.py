@@ -77,6 +77,42 @@ def test_stencil_sampled_sites(L, eps, seed):
     torch.cuda.empty_cache()
 
 
+def test_batched_defaults_sampled_sites_32_64():
+    """The batch defaults on the benchmark lattice (whole-line tiles in columns of 4 z-slices, the
+    column groups of a tile in consecutive blocks: FP64 R = 2, FP32 R = 3 two rows wide, bfloat16
+    links the x-line kernel one RHS per thread) on 5 columns (ragged groups), every column against
+    the oracle at sampled sites (App. C.1 stencil), D and D^dag."""
+    need_gpu()
+    L = L32
+    seed = synth.LINK_SEED_BASE + 6
+    U, Ud = _links(L, 0.7, seed)
+    rng = np.random.default_rng(seed)
+    nrhs = 5
+    psi = synth.gaussian_source(L, seed + 1, nrhs=nrhs)
+    sites = _sites(L, rng, n_random=8)
+    Uh = U.cpu().numpy()
+    del U
+    m0 = -1.0
+    ref = [oracle.dirac_at(L, Uh, 0, m0, psi[c], sites) for c in range(nrhs)]
+    refd = [oracle.dirac_adj_at(L, Uh, 0, m0, psi[c], sites) for c in range(nrhs)]
+    idx = torch.tensor(sites, device="cuda")
+    for prec, tol in ((bri.F64, 1e-13), (bri.F32, 1e-5), (bri.F32_BF16W, 2e-2)):
+        cfg = bri.get_stencil_cfg(L, prec, nrhs)
+        assert (cfg.tile_x, cfg.col_z) == (32, 4), cfg.as_dict()
+        print(f"[fullsize] batch defaults prec {prec}: {cfg.as_dict()}", flush=True)
+        W = bri.build_links(L, Ud, prec)
+        p = bri.spinor_to_device(psi, prec)
+        out = bri.apply(L, W, prec, m0, p)
+        outd = bri.apply_dag(L, W, prec, m0, p)
+        for c in range(nrhs):
+            got = out[c][:, :, idx].permute(2, 0, 1).cpu().numpy().astype(np.complex128)
+            gotd = outd[c][:, :, idx].permute(2, 0, 1).cpu().numpy().astype(np.complex128)
+            assert np.abs(got - ref[c]).max() <= tol * np.abs(ref[c]).max(), (prec, c)
+            assert np.abs(gotd - refd[c]).max() <= tol * np.abs(refd[c]).max(), (prec, c)
+        del W, p, out, outd
+        torch.cuda.empty_cache()
+
+
 def _identities(op, b, tol):
     s1, st1 = op.sign(b)
     s2, _ = op.sign(s1)
