@@ -98,8 +98,9 @@ static std::vector<StencilConfig> candidates(const Geom &g, int prec, int ncol) 
         for (int cz : {2, 4, 8, 16})
             if (g.L[0] % t[0] == 0 && g.L[1] % t[1] == 0 && g.L[2] % cz == 0) {
                 trav.push_back({t[0], t[1], 1, 1, cz, 1});
-                // whole-line tiles also in columns several tile rows wide (y fastest inside)
-                for (int cy : {2, 8})
+                // whole-line tiles also in columns several tile rows wide (y fastest inside), the
+                // widths of the defaults among them
+                for (int cy : {2, 8, 16})
                     if (t[0] == g.L[0] && cz <= 4 && (g.L[1] / t[1]) % cy == 0)
                         trav.push_back({t[0], t[1], 1, 1, cz, cy});
             }
